@@ -1,0 +1,79 @@
+"""Write oracle reference values for the 20- and 28-qubit workloads.
+
+Calls only the CPU oracle (oracle/) and the seeded input module.  Usage:
+
+    python tests/golden/make_golden.py 20q     # ~1 min on 8 cores
+    python tests/golden/make_golden.py 28q     # hours on 8 cores
+
+Each output JSON holds the recipe, the energy, sampled final-state
+amplitudes, and (20q) the full gradient dE/dtheta and dE/dt.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import qf_inputs as qi  # noqa: E402
+from oracle import ansatz as an, core, hamiltonian as ham  # noqa: E402
+
+
+def sample_indices(n, psi, seed, count=256):
+    rng = np.random.default_rng([seed, 9])
+    rand = rng.integers(0, 1 << n, count)
+    top = np.argsort(-np.abs(psi), kind="stable")[:count]
+    return np.unique(np.concatenate([rand, top]))
+
+
+def system(name):
+    w, h, g = qi.workload(name)
+    n = 2 * w["n_orb"]
+    hx, hz, hc, goff = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
+    if w["ansatz"] == "uccd_top":
+        n_all = len(an.excitations(n, w["n_elec"], singles=False))
+        t_all = qi.amplitudes(n_all, w["seed"], w["t_scale"])
+        excs, ax, az, ac, off, kept = an.build(w["n_orb"], w["n_elec"], "uccd_top", t_all, w["top_k"])
+        t = t_all[kept]
+    else:
+        excs, ax, az, ac, off, kept = an.build(w["n_orb"], w["n_elec"])
+        t = qi.amplitudes(len(excs), w["seed"], w["t_scale"])
+    th = an.angles(ac, off, t)
+    return w, n, an.reference_mask(w["n_elec"]), (hx, hz, hc, goff), (ax, az, ac, off, th, t)
+
+
+def main(name):
+    t0 = time.time()
+    w, n, occ, (hx, hz, hc, goff), (ax, az, ac, off, th, t) = system(name)
+    print(f"{name}: {len(hx)} strings, {len(goff) - 1} groups, K={len(ax)}", flush=True)
+    psi = core.apply_product(core.prepare(n, occ), n, ax, az, th)
+    print(f"forward done {time.time() - t0:.0f}s", flush=True)
+    e_group = core.energy(psi, n, hx, hz, hc, goff)
+    print(f"energy {e_group!r} {time.time() - t0:.0f}s", flush=True)
+    idx = sample_indices(n, psi, w["seed"])
+    out = dict(workload=name, recipe=w, n_qubits=n, occ_mask=occ, n_strings=len(hx),
+               n_groups=len(goff) - 1, K=len(ax), n_par=len(off) - 1,
+               energy=e_group, norm=core.vdot(psi, psi, n).real,
+               sample_index=idx.tolist(), sample_re=psi[idx].real.tolist(),
+               sample_im=psi[idx].imag.tolist(), oracle_threads=core.threads())
+    if name != "28q":
+        lam = core.sigma(psi, n, hx, hz, hc)
+        out["sigma_re"] = lam[idx].real.tolist()
+        out["sigma_im"] = lam[idx].imag.tolist()
+        e_adj, g = core.energy_grad(n, occ, ax, az, th, hx, hz, hc)
+        out["energy_adjoint"] = e_adj
+        out["grad_theta"] = g.tolist()
+        out["grad_t"] = an.grad_t(ac, off, g).tolist()
+        print(f"gradient done {time.time() - t0:.0f}s", flush=True)
+    out["seconds"] = time.time() - t0
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])
