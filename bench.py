@@ -1,0 +1,203 @@
+"""Benchmark: state GB/s of the Pauli-exponential state-vector path on MI355X.
+
+One step = one pass of the hot path on the 28-qubit workload (4 GiB
+complex128 state): prepare the Hartree-Fock determinant, apply the 512
+truncated-UCCD exponentials (4096 Pauli strings, one fused pass per
+excitation), and evaluate <psi|H|psi> over 55371 strings in 10466 flip-mask
+groups (one pass per group).  `value` = algorithmic state bytes of the step
+/ step time, inputs resident in HBM.
+
+Algorithmic bytes (S = 2^n * 16 B): prepare S (write), each fused
+excitation pass 2S (read + write), each flip-mask group S (read).
+
+Extra legs: the 20-qubit energy + adjoint gradient (evals/s), and the CPU
+oracle timed on a bounded sample of the 28-qubit step (rank 0, N = 1).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "state GB/s vs HBM peak; energy+grad evals/s and p99 latency, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def device_system(qf, qi, name):
+    w, h, g = qi.workload(name)
+    n = 2 * w["n_orb"]
+    H, off, _ = qf.build_paulis("hamiltonian", w["n_orb"], w["n_elec"], h, g)
+    if w["ansatz"] == "uccd_top":
+        _, off_all, _ = qf.build_paulis("uccd", w["n_orb"], w["n_elec"])
+        t_all = qi.amplitudes(len(off_all) - 1, w["seed"], w["t_scale"])
+        A, aoff, kept = qf.build_paulis("uccd_top", w["n_orb"], w["n_elec"], t_rank=t_all, top_k=w["top_k"])
+        t = t_all[kept]
+    else:
+        A, aoff, _ = qf.build_paulis("uccsd", w["n_orb"], w["n_elec"])
+        t = qi.amplitudes(len(aoff) - 1, w["seed"], w["t_scale"])
+    th = qf.ansatz_angles(A, aoff, t)
+    return dict(w=w, n=n, occ=(1 << w["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff, theta=th)
+
+
+def n_apply_passes(A):
+    """Fused passes the library executes: runs of equal flip mask (<= 8 strings)."""
+    x = A["x"]
+    passes, run = 0, 0
+    for k in range(len(x)):
+        if k == 0 or x[k] != x[k - 1] or run == 8:
+            passes += 1
+            run = 0
+        run += 1
+    return passes
+
+
+def cpu_baseline(qi, sysd, budget_s=20.0):
+    """Oracle (plain C, OpenMP) on a bounded sample of the 28-qubit step."""
+    from oracle import ansatz as an, core, hamiltonian as ham
+    w, h, g = qi.workload("28q")
+    n = sysd["n"]
+    x, z, c, goff = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
+    n_all = len(an.excitations(n, w["n_elec"], singles=False))
+    t_all = qi.amplitudes(n_all, w["seed"], w["t_scale"])
+    _, ax, az, ac, aoff, kept = an.build(w["n_orb"], w["n_elec"], "uccd_top", t_all, w["top_k"])
+    th = an.angles(ac, aoff, t_all[kept])
+    S = (1 << n) * 16
+    psi = core.prepare(n, sysd["occ"])
+    bytes_done, t_used = 0.0, 0.0
+    # apply the first excitations term by term, then energy groups 1.. (skip
+    # the 407-string diagonal group), until the time budget is spent
+    n_terms = 0
+    t0 = time.perf_counter()
+    for mu in range(4):
+        sl = slice(int(aoff[mu]), int(aoff[mu + 1]))
+        core.apply_product(psi, n, ax[sl], az[sl], th[sl])
+        n_terms += sl.stop - sl.start
+    t_apply = time.perf_counter() - t0
+    bytes_done += n_terms * 2 * S
+    t_used += t_apply
+    n_groups = 0
+    g = 1
+    while t_used < budget_s and g < len(goff) - 1:
+        t0 = time.perf_counter()
+        core.energy(psi, n, x, z, c, goff[g:g + 2])
+        dt = time.perf_counter() - t0
+        t_used += dt
+        bytes_done += S
+        n_groups += 1
+        g += 1
+    return {"value": bytes_done / t_used / 1e9, "unit": "GB/s", "cores": core.threads(), "kind": "oracle",
+            "sample": f"28q: {n_terms} ansatz strings applied one pass each (4 excitations) + "
+                      f"{n_groups} flip-mask groups of the energy (groups 1..{n_groups}), "
+                      f"{t_used:.1f} s on the host; same algorithmic byte count as the GPU step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-20q", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the state-vector path "
+              "runs on a single MI355X here).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2108_04413_amd as qf
+    import qf_inputs as qi
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    log("building 28q tables")
+    s28 = device_system(qf, qi, "28q")
+    n = s28["n"]
+    S = (1 << n) * 16
+    G = len(s28["off"]) - 1
+    passes = n_apply_passes(s28["A"])
+    plan = qf.Plan(n, s28["A"], s28["H"], s28["off"])
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    step_bytes = S + passes * 2 * S + G * S
+    energy_bytes = G * S
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_step, t_energy, t_apply = [], [], []
+    E = None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        qf.prepare_state(psi, n, s28["occ"])
+        plan.apply(psi, s28["theta"])
+        ev[1].record(stream)
+        ev[2].record(stream)
+        E = plan.energy(psi)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        ta = ev[0].elapsed_time(ev[1])
+        te = ev[2].elapsed_time(ev[3])
+        log(f"step {it} ({'warmup' if it < args.warmup else 'timed'}): prep+apply {ta:.1f} ms, "
+            f"energy {te:.1f} ms, E = {E:.12f}")
+        if it >= args.warmup:
+            t_apply.append(ta)
+            t_energy.append(te)
+            t_step.append(ta + te)
+    ms = float(np.mean(t_step))
+    value = step_bytes / (ms * 1e-3) / 1e9
+    e_ms = float(np.mean(t_energy))
+    achieved = energy_bytes / (e_ms * 1e-3) / 1e9
+    del psi
+    torch.cuda.empty_cache()
+
+    extra = {"energy_28q": E, "apply_ms": float(np.mean(t_apply)), "energy_ms": e_ms,
+             "apply_passes": passes, "energy_groups": G,
+             "apply_GBps": (S + passes * 2 * S) / (np.mean(t_apply) * 1e-3) / 1e9}
+
+    if not args.no_20q:
+        log("20q energy + adjoint gradient")
+        s20 = device_system(qf, qi, "20q")
+        p20 = qf.Plan(s20["n"], s20["A"], s20["H"], s20["off"])
+        ws = torch.empty(2 << s20["n"], dtype=torch.complex128, device="cuda")
+        p20.energy_grad(s20["occ"], s20["theta"], ws)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e20, g20 = p20.energy_grad(s20["occ"], s20["theta"], ws)
+        dt = (time.perf_counter() - t0) / reps
+        extra.update({"energy_grad_20q_ms": dt * 1e3, "energy_grad_20q_evals_per_s": 1.0 / dt,
+                      "energy_20q": e20})
+
+    line = {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "28q: 14 orbitals / 14 electrons, seeded random integrals, "
+                                   "UCCD top-512 ansatz (4096 strings), H of 55371 strings / 10466 groups, "
+                                   "complex128 2^28 state; step = prepare + apply + energy",
+                       "n_qubits": n, "state_bytes": S, "step_algorithmic_bytes": step_bytes},
+            "roofline": {"bound": "hbm", "kernel": "k_energy", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": energy_bytes, "launch_ms": e_ms},
+            "extra": extra}
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(qi, s28)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * qforte_mi355x.h - C ABI of the MI355X (gfx950) Pauli-exponential
+ * state-vector library.
+ *
+ * The library implements the state-vector hot path of Stair & Evangelista,
+ * "QForte: an efficient state simulator and quantum algorithms library for
+ * molecular electronic structure": a molecular Hamiltonian and a
+ * disentangled UCC ansatz are mapped to Pauli strings by the Jordan-Wigner
+ * transformation, the ansatz is applied to a 2^n complex128 state as an
+ * ordered product of Pauli-string exponentials, and <psi|H|psi> and its
+ * gradient are evaluated.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Qubit q is bit q of the amplitude index (Sec. 2.1.1, Eq. (3)).  A state
+ *   is 2^n complex128 values, interleaved (re, im), in DEVICE memory owned by
+ *   the caller; the library never frees caller memory.
+ * - A term {x, z, c} denotes c * P(x, z) with
+ *       P(x, z) = i^popcount(x & z) X^x Z^z,
+ *   a Hermitian Pauli string (a qubit in both masks carries Y).  Term arrays
+ *   are HOST memory, read during the call only.
+ * - 1 <= n_qubits <= QF_MAX_QUBITS; every mask must be < 2^n_qubits.
+ * - Calls are ordered on `stream` (a hipStream_t; NULL = the default
+ *   stream).  Calls that return host values synchronize that stream before
+ *   returning.  Calls on distinct states and streams may run concurrently.
+ * - Every call returns a qf_status; on failure qf_last_error() returns a
+ *   message for the calling thread.  No C++ exception crosses this ABI.
+ */
+#ifndef QFORTE_MI355X_H
+#define QFORTE_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QF_MAX_QUBITS 32
+
+typedef struct qf_term {
+    uint64_t x; /* flip mask: qubits carrying X or Y */
+    uint64_t z; /* phase mask: qubits carrying Z or Y */
+    double c;   /* real coefficient */
+} qf_term;
+
+typedef enum qf_status {
+    QF_OK = 0,
+    QF_E_ARG = -1,     /* null pointer, negative count, bad kind */
+    QF_E_RANGE = -2,   /* n_qubits out of range, mask bit >= n_qubits */
+    QF_E_NOMEM = -3,   /* device or host allocation failed */
+    QF_E_HIP = -4,     /* a HIP runtime call failed */
+    QF_E_SIZE = -5,    /* output buffer too small; sizes were written */
+    QF_E_NOTHERM = -6  /* a built operator has a non-real coefficient */
+} qf_status;
+
+typedef enum qf_kind {
+    QF_HAMILTONIAN = 0, /* H of Eq. (1) mapped to Eq. (2), grouped by flip mask */
+    QF_UCCSD = 1,       /* kappa_mu for all S_z-conserving singles + doubles */
+    QF_UCCD = 2,        /* kappa_mu for all S_z-conserving doubles */
+    QF_UCCD_TOP = 3,    /* the top_k doubles by |t_rank|, canonical order */
+    QF_PUCCD = 4        /* paired (seniority-zero) doubles of Sec. 5 */
+} qf_kind;
+
+/*
+ * Build Jordan-Wigner Pauli tables on the host.
+ *
+ * Hamiltonian (kind QF_HAMILTONIAN), Sec. 1 Eqs. (1)-(2):
+ *   H = sum_PQ h_PQ a+_P a_Q + 1/4 sum_PQRS <PQ||RS> a+_P a+_Q a_S a_R + e_core
+ *   over 2*n_orb spin orbitals, spin orbital 2p = alpha and 2p+1 = beta of
+ *   spatial orbital p; h is n_orb x n_orb (row-major, symmetric) and g is
+ *   n_orb^4 (row-major) chemists' integrals g[p,q,r,s] = (pq|rs) with
+ *   <PQ|RS> = (pr|qs) when spins of P,R and of Q,S agree.  JW of Sec. 2.2,
+ *   Eqs. (13)-(14).  Like strings are summed; |Im c| > 1e-12 gives
+ *   QF_E_NOTHERM; |c| <= 1e-12 is dropped.  Output is sorted by (x, z);
+ *   off[] is the CSR of flip-mask groups (off[0] = 0, n_off = groups + 1).
+ *
+ * Ansatz kinds, Sec. 3.1 Eq. (18): for each excitation mu,
+ *   kappa_mu = tau_mu - tau_mu^dagger, tau = a+_a [a+_b] [a_j] a_i,
+ *   i < j occupied, a < b virtual, S_z conserved, reference = the n_elec
+ *   lowest spin orbitals.  Excitations are ordered by the ascending integer
+ *   value of the excited determinant; the output holds, per excitation, the
+ *   strings of JW(kappa_mu) = i sum_k c_k P_k sorted by (x, z), and off[] is
+ *   the excitation CSR.  exp(t kappa_mu) = prod_k exp(-i theta_k P_k) with
+ *   theta_k = -c_k t_mu (see qf_ansatz_angles).
+ *   QF_UCCD_TOP ranks all doubles by |t_rank[m]| (descending, ties to the
+ *   lower canonical index m), keeps top_k and emits them in canonical order;
+ *   t_rank has one value per double in QF_UCCD order.  kept[] (may be NULL)
+ *   receives, per emitted excitation, its index in the unfiltered list.
+ *
+ * Sizes: with out == NULL only *n_out and *n_off are written (QF_OK).  With
+ * cap < *n_out or off_cap < *n_off the sizes are written and QF_E_SIZE is
+ * returned.  h and g may be NULL for ansatz kinds.
+ */
+int qf_build_paulis(int kind, int n_orb, int n_elec, const double *h, const double *g,
+                    double e_core, const double *t_rank, int64_t top_k,
+                    qf_term *out, int64_t cap, int64_t *n_out,
+                    int64_t *off, int64_t off_cap, int64_t *n_off, int64_t *kept);
+
+/*
+ * theta_k = -c_k t_mu for every string k of excitation mu (Sec. 3.1,
+ * Eq. (18) written as a product of exponentials exp(-i theta_k P_k)).
+ * All arrays are host memory; exc_off has n_par + 1 entries.
+ */
+int qf_ansatz_angles(const qf_term *A, const int64_t *exc_off, int64_t n_par,
+                     const double *t, double *theta);
+
+/* dE/dt_mu = -sum_{k in mu} c_k dE/dtheta_k (chain rule of qf_ansatz_angles). */
+int qf_grad_t(const qf_term *A, const int64_t *exc_off, int64_t n_par,
+              const double *dE_dtheta, double *dE_dt);
+
+/*
+ * psi <- |occ_mask>: the reference determinant Phi_0 (Sec. 3.1), one write
+ * pass over the 2^n_qubits device amplitudes.
+ */
+int qf_prepare_state(void *psi, int n_qubits, uint64_t occ_mask, void *stream);
+
+/*
+ * psi <- U psi with U = exp(-i theta_{K-1} P_{K-1}) ... exp(-i theta_0 P_0)
+ * (term 0 acts first; the c field of each term is ignored).  inverse != 0
+ * applies U^dagger instead.  Each exponential is cos(theta) - i sin(theta) P
+ * (Sec. 2.1.4, Eq. (8) with the sign of the worked example, Eqs. (10)-(11)).
+ * Consecutive terms with the same flip mask that commute are applied in one
+ * pass over the state.  theta is host memory (K values).
+ */
+int qf_apply_pauli_exp(void *psi, int n_qubits, const qf_term *terms, const double *theta,
+                       int64_t K, int inverse, void *stream);
+
+/*
+ * *E_out = <psi|H|psi> = sum_l c_l <psi|P_l|psi> (Sec. 3.1, Eq. (17);
+ * Sec. 2.2 exact operator averaging).  H is grouped by flip mask: group g
+ * holds H[group_off[g] .. group_off[g+1]) and every string in it has the
+ * same x.  The reduction order is fixed, so results are reproducible.
+ */
+int qf_energy(const void *psi, int n_qubits, const qf_term *H, const int64_t *group_off,
+              int64_t n_groups, double *E_out, void *stream);
+
+/*
+ * Energy E(theta) = <Phi|U^dagger H U|Phi> (Sec. 3.1, Eq. (16)) with
+ * U from qf_apply_pauli_exp and Phi = |occ_mask>, and its gradient
+ * dE_dtheta[k] = dE/dtheta_k = 2 Im <lambda_k|P_k|phi_k> by one reverse
+ * sweep (phi_k = U_k..U_0 Phi, lambda_k = U_{k+1}^dagger..U_{K-1}^dagger H psi).
+ * workspace: device memory of at least 2 * 2^n_qubits * 16 bytes, owned by
+ * the caller.  E_out and dE_dtheta (K values) are host memory.
+ */
+int qf_energy_grad(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta,
+                   int64_t K, const qf_term *H, const int64_t *group_off, int64_t n_groups,
+                   void *workspace, double *E_out, double *dE_dtheta, void *stream);
+
+/*
+ * Plans: device-resident copies of an ansatz and/or a Hamiltonian for
+ * repeated calls (the one-shot calls above build and free one per call).
+ * A may be NULL with K = 0; H may be NULL with n_groups = 0.  A plan may be
+ * used from one stream at a time.
+ */
+typedef struct qf_plan qf_plan;
+
+int qf_plan_create(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
+                   const int64_t *group_off, int64_t n_groups, qf_plan **out);
+int qf_plan_destroy(qf_plan *plan);
+/* as qf_apply_pauli_exp with the plan's ansatz */
+int qf_plan_apply(qf_plan *plan, void *psi, const double *theta, int inverse, void *stream);
+/* as qf_energy with the plan's Hamiltonian */
+int qf_plan_energy(qf_plan *plan, const void *psi, double *E_out, void *stream);
+/* as qf_energy_grad with the plan's ansatz and Hamiltonian */
+int qf_plan_energy_grad(qf_plan *plan, uint64_t occ_mask, const double *theta, void *workspace,
+                        double *E_out, double *dE_dtheta, void *stream);
+/* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out) */
+int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *qf_last_error(void);
+
+/* Library version string. */
+const char *qf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QFORTE_MI355X_H */

@@ -1,0 +1,137 @@
+"""Python face of the C ABI: the same calls, torch tensors for device memory.
+
+Each function checks the status code of the C call and raises QFError on
+failure.  States are complex128 CUDA(ROCm) tensors of length 2**n_qubits.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import TERM_DTYPE, check, lib, ptr, stream_handle
+
+KINDS = {"hamiltonian": _lib.QF_HAMILTONIAN, "uccsd": _lib.QF_UCCSD, "uccd": _lib.QF_UCCD,
+         "uccd_top": _lib.QF_UCCD_TOP, "puccd": _lib.QF_PUCCD}
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def build_paulis(kind: str, n_orb: int, n_elec: int, h=None, g=None, e_core: float = 0.0,
+                 t_rank=None, top_k: int = 0):
+    """qf_build_paulis: returns (terms[TERM_DTYPE], off[int64], kept[int64] or None)."""
+    k = KINDS[kind]
+    h, g, t_rank = _f64(h), _f64(g), _f64(t_rank)
+    n_out, n_off = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.qf_build_paulis(k, n_orb, n_elec, ptr(h), ptr(g), e_core, ptr(t_rank), int(top_k),
+                              None, 0, ctypes.byref(n_out), None, 0, ctypes.byref(n_off), None),
+          "qf_build_paulis(size)")
+    terms = np.zeros(n_out.value, dtype=TERM_DTYPE)
+    off = np.zeros(n_off.value, dtype=np.int64)
+    kept = np.zeros(max(n_off.value - 1, 0), dtype=np.int64) if k != _lib.QF_HAMILTONIAN else None
+    check(lib.qf_build_paulis(k, n_orb, n_elec, ptr(h), ptr(g), e_core, ptr(t_rank), int(top_k),
+                              ptr(terms), len(terms), ctypes.byref(n_out), ptr(off), len(off),
+                              ctypes.byref(n_off), ptr(kept)), "qf_build_paulis")
+    return terms, off, kept
+
+
+def ansatz_angles(A: np.ndarray, exc_off: np.ndarray, t) -> np.ndarray:
+    t = _f64(t)
+    theta = np.zeros(len(A), dtype=np.float64)
+    exc_off = np.ascontiguousarray(exc_off, dtype=np.int64)
+    check(lib.qf_ansatz_angles(ptr(A), ptr(exc_off), len(exc_off) - 1, ptr(t), ptr(theta)), "qf_ansatz_angles")
+    return theta
+
+
+def grad_t(A: np.ndarray, exc_off: np.ndarray, dtheta) -> np.ndarray:
+    dtheta = _f64(dtheta)
+    exc_off = np.ascontiguousarray(exc_off, dtype=np.int64)
+    out = np.zeros(len(exc_off) - 1, dtype=np.float64)
+    check(lib.qf_grad_t(ptr(A), ptr(exc_off), len(exc_off) - 1, ptr(dtheta), ptr(out)), "qf_grad_t")
+    return out
+
+
+def prepare_state(psi, n_qubits: int, occ_mask: int, stream=None) -> None:
+    check(lib.qf_prepare_state(ptr(psi), n_qubits, occ_mask, stream_handle(stream)), "qf_prepare_state")
+
+
+def apply_pauli_exp(psi, n_qubits: int, terms: np.ndarray, theta, inverse: bool = False, stream=None) -> None:
+    theta = _f64(theta)
+    check(lib.qf_apply_pauli_exp(ptr(psi), n_qubits, ptr(terms), ptr(theta), len(terms), int(inverse),
+                                 stream_handle(stream)), "qf_apply_pauli_exp")
+
+
+def energy(psi, n_qubits: int, H: np.ndarray, group_off: np.ndarray, stream=None) -> float:
+    group_off = np.ascontiguousarray(group_off, dtype=np.int64)
+    e = ctypes.c_double()
+    check(lib.qf_energy(ptr(psi), n_qubits, ptr(H), ptr(group_off), len(group_off) - 1, ctypes.byref(e),
+                        stream_handle(stream)), "qf_energy")
+    return e.value
+
+
+def energy_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarray, group_off: np.ndarray,
+                workspace=None, stream=None):
+    """Returns (E, dE/dtheta).  workspace: complex128 tensor of 2 * 2**n (allocated if None)."""
+    import torch
+    theta = _f64(theta)
+    group_off = np.ascontiguousarray(group_off, dtype=np.int64)
+    if workspace is None:
+        workspace = torch.empty(2 << n_qubits, dtype=torch.complex128, device="cuda")
+    e = ctypes.c_double()
+    g = np.zeros(len(A), dtype=np.float64)
+    check(lib.qf_energy_grad(n_qubits, occ_mask, ptr(A), ptr(theta), len(A), ptr(H), ptr(group_off),
+                             len(group_off) - 1, ptr(workspace), ctypes.byref(e), ptr(g),
+                             stream_handle(stream)), "qf_energy_grad")
+    return e.value, g
+
+
+class Plan:
+    """qf_plan_*: device-resident ansatz and Hamiltonian tables for repeated calls."""
+
+    def __init__(self, n_qubits: int, A: np.ndarray | None = None, H: np.ndarray | None = None,
+                 group_off: np.ndarray | None = None):
+        self.n = n_qubits
+        self.K = 0 if A is None else len(A)
+        self._A = A
+        self._H = H
+        self._goff = None if group_off is None else np.ascontiguousarray(group_off, dtype=np.int64)
+        G = 0 if self._goff is None else len(self._goff) - 1
+        h = ctypes.c_void_p()
+        check(lib.qf_plan_create(n_qubits, ptr(A), self.K, ptr(H), ptr(self._goff), G, ctypes.byref(h)),
+              "qf_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.qf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def apply(self, psi, theta, inverse: bool = False, stream=None) -> None:
+        theta = _f64(theta)
+        check(lib.qf_plan_apply(self._h, ptr(psi), ptr(theta), int(inverse), stream_handle(stream)),
+              "qf_plan_apply")
+
+    def energy(self, psi, stream=None) -> float:
+        e = ctypes.c_double()
+        check(lib.qf_plan_energy(self._h, ptr(psi), ctypes.byref(e), stream_handle(stream)), "qf_plan_energy")
+        return e.value
+
+    def sigma(self, psi, lam, stream=None) -> float:
+        e = ctypes.c_double()
+        check(lib.qf_plan_sigma(self._h, ptr(psi), ptr(lam), ctypes.byref(e), stream_handle(stream)),
+              "qf_plan_sigma")
+        return e.value
+
+    def energy_grad(self, occ_mask: int, theta, workspace, stream=None):
+        theta = _f64(theta)
+        e = ctypes.c_double()
+        g = np.zeros(self.K, dtype=np.float64)
+        check(lib.qf_plan_energy_grad(self._h, occ_mask, ptr(theta), ptr(workspace), ctypes.byref(e), ptr(g),
+                                      stream_handle(stream)), "qf_plan_energy_grad")
+        return e.value, g

@@ -1,0 +1,879 @@
+// Device side of the Pauli-exponential state-vector library (gfx950).
+//
+// State: 2^n complex128 amplitudes (double2), qubit q = bit q of the index.
+// A Pauli string P(x, z) = i^popcount(x&z) X^x Z^z maps |y> to
+// omega(y) |y ^ x>, omega(y) = i^(popcount(x&z) + 2 popcount(y&z)).
+//
+// Kernels (all HBM-bound streaming passes; FP64 throughout):
+//   k_prepare      one write pass: psi = |occ>.
+//   k_run_tables   per fused run, cos/sin of the combined angle for each
+//                  sign pattern (tiny).
+//   k_apply_run    one pass per run of consecutive commuting strings that
+//                  share the flip mask x: every amplitude pair (y, y^x) gets
+//                  one 2x2 rotation (Sec. 2.1.4 exponentials, fused).
+//   k_energy       all flip-mask groups in one launch: per pair,
+//                  2 Re conj(psi[y^x]) D_g(y) psi[y] with D_g(y) = sum of
+//                  c_k omega_k(y) over the group (Sec. 3.1, Eq. (17)).
+//   k_sigma        lambda = H psi by gathering psi[y ^ x_g] for every group,
+//                  fused with E = Re <psi|lambda>.
+//   k_adjoint_run  reverse sweep step for one run: 2 Im <lambda|P_k|phi> for
+//                  each string of the run, then phi, lambda <- U_run^dagger.
+// Reductions are deterministic: per-block partials in a fixed shape, then
+// the last block to finish (ticket counter) sums them in index order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "qf_common.h"
+
+namespace qf {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 4;        // amplitude pairs per thread per step
+constexpr int kMaxRun = 8;       // strings per fused run
+constexpr int kMaxRank = 6;      // rank of a run's sign patterns (table <= 64)
+constexpr int kMaxBlocks = 2048; // cap of grid-stride launches (8 blocks / CU)
+
+struct RunDesc {
+    uint32_t x, z0, hbit, a0;
+    uint32_t b[kMaxRank];
+    int32_t r, k0, m, tab;
+    uint8_t e[kMaxRun];
+    int8_t s[kMaxRun];
+};
+
+struct GroupDesc {
+    uint32_t x, hbit;
+    int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
+};
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)
+{
+    const uint32_t lo = j & ((1u << bit) - 1u);
+    return ((j ^ lo) << 1) | lo;
+}
+
+__device__ __forceinline__ uint32_t par(uint32_t v) { return __popc(v) & 1u; }
+
+// v * i^k
+__device__ __forceinline__ double2 mul_ik(uint32_t k, double2 v)
+{
+    double re = (k & 1u) ? -v.y : v.x;
+    double im = (k & 1u) ? v.x : v.y;
+    if (k & 2u) {
+        re = -re;
+        im = -im;
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double flip(double v, uint32_t p)
+{
+    // multiply by (-1)^p on the sign bit
+    return __hiloint2double(__double2hiint(v) ^ (int)(p << 31), __double2loint(v));
+}
+
+__device__ __forceinline__ uint32_t run_coords(const RunDesc &d, uint32_t y)
+{
+    uint32_t u = 0;
+    for (int q = 0; q < d.r; q++)
+        u |= par(y & d.b[q]) << q;
+    return u;
+}
+
+// Block-wide deterministic sum of M values per thread, then the last block
+// to arrive sums the per-block partials in block order into out[0..M).
+template <int M>
+__device__ void reduce_finish(double (&v)[M], double *partials, unsigned *counter, double *out,
+                              double scale, int nout)
+{
+    __shared__ double lds[kBlock / 64][M];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < M; k++) {
+        double s = v[k];
+        for (int off = 32; off > 0; off >>= 1)
+            s += __shfl_xor(s, off, 64);
+        if (lane == 0)
+            lds[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; w++)
+            s += lds[w][threadIdx.x];
+        __hip_atomic_store(&partials[(size_t)blockIdx.x * M + threadIdx.x], s, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    // fixed-shape tree: thread t sums blocks t, t+256, ... for each k
+    const int nb = gridDim.x;
+    __shared__ double red[kBlock];
+    for (int k = 0; k < M; k++) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock)
+            s += __hip_atomic_load(&partials[(size_t)b * M + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && k < nout)
+            out[k] = scale * red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ kernels
+
+__global__ __launch_bounds__(kBlock) void k_prepare(double2 *__restrict__ psi, uint64_t dim, uint32_t occ)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t y = (uint64_t)blockIdx.x * kBlock + threadIdx.x; y < dim; y += stride)
+        psi[y] = make_double2(y == occ ? 1.0 : 0.0, 0.0);
+}
+
+// One block per run; Theta(u) = sum_k s_k (-1)^popcount(u & e_k) theta_k.
+__global__ __launch_bounds__(64) void k_run_tables(const RunDesc *__restrict__ runs,
+                                                   const double *__restrict__ theta,
+                                                   double2 *__restrict__ tab)
+{
+    const RunDesc d = runs[blockIdx.x];
+    for (int u = threadIdx.x; u < (1 << d.r); u += blockDim.x) {
+        double th = 0.0;
+        for (int k = 0; k < d.m; k++) {
+            const double v = (double)d.s[k] * theta[d.k0 + k];
+            th += (__popc((uint32_t)u & d.e[k]) & 1) ? -v : v;
+        }
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        tab[d.tab + u] = make_double2(cs, sn);
+    }
+}
+
+// psi <- U_run psi (sgn = +1) or U_run^dagger psi (sgn = -1), x != 0.
+__global__ __launch_bounds__(kBlock) void k_apply_run(double2 *__restrict__ psi, uint64_t npairs,
+                                                      RunDesc d, const double2 *__restrict__ tab,
+                                                      double sgn)
+{
+    const uint64_t base = (uint64_t)blockIdx.x * (kBlock * kItems) + threadIdx.x;
+    uint32_t y[kItems];
+    double2 a[kItems], b[kItems];
+    bool ok[kItems];
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        const uint64_t j = base + (uint64_t)i * kBlock;
+        ok[i] = j < npairs;
+        y[i] = insert0((uint32_t)(ok[i] ? j : 0), d.hbit);
+        if (ok[i]) {
+            a[i] = psi[y[i]];
+            b[i] = psi[y[i] ^ d.x];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        if (!ok[i])
+            continue;
+        const uint32_t y1 = y[i], y2 = y1 ^ d.x;
+        const double2 cs = tab[d.tab + run_coords(d, y1)];
+        const double c = cs.x, s = sgn * cs.y;
+        const double2 pb = mul_ik((d.a0 + 2u * par(y2 & d.z0)) & 3u, b[i]);  // (P0 psi)[y1]
+        const double2 pa = mul_ik((d.a0 + 2u * par(y1 & d.z0)) & 3u, a[i]);  // (P0 psi)[y2]
+        // new = c v - i s (p)  ->  (c v.x + s p.y, c v.y - s p.x)
+        psi[y1] = make_double2(c * a[i].x + s * pb.y, c * a[i].y - s * pb.x);
+        psi[y2] = make_double2(c * b[i].x + s * pa.y, c * b[i].y - s * pa.x);
+    }
+}
+
+// Diagonal run (x == 0): psi[y] *= cos(Theta) - i sgn sin(Theta).
+__global__ __launch_bounds__(kBlock) void k_apply_diag(double2 *__restrict__ psi, uint64_t dim, RunDesc d,
+                                                       const double2 *__restrict__ tab, double sgn)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < dim; j += stride) {
+        const uint32_t y = (uint32_t)j;
+        const double2 cs = tab[d.tab + run_coords(d, y)];
+        const double c = cs.x, s = sgn * cs.y;
+        const double2 v = psi[y];
+        psi[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
+    }
+}
+
+// D_g(y_i) = sum_{k in g} c_k omega_k(y_i) for kItems indices at once; every
+// string is loaded once (scalar) and applied to all items.
+__device__ __forceinline__ void group_d(const GroupDesc &g, const uint32_t *__restrict__ zs,
+                                        const double *__restrict__ cs, const uint32_t (&y)[kItems],
+                                        double (&dre)[kItems], double (&dim)[kItems])
+{
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        dre[i] = 0.0;
+        dim[i] = 0.0;
+    }
+#pragma unroll 2
+    for (int k = g.k0; k < g.kre; k++) {
+        const uint32_t z = zs[k];
+        const double c = cs[k];
+#pragma unroll
+        for (int i = 0; i < kItems; i++)
+            dre[i] += flip(c, par(y[i] & z));
+    }
+    for (int k = g.kre; k < g.k1; k++) {
+        const uint32_t z = zs[k];
+        const double c = cs[k];
+#pragma unroll
+        for (int i = 0; i < kItems; i++)
+            dim[i] += flip(c, par(y[i] & z));
+    }
+}
+
+// E = sum_g sum_pairs 2 Re conj(psi[y^x]) D_g(y) psi[y]  (x != 0)
+//   + sum_y |psi[y]|^2 D_0(y)                            (x == 0)
+__global__ __launch_bounds__(kBlock) void k_energy(const double2 *__restrict__ psi, int n,
+                                                   const GroupDesc *__restrict__ groups, int G,
+                                                   const uint32_t *__restrict__ zs,
+                                                   const double *__restrict__ cs, double *partials,
+                                                   unsigned *counter, double *result)
+{
+    double acc = 0.0;
+    for (int gi = 0; gi < G; gi++) {
+        const GroupDesc g = groups[gi];
+        const uint64_t npairs = g.x ? (1ull << (n - 1)) : (1ull << n);
+        const uint64_t per = (uint64_t)kBlock * kItems;
+        const uint64_t chunk = ((npairs + (uint64_t)gridDim.x * per - 1) / ((uint64_t)gridDim.x * per)) * per;
+        const uint64_t start = (uint64_t)blockIdx.x * chunk;
+        const uint64_t end = start + chunk < npairs ? start + chunk : npairs;
+        const double w = g.x ? 2.0 : 1.0;
+        for (uint64_t j0 = start + threadIdx.x; j0 < end; j0 += per) {
+            uint32_t y[kItems];
+            double2 a[kItems], b[kItems];
+            bool ok[kItems];
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                const uint64_t j = j0 + (uint64_t)i * kBlock;
+                ok[i] = j < end;
+                const uint32_t jj = (uint32_t)(ok[i] ? j : start);
+                y[i] = g.x ? insert0(jj, g.hbit) : jj;
+                a[i] = psi[y[i]];
+                b[i] = psi[y[i] ^ g.x];
+            }
+            double dre[kItems], dim[kItems];
+            group_d(g, zs, cs, y, dre, dim);
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
+                const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
+                const double v = b[i].x * tr + b[i].y * ti;
+                acc += ok[i] ? w * v : 0.0;
+            }
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
+}
+
+// lambda[y] = sum_g D_g(y ^ x_g) psi[y ^ x_g];  E = Re sum_y conj(psi[y]) lambda[y]
+__global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                  int n, const GroupDesc *__restrict__ groups, int G,
+                                                  const uint32_t *__restrict__ zs,
+                                                  const double *__restrict__ cs, double *partials,
+                                                  unsigned *counter, double *result)
+{
+    const uint64_t dim = 1ull << n;
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    double acc = 0.0;
+    for (uint64_t j0 = (uint64_t)blockIdx.x * per; j0 < dim; j0 += (uint64_t)gridDim.x * per) {
+        uint32_t y[kItems];
+        bool ok[kItems];
+        double2 l[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            ok[i] = j < dim;
+            y[i] = (uint32_t)(ok[i] ? j : 0);
+            l[i] = make_double2(0.0, 0.0);
+        }
+        for (int gi = 0; gi < G; gi++) {
+            const GroupDesc g = groups[gi];
+            double2 b[kItems];
+            uint32_t y2[kItems];
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                y2[i] = y[i] ^ g.x;
+                b[i] = psi[y2[i]];
+            }
+            double dre[kItems], dimg[kItems];
+            group_d(g, zs, cs, y2, dre, dimg);
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                l[i].x += dre[i] * b[i].x - dimg[i] * b[i].y;
+                l[i].y += dre[i] * b[i].y + dimg[i] * b[i].x;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            if (!ok[i])
+                continue;
+            lam[y[i]] = l[i];
+            const double2 p = psi[y[i]];
+            acc += p.x * l[i].x + p.y * l[i].y;
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
+}
+
+// One reverse-sweep step over a run: grad[k0+k] = 2 Im <lam|P_k|phi>, then
+// phi, lam <- U_run^dagger (phi, lam).
+__global__ __launch_bounds__(kBlock) void k_adjoint_run(double2 *__restrict__ phi, double2 *__restrict__ lam,
+                                                        uint64_t npairs, RunDesc d,
+                                                        const double2 *__restrict__ tab, double *partials,
+                                                        unsigned *counter, double *grad)
+{
+    double acc[kMaxRun];
+#pragma unroll
+    for (int k = 0; k < kMaxRun; k++)
+        acc[k] = 0.0;
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    const bool diag = d.x == 0;
+    for (uint64_t j0 = (uint64_t)blockIdx.x * per; j0 < npairs; j0 += (uint64_t)gridDim.x * per) {
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            if (j >= npairs)
+                break;
+            const uint32_t y1 = diag ? (uint32_t)j : insert0((uint32_t)j, d.hbit);
+            const uint32_t y2 = y1 ^ d.x;
+            const double2 a = phi[y1], la = lam[y1];
+            const uint32_t u = run_coords(d, y1);
+            const double2 cs = tab[d.tab + u];
+            const double c = cs.x, s = cs.y;
+            double q;
+            if (diag) {
+                // Im conj(la) a
+                q = la.x * a.y - la.y * a.x;
+                // U^dagger: v * (c + i s)
+                phi[y1] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
+                lam[y1] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+            } else {
+                const double2 b = phi[y2], lb = lam[y2];
+                const uint32_t k1 = (d.a0 + 2u * par(y1 & d.z0)) & 3u;
+                const uint32_t k2 = (d.a0 + 2u * par(y2 & d.z0)) & 3u;
+                const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
+                // Q = conj(lb) wa + conj(la) wb ; q = Im Q
+                q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
+                // U^dagger: new = c v + i s p -> (c v.x - s p.y, c v.y + s p.x)
+                phi[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
+                phi[y2] = make_double2(c * b.x - s * wa.y, c * b.y + s * wa.x);
+                const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
+                lam[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
+                lam[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++) {
+                const double v = flip((double)d.s[k] * q, __popc(u & d.e[k]) & 1u);
+                acc[k] += k < d.m ? v : 0.0;
+            }
+        }
+    }
+    reduce_finish<kMaxRun>(acc, partials, counter, grad + d.k0, 2.0, d.m);
+}
+
+} // namespace qf
+
+// ===================================================================== host
+
+#define QF_HIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            qf::raise(QF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+namespace qf {
+
+template <class T> T *dev_alloc(size_t count)
+{
+    void *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        raise(QF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return (T *)p;
+}
+
+void check_terms(const char *who, int n, const qf_term *t, int64_t K)
+{
+    const uint64_t lim = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    for (int64_t k = 0; k < K; k++)
+        if ((t[k].x & ~lim) || (t[k].z & ~lim))
+            raise(QF_E_RANGE, std::string(who) + ": term " + std::to_string(k) + " has a mask bit >= n_qubits");
+}
+
+inline uint32_t hibit(uint32_t x) { return x ? 31u - (uint32_t)__builtin_clz(x) : 0u; }
+
+// Split a term list into fused runs: consecutive strings with the same flip
+// mask whose Y-parity agrees (so they commute), at most kMaxRun strings and
+// a sign-pattern space of rank <= kMaxRank.
+std::vector<RunDesc> make_runs(const qf_term *T, int64_t K, int &tab_entries)
+{
+    std::vector<RunDesc> runs;
+    tab_entries = 0;
+    int64_t k = 0;
+    while (k < K) {
+        RunDesc d;
+        std::memset(&d, 0, sizeof d);
+        const uint32_t x = (uint32_t)T[k].x;
+        const uint32_t zf = (uint32_t)T[k].z;
+        const int afull = popc64(T[k].x & T[k].z);
+        d.x = x;
+        d.z0 = x ? zf : 0u;
+        d.a0 = x ? (uint32_t)(afull & 3) : 0u;
+        d.hbit = hibit(x);
+        d.k0 = (int32_t)k;
+        uint32_t rv[kMaxRank], cm[kMaxRank];
+        int piv[kMaxRank];
+        int r = 0, m = 0;
+        while (k < K && m < kMaxRun && (uint32_t)T[k].x == x) {
+            const int ak = popc64(T[k].x & T[k].z);
+            if (((ak - afull) & 1) != 0)
+                break;  // anticommutes with the run
+            const uint32_t dv = x ? ((uint32_t)T[k].z ^ d.z0) : (uint32_t)T[k].z;
+            uint32_t v = dv, coords = 0;
+            for (int i = 0; i < r; i++)
+                if ((v >> piv[i]) & 1u) {
+                    v ^= rv[i];
+                    coords ^= cm[i];
+                }
+            if (v) {
+                if (r == kMaxRank)
+                    break;
+                d.b[r] = dv;
+                rv[r] = v;
+                cm[r] = coords ^ (1u << r);
+                piv[r] = (int)hibit(v);
+                coords = 1u << r;
+                r++;
+            }
+            d.e[m] = (uint8_t)coords;
+            d.s[m] = x ? ((((ak - afull) & 3) == 0) ? 1 : -1) : 1;
+            m++;
+            k++;
+        }
+        d.r = r;
+        d.m = m;
+        d.tab = tab_entries;
+        tab_entries += 1 << r;
+        runs.push_back(d);
+    }
+    return runs;
+}
+
+} // namespace qf
+
+struct qf_plan {
+    int n = 0;
+    int64_t K = 0;
+    std::vector<qf::RunDesc> runs;
+    int tab_entries = 0;
+    qf::RunDesc *d_runs = nullptr;
+    double *d_theta = nullptr;
+    double *h_theta = nullptr;  // pinned staging for theta uploads
+    hipEvent_t theta_done = nullptr;
+    double2 *d_tab = nullptr;
+    double *d_grad = nullptr;
+    int G = 0;
+    qf::GroupDesc *d_groups = nullptr;
+    uint32_t *d_z = nullptr;
+    double *d_c = nullptr;
+    double *d_partials = nullptr;
+    unsigned *d_counter = nullptr;
+    double *d_result = nullptr;
+
+    ~qf_plan()
+    {
+        if (theta_done)
+            (void)hipEventDestroy(theta_done);
+        if (h_theta)
+            (void)hipHostFree(h_theta);
+        void *bufs[] = {d_runs, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result};
+        for (void *p : bufs)
+            if (p)
+                (void)hipFree(p);
+    }
+};
+
+namespace qf {
+
+void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H, const int64_t *goff,
+               int64_t G)
+{
+    if (n < 1 || n > QF_MAX_QUBITS)
+        raise(QF_E_RANGE, "n_qubits=" + std::to_string(n) + " out of range [1, 32]");
+    if (K < 0 || G < 0)
+        raise(QF_E_ARG, "negative term or group count");
+    if ((K > 0 && !A) || (G > 0 && (!H || !goff)))
+        raise(QF_E_ARG, "null term table");
+    if (K > (int64_t)1 << 30 || G > (int64_t)1 << 30)
+        raise(QF_E_ARG, "term table too large");
+    P.n = n;
+    P.K = K;
+    if (K > 0) {
+        check_terms("ansatz", n, A, K);
+        P.runs = make_runs(A, K, P.tab_entries);
+        P.d_runs = dev_alloc<RunDesc>(P.runs.size());
+        P.d_theta = dev_alloc<double>((size_t)K);
+        P.d_tab = dev_alloc<double2>((size_t)P.tab_entries);
+        P.d_grad = dev_alloc<double>((size_t)K);
+        QF_HIP(hipMemcpy(P.d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice));
+        QF_HIP(hipHostMalloc((void **)&P.h_theta, (size_t)K * sizeof(double), hipHostMallocDefault));
+        QF_HIP(hipEventCreateWithFlags(&P.theta_done, hipEventDisableTiming));
+    }
+    if (G > 0) {
+        if (goff[0] != 0)
+            raise(QF_E_ARG, "group_off[0] must be 0");
+        const int64_t KH = goff[G];
+        check_terms("hamiltonian", n, H, KH);
+        std::vector<GroupDesc> gd((size_t)G);
+        std::vector<uint32_t> zs((size_t)KH);
+        std::vector<double> cs((size_t)KH);
+        for (int64_t g = 0; g < G; g++) {
+            const int64_t a = goff[g], b = goff[g + 1];
+            if (b < a || b > KH)
+                raise(QF_E_ARG, "group_off is not monotone");
+            if (b == a)
+                raise(QF_E_ARG, "empty group " + std::to_string(g));
+            const uint64_t x = H[a].x;
+            int64_t w = a;
+            // real-phase strings (even number of Y) first, then imaginary
+            for (int pass = 0; pass < 2; pass++) {
+                for (int64_t k = a; k < b; k++) {
+                    if (H[k].x != x)
+                        raise(QF_E_ARG, "group " + std::to_string(g) + " mixes flip masks");
+                    const int ph = popc64(H[k].x & H[k].z) & 3;
+                    if ((ph & 1) != pass)
+                        continue;
+                    zs[(size_t)w] = (uint32_t)H[k].z;
+                    cs[(size_t)w] = (ph & 2) ? -H[k].c : H[k].c;
+                    w++;
+                }
+                if (pass == 0)
+                    gd[(size_t)g].kre = (int32_t)w;
+            }
+            gd[(size_t)g].x = (uint32_t)x;
+            gd[(size_t)g].hbit = hibit((uint32_t)x);
+            gd[(size_t)g].k0 = (int32_t)a;
+            gd[(size_t)g].k1 = (int32_t)b;
+            gd[(size_t)g].pad = 0;
+        }
+        P.G = (int)G;
+        P.d_groups = dev_alloc<GroupDesc>((size_t)G);
+        P.d_z = dev_alloc<uint32_t>((size_t)KH);
+        P.d_c = dev_alloc<double>((size_t)KH);
+        QF_HIP(hipMemcpy(P.d_groups, gd.data(), gd.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+        QF_HIP(hipMemcpy(P.d_z, zs.data(), zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        QF_HIP(hipMemcpy(P.d_c, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    P.d_partials = dev_alloc<double>((size_t)kMaxBlocks * kMaxRun);
+    P.d_counter = dev_alloc<unsigned>(1);
+    P.d_result = dev_alloc<double>(4);
+    QF_HIP(hipMemset(P.d_counter, 0, sizeof(unsigned)));
+}
+
+inline unsigned grid_for(uint64_t work, uint64_t per, unsigned cap)
+{
+    uint64_t g = (work + per - 1) / per;
+    if (g < 1)
+        g = 1;
+    if (cap && g > cap)
+        g = cap;
+    return (unsigned)g;
+}
+
+void upload_theta(qf_plan &P, const double *theta, hipStream_t s)
+{
+    if (!theta)
+        raise(QF_E_ARG, "theta is NULL");
+    QF_HIP(hipEventSynchronize(P.theta_done));  // previous upload has left the staging buffer
+    std::memcpy(P.h_theta, theta, (size_t)P.K * sizeof(double));
+    QF_HIP(hipMemcpyAsync(P.d_theta, P.h_theta, (size_t)P.K * sizeof(double), hipMemcpyHostToDevice, s));
+    QF_HIP(hipEventRecord(P.theta_done, s));
+    hipLaunchKernelGGL(k_run_tables, dim3((unsigned)P.runs.size()), dim3(64), 0, s, P.d_runs, P.d_theta,
+                       P.d_tab);
+    QF_HIP(hipGetLastError());
+}
+
+void launch_runs(qf_plan &P, double2 *psi, bool inverse, hipStream_t s)
+{
+    const uint64_t dim = 1ull << P.n;
+    const size_t R = P.runs.size();
+    for (size_t i = 0; i < R; i++) {
+        const RunDesc &d = P.runs[inverse ? R - 1 - i : i];
+        const double sgn = inverse ? -1.0 : 1.0;
+        if (d.x) {
+            const uint64_t np = dim >> 1;
+            hipLaunchKernelGGL(k_apply_run, dim3(grid_for(np, (uint64_t)kBlock * kItems, 0)), dim3(kBlock), 0, s,
+                               psi, np, d, P.d_tab, sgn);
+        } else {
+            hipLaunchKernelGGL(k_apply_diag, dim3(grid_for(dim, kBlock, 8 * kMaxBlocks)), dim3(kBlock), 0, s,
+                               psi, dim, d, P.d_tab, sgn);
+        }
+    }
+    QF_HIP(hipGetLastError());
+}
+
+void launch_prepare(double2 *psi, int n, uint64_t occ, hipStream_t s)
+{
+    const uint64_t dim = 1ull << n;
+    hipLaunchKernelGGL(k_prepare, dim3(grid_for(dim, kBlock, 8 * kMaxBlocks)), dim3(kBlock), 0, s, psi, dim,
+                       (uint32_t)occ);
+    QF_HIP(hipGetLastError());
+}
+
+void launch_energy(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t s)
+{
+    const uint64_t np = 1ull << (P.n - 1 > 0 ? P.n - 1 : 0);
+    const unsigned nb = grid_for(np, (uint64_t)kBlock * kItems, kMaxBlocks);
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kBlock), 0, s, psi, P.n, P.d_groups, P.G, P.d_z, P.d_c,
+                       P.d_partials, P.d_counter, dev_out);
+    QF_HIP(hipGetLastError());
+}
+
+void launch_sigma(qf_plan &P, const double2 *psi, double2 *lam, double *dev_out, hipStream_t s)
+{
+    const uint64_t dim = 1ull << P.n;
+    const unsigned nb = grid_for(dim, (uint64_t)kBlock * kItems, kMaxBlocks);
+    hipLaunchKernelGGL(k_sigma, dim3(nb), dim3(kBlock), 0, s, psi, lam, P.n, P.d_groups, P.G, P.d_z, P.d_c,
+                       P.d_partials, P.d_counter, dev_out);
+    QF_HIP(hipGetLastError());
+}
+
+void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
+{
+    const uint64_t dim = 1ull << P.n;
+    for (size_t i = P.runs.size(); i-- > 0;) {
+        const RunDesc &d = P.runs[i];
+        const uint64_t np = d.x ? dim >> 1 : dim;
+        hipLaunchKernelGGL(k_adjoint_run, dim3(grid_for(np, (uint64_t)kBlock * kItems, kMaxBlocks)), dim3(kBlock),
+                           0, s, phi, lam, np, d, P.d_tab, P.d_partials, P.d_counter, P.d_grad);
+    }
+    QF_HIP(hipGetLastError());
+}
+
+void fetch(double *host, const double *dev, size_t count, hipStream_t s)
+{
+    QF_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipStreamSynchronize(s));
+}
+
+void need_ansatz(const qf_plan *P)
+{
+    if (!P)
+        raise(QF_E_ARG, "plan is NULL");
+}
+
+void energy_grad_impl(qf_plan &P, uint64_t occ, const double *theta, void *workspace, double *E_out,
+                      double *grad, hipStream_t s)
+{
+    if (!workspace || !E_out || (P.K > 0 && !grad))
+        raise(QF_E_ARG, "energy_grad: null workspace or output");
+    if (P.G == 0)
+        raise(QF_E_ARG, "energy_grad: plan has no Hamiltonian");
+    if (occ >> P.n)
+        raise(QF_E_RANGE, "occ_mask has a bit >= n_qubits");
+    double2 *phi = (double2 *)workspace;
+    double2 *lam = phi + (1ull << P.n);
+    launch_prepare(phi, P.n, occ, s);
+    if (P.K > 0) {
+        upload_theta(P, theta, s);
+        launch_runs(P, phi, false, s);
+    }
+    launch_sigma(P, phi, lam, P.d_result, s);
+    if (P.K > 0)
+        launch_adjoint(P, phi, lam, s);
+    QF_HIP(hipMemcpyAsync(E_out, P.d_result, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (P.K > 0)
+        QF_HIP(hipMemcpyAsync(grad, P.d_grad, (size_t)P.K * sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipStreamSynchronize(s));
+}
+
+} // namespace qf
+
+using namespace qf;
+
+extern "C" int qf_plan_create(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
+                              const int64_t *group_off, int64_t n_groups, qf_plan **out)
+{
+    return guarded([&]() -> int {
+        if (!out)
+            return fail(QF_E_ARG, "qf_plan_create: out is NULL");
+        *out = nullptr;
+        qf_plan *P = new qf_plan();
+        try {
+            plan_init(*P, n_qubits, A, K, H, group_off, n_groups);
+        } catch (...) {
+            delete P;
+            throw;
+        }
+        *out = P;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_destroy(qf_plan *plan)
+{
+    delete plan;
+    return QF_OK;
+}
+
+extern "C" int qf_plan_apply(qf_plan *P, void *psi, const double *theta, int inverse, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!P || !psi)
+            return fail(QF_E_ARG, "qf_plan_apply: null plan or state");
+        if (P->K == 0)
+            return QF_OK;
+        hipStream_t s = (hipStream_t)stream;
+        upload_theta(*P, theta, s);
+        launch_runs(*P, (double2 *)psi, inverse != 0, s);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_energy(qf_plan *P, const void *psi, double *E_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!P || !psi || !E_out)
+            return fail(QF_E_ARG, "qf_plan_energy: null argument");
+        if (P->G == 0) {
+            *E_out = 0.0;
+            return QF_OK;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        launch_energy(*P, (const double2 *)psi, P->d_result, s);
+        fetch(E_out, P->d_result, 1, s);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_sigma(qf_plan *P, const void *psi, void *lambda, double *E_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!P || !psi || !lambda || !E_out)
+            return fail(QF_E_ARG, "qf_plan_sigma: null argument");
+        if (P->G == 0)
+            return fail(QF_E_ARG, "qf_plan_sigma: plan has no Hamiltonian");
+        hipStream_t s = (hipStream_t)stream;
+        launch_sigma(*P, (const double2 *)psi, (double2 *)lambda, P->d_result, s);
+        fetch(E_out, P->d_result, 1, s);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_energy_grad(qf_plan *P, uint64_t occ_mask, const double *theta, void *workspace,
+                                   double *E_out, double *dE_dtheta, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!P)
+            return fail(QF_E_ARG, "qf_plan_energy_grad: plan is NULL");
+        energy_grad_impl(*P, occ_mask, theta, workspace, E_out, dE_dtheta, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_prepare_state(void *psi, int n_qubits, uint64_t occ_mask, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!psi)
+            return fail(QF_E_ARG, "qf_prepare_state: psi is NULL");
+        if (n_qubits < 1 || n_qubits > QF_MAX_QUBITS)
+            return fail(QF_E_RANGE, "qf_prepare_state: n_qubits=%d out of range [1, 32]", n_qubits);
+        if (occ_mask >> n_qubits)
+            return fail(QF_E_RANGE, "qf_prepare_state: occ_mask has a bit >= n_qubits");
+        launch_prepare((double2 *)psi, n_qubits, occ_mask, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_apply_pauli_exp(void *psi, int n_qubits, const qf_term *terms, const double *theta,
+                                  int64_t K, int inverse, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!psi)
+            return fail(QF_E_ARG, "qf_apply_pauli_exp: psi is NULL");
+        if (K < 0)
+            return fail(QF_E_ARG, "qf_apply_pauli_exp: K < 0");
+        if (n_qubits < 1 || n_qubits > QF_MAX_QUBITS)
+            return fail(QF_E_RANGE, "qf_apply_pauli_exp: n_qubits=%d out of range", n_qubits);
+        if (K == 0)
+            return QF_OK;
+        if (!terms || !theta)
+            return fail(QF_E_ARG, "qf_apply_pauli_exp: null terms or theta");
+        qf_plan P;
+        plan_init(P, n_qubits, terms, K, nullptr, nullptr, 0);
+        hipStream_t s = (hipStream_t)stream;
+        upload_theta(P, theta, s);
+        launch_runs(P, (double2 *)psi, inverse != 0, s);
+        QF_HIP(hipStreamSynchronize(s));  // the temporary plan's buffers are freed on return
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_energy(const void *psi, int n_qubits, const qf_term *H, const int64_t *group_off,
+                         int64_t n_groups, double *E_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!psi || !E_out)
+            return fail(QF_E_ARG, "qf_energy: null psi or E_out");
+        if (n_groups < 0)
+            return fail(QF_E_ARG, "qf_energy: n_groups < 0");
+        if (n_qubits < 1 || n_qubits > QF_MAX_QUBITS)
+            return fail(QF_E_RANGE, "qf_energy: n_qubits=%d out of range", n_qubits);
+        if (n_groups == 0) {
+            *E_out = 0.0;
+            return QF_OK;
+        }
+        qf_plan P;
+        plan_init(P, n_qubits, nullptr, 0, H, group_off, n_groups);
+        hipStream_t s = (hipStream_t)stream;
+        launch_energy(P, (const double2 *)psi, P.d_result, s);
+        fetch(E_out, P.d_result, 1, s);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_energy_grad(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta,
+                              int64_t K, const qf_term *H, const int64_t *group_off, int64_t n_groups,
+                              void *workspace, double *E_out, double *dE_dtheta, void *stream)
+{
+    return guarded([&]() -> int {
+        if (n_groups < 1)
+            return fail(QF_E_ARG, "qf_energy_grad: needs a Hamiltonian (n_groups >= 1)");
+        qf_plan P;
+        plan_init(P, n_qubits, A, K, H, group_off, n_groups);
+        energy_grad_impl(P, occ_mask, theta, workspace, E_out, dE_dtheta, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
