@@ -32,6 +32,19 @@ METRIC = "state GB/s vs HBM peak; energy+grad evals/s and p99 latency, batched v
 HBM_PEAK_GBS = 8000.0
 
 
+def profiled_traffic(kernel, version):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if that summary was taken on another library version."""
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if line.startswith("traffic_bytes_per_launch "):
+                parts = line.split()
+                if parts[1] == kernel and " ".join(parts[2:-1]) == version:
+                    return float(parts[-1])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -111,6 +124,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-20q", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="run one torch copy of one state (4 GiB) first: a plain copy kernel of known "
+                         "size for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the state-vector path "
@@ -124,6 +140,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calib:
+        src = torch.zeros(1 << 28, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        log("calibration copy of 4 GiB done")
     log("building 28q tables")
     s28 = device_system(qf, qi, "28q")
     n = s28["n"]
@@ -190,7 +214,8 @@ def main():
                                    "complex128 2^28 state; step = prepare + apply + energy",
                        "n_qubits": n, "state_bytes": S, "step_algorithmic_bytes": step_bytes},
             "roofline": {"bound": "hbm", "kernel": "k_energy", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": profiled_traffic("k_energy", qf.__version__),
                          "bytes_per_launch": energy_bytes, "launch_ms": e_ms},
             "extra": extra}
     if not args.no_cpu:
