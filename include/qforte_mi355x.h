@@ -167,6 +167,42 @@ int qf_plan_energy_grad(qf_plan *plan, uint64_t occ_mask, const double *theta, v
 /* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out) */
 int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
 
+/*
+ * Batches: energy and adjoint gradient of many instances (different
+ * molecules, qubit counts or parameter vectors) in ONE persistent kernel
+ * launch, optionally replayed as a HIP graph.  Sec. 3.1, Eqs. (16)-(18)
+ * per instance, as qf_energy_grad.
+ *
+ * qf_batch_create: count instances; instance i has n_qubits[i] (<= 30),
+ *   occ_mask[i], ansatz A[i] (K[i] strings, host), grouped Hamiltonian H[i]
+ *   with group_off[i] (n_groups[i] groups, host).  team (may be NULL) gives
+ *   the number of workgroups that cooperate on instance i (clamped to the
+ *   resident grid and to one 1024-pair tile per workgroup); NULL uses the
+ *   built-in table.  The batch owns all device memory: tables, two states per
+ *   instance, outputs.  Results of an instance depend only on the instance
+ *   and its team size, so they are identical alone and in any batch.
+ * qf_batch_run: theta is host memory, the instances' K[i] angles
+ *   concatenated in instance order; E_out[count] and dE_dtheta (same layout
+ *   as theta, may be NULL) are host memory, valid on return.  use_graph != 0
+ *   captures the launch (theta upload, counter reset, persistent kernel,
+ *   result copies) into a HIP graph on the first call and replays it after.
+ *   A team barrier that waits longer than the spin limit sets an error flag;
+ *   the kernel still exits and the call returns QF_E_HIP.
+ * qf_batch_info: per-instance team sizes (count ints), device state bytes,
+ *   persistent grid size; any output may be NULL.
+ * qf_batch_set_spin_limit: polls before a team barrier gives up (default 2^28).
+ */
+typedef struct qf_batch qf_batch;
+
+int qf_batch_create(int count, const int *n_qubits, const uint64_t *occ_mask, const qf_term *const *A,
+                    const int64_t *K, const qf_term *const *H, const int64_t *const *group_off,
+                    const int64_t *n_groups, const int *team, qf_batch **out);
+int qf_batch_run(qf_batch *batch, const double *theta, double *E_out, double *dE_dtheta, int use_graph,
+                 void *stream);
+int qf_batch_info(const qf_batch *batch, int *team, int64_t *state_bytes, int *grid);
+int qf_batch_set_spin_limit(qf_batch *batch, uint32_t polls);
+int qf_batch_destroy(qf_batch *batch);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char *qf_last_error(void);
 

@@ -28,7 +28,8 @@ QF_HAMILTONIAN, QF_UCCSD, QF_UCCD, QF_UCCD_TOP, QF_PUCCD = 0, 1, 2, 3, 4
 
 EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state", "qf_apply_pauli_exp",
            "qf_energy", "qf_energy_grad", "qf_plan_create", "qf_plan_destroy", "qf_plan_apply",
-           "qf_plan_energy", "qf_plan_energy_grad", "qf_plan_sigma", "qf_last_error", "qf_version")
+           "qf_plan_energy", "qf_plan_energy_grad", "qf_plan_sigma", "qf_last_error", "qf_version",
+           "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy")
 
 
 class QFError(RuntimeError):
@@ -58,6 +59,11 @@ _sig = {
     "qf_plan_energy": [_vp, _vp, _vp, _vp],
     "qf_plan_energy_grad": [_vp, _u64, _vp, _vp, _vp, _vp, _vp],
     "qf_plan_sigma": [_vp, _vp, _vp, _vp, _vp],
+    "qf_batch_create": [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "qf_batch_run": [_vp, _vp, _vp, _vp, _int, _vp],
+    "qf_batch_info": [_vp, _vp, _vp, _vp],
+    "qf_batch_set_spin_limit": [_vp, ctypes.c_uint32],
+    "qf_batch_destroy": [_vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)

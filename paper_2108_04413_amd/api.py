@@ -135,3 +135,61 @@ class Plan:
         check(lib.qf_plan_energy_grad(self._h, occ_mask, ptr(theta), ptr(workspace), ctypes.byref(e), ptr(g),
                                       stream_handle(stream)), "qf_plan_energy_grad")
         return e.value, g
+
+
+class Batch:
+    """qf_batch_*: many instances' energy + adjoint gradient in one persistent launch.
+
+    instances: list of dicts with keys n (qubits), occ (int mask), A (ansatz
+    terms), H (Hamiltonian terms), off (group offsets).  team: optional list
+    of workgroups per instance.
+    """
+
+    def __init__(self, instances, team=None):
+        self.count = len(instances)
+        self._keep = []
+        n = (ctypes.c_int * self.count)(*[int(d["n"]) for d in instances])
+        occ = (ctypes.c_uint64 * self.count)(*[int(d["occ"]) for d in instances])
+        self.K = [0 if d["A"] is None else len(d["A"]) for d in instances]
+        K = (ctypes.c_int64 * self.count)(*self.K)
+        offs = [np.ascontiguousarray(d["off"], dtype=np.int64) for d in instances]
+        self._keep += [d["A"] for d in instances] + [d["H"] for d in instances] + offs
+        A = (ctypes.c_void_p * self.count)(*[ptr(d["A"]) for d in instances])
+        H = (ctypes.c_void_p * self.count)(*[ptr(d["H"]) for d in instances])
+        O = (ctypes.c_void_p * self.count)(*[ptr(o) for o in offs])
+        G = (ctypes.c_int64 * self.count)(*[len(o) - 1 for o in offs])
+        T = None if team is None else (ctypes.c_int * self.count)(*[int(w) for w in team])
+        h = ctypes.c_void_p()
+        check(lib.qf_batch_create(self.count, n, occ, A, K, H, O, G, T, ctypes.byref(h)), "qf_batch_create")
+        self._h = h
+        self.koff = np.concatenate([[0], np.cumsum(self.K)]).astype(np.int64)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.qf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        team = (ctypes.c_int * self.count)()
+        sb = ctypes.c_int64()
+        grid = ctypes.c_int()
+        check(lib.qf_batch_info(self._h, team, ctypes.byref(sb), ctypes.byref(grid)), "qf_batch_info")
+        return {"team": list(team), "state_bytes": sb.value, "grid": grid.value}
+
+    def set_spin_limit(self, polls: int):
+        check(lib.qf_batch_set_spin_limit(self._h, int(polls)), "qf_batch_set_spin_limit")
+
+    def run(self, thetas, use_graph: bool = True, stream=None):
+        """thetas: list of per-instance angle arrays.  Returns (E[count], [grad_i])."""
+        theta = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in thetas])
+                                     if self.count else np.zeros(0), dtype=np.float64)
+        if len(theta) != self.koff[-1]:
+            raise ValueError("theta lengths do not match the batch's ansatz sizes")
+        E = np.zeros(self.count)
+        g = np.zeros(max(len(theta), 1))
+        check(lib.qf_batch_run(self._h, ptr(theta), ptr(E), ptr(g), int(use_graph), stream_handle(stream)),
+              "qf_batch_run")
+        return E, [g[self.koff[i]:self.koff[i + 1]].copy() for i in range(self.count)]

@@ -1,0 +1,678 @@
+// Batched energy + adjoint gradient: many instances (molecules of uneven
+// qubit count, or many parameter vectors) in ONE persistent kernel launch,
+// optionally replayed as a HIP graph.
+//
+// Scheduling.  Instances are sorted by state size, largest first.  Instance
+// e gets a team of W_e workgroups and the ticket range
+// [ticket0_e, ticket0_e + W_e).  Every workgroup of the persistent grid takes
+// tickets from one device counter; ticket t makes it member t - ticket0_e of
+// the team of the instance that owns t.  A team runs the instance's passes
+// (prepare, each fused run forward, sigma = H psi, each run backward) on
+// disjoint slices of the state and meets at a team barrier after every pass:
+// W = 1 teams only need the workgroup barrier, so small states stay in the
+// CU's L2; larger teams use an agent-scope counter barrier with a bounded
+// spin (timeout -> error flag, every wave still exits).  The grid never
+// exceeds the resident capacity and W_e never exceeds the grid, and tickets
+// are taken in order, so every team's members are or will become resident:
+// the schedule cannot deadlock.
+//
+// Reductions: each member sums its slice (wavefront shuffles + LDS), writes
+// one partial per value, and member 0 sums the W partials in member order
+// after the barrier, so an instance's results depend only on (instance, W):
+// they are identical alone and in any batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "qf_common.h"
+#include "qf_host.h"
+#include "qf_kernels.h"
+
+namespace qf {
+
+struct BatchEntry {
+    int32_t n, W, nruns, G;
+    uint32_t occ;
+    int32_t run0;    // first RunDesc of the instance
+    int32_t group0;  // first GroupDesc
+    int32_t term0;   // first Hamiltonian string (GroupDesc ranges are instance-relative)
+    int32_t theta0;  // first ansatz string (RunDesc.k0 is instance-relative)
+    int32_t ticket0; // first ticket of the team
+    int32_t part0;   // partial slots: 2 * W * kMaxRun (adjoint, two buffers) + W (energy)
+    int32_t out;     // caller index of the instance
+    uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
+};
+
+__device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target, unsigned spin_limit,
+                                          unsigned *err)
+{
+    if (W == 1) {  // one workgroup: its waves share the CU's caches
+        __syncthreads();
+        return;
+    }
+    __threadfence();
+    __syncthreads();
+    {
+        if (threadIdx.x == 0) {
+            atomicAdd(ctr, 1u);
+            unsigned spins = 0;
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+                __builtin_amdgcn_s_sleep(4);
+                if (++spins >= spin_limit) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        __threadfence();
+    }
+}
+
+// member's slice [b, e) of `units`, in whole tiles of kBlock * kItems
+__device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
+{
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    const uint64_t tiles = (units + per - 1) / per;
+    const uint64_t tpm = (tiles + (uint64_t)W - 1) / (uint64_t)W;
+    b = (uint64_t)rank * tpm * per;
+    e = b + tpm * per;
+    if (b > units)
+        b = units;
+    if (e > units)
+        e = units;
+}
+
+__device__ void load_table(const RunDesc &d, const double *__restrict__ theta, double2 *tab)
+{
+    for (int u = threadIdx.x; u < (1 << d.r); u += kBlock) {
+        double th = 0.0;
+        for (int k = 0; k < d.m; k++) {
+            const double v = (double)d.s[k] * theta[d.k0 + k];
+            th += (__popc((uint32_t)u & d.e[k]) & 1) ? -v : v;
+        }
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        tab[u] = make_double2(cs, sn);
+    }
+    __syncthreads();
+}
+
+template <int M> __device__ void block_sum(double (&v)[M], double *out)
+{
+    __shared__ double lds[kBlock / 64][kMaxRun];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < M; k++) {
+        double s = v[k];
+        for (int off = 32; off > 0; off >>= 1)
+            s += __shfl_xor(s, off, 64);
+        if (lane == 0)
+            lds[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; w++)
+            s += lds[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+__device__ void pass_prepare(double2 *__restrict__ psi, uint64_t b, uint64_t e, uint32_t occ)
+{
+    for (uint64_t y = b + threadIdx.x; y < e; y += kBlock)
+        psi[y] = make_double2(y == occ ? 1.0 : 0.0, 0.0);
+}
+
+__device__ void pass_apply(double2 *__restrict__ psi, const RunDesc &d, const double2 *tab, uint64_t b,
+                           uint64_t e)
+{
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    const bool diag = d.x == 0;
+    for (uint64_t j0 = b; j0 < e; j0 += per) {
+        uint32_t y[kItems];
+        double2 a[kItems], c2[kItems];
+        bool ok[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            ok[i] = j < e;
+            const uint32_t jj = (uint32_t)(ok[i] ? j : b);
+            y[i] = diag ? jj : insert0(jj, d.hbit);
+            a[i] = psi[y[i]];
+            c2[i] = psi[y[i] ^ d.x];
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            if (!ok[i])
+                continue;
+            const uint32_t y1 = y[i], y2 = y1 ^ d.x;
+            const double2 cs = tab[run_coords(d, y1)];
+            const double c = cs.x, s = cs.y;
+            if (diag) {
+                psi[y1] = make_double2(c * a[i].x + s * a[i].y, c * a[i].y - s * a[i].x);
+            } else {
+                const double2 pb = mul_ik((d.a0 + 2u * par(y2 & d.z0)) & 3u, c2[i]);
+                const double2 pa = mul_ik((d.a0 + 2u * par(y1 & d.z0)) & 3u, a[i]);
+                psi[y1] = make_double2(c * a[i].x + s * pb.y, c * a[i].y - s * pb.x);
+                psi[y2] = make_double2(c * c2[i].x + s * pa.y, c * c2[i].y - s * pa.x);
+            }
+        }
+    }
+}
+
+__device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                             const GroupDesc *__restrict__ groups, int G, const uint32_t *__restrict__ zs,
+                             const double *__restrict__ cs, uint64_t b, uint64_t e)
+{
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    double acc = 0.0;
+    for (uint64_t j0 = b; j0 < e; j0 += per) {
+        uint32_t y[kItems];
+        bool ok[kItems];
+        double2 l[kItems];
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            ok[i] = j < e;
+            y[i] = (uint32_t)(ok[i] ? j : b);
+            l[i] = make_double2(0.0, 0.0);
+        }
+        for (int gi = 0; gi < G; gi++) {
+            const GroupDesc g = groups[gi];
+            uint32_t y2[kItems];
+            double2 bv[kItems];
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                y2[i] = y[i] ^ g.x;
+                bv[i] = psi[y2[i]];
+            }
+            double dre[kItems], dim[kItems];
+            group_d(g, zs, cs, y2, dre, dim);
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                l[i].x += dre[i] * bv[i].x - dim[i] * bv[i].y;
+                l[i].y += dre[i] * bv[i].y + dim[i] * bv[i].x;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            if (!ok[i])
+                continue;
+            lam[y[i]] = l[i];
+            const double2 p = psi[y[i]];
+            acc += p.x * l[i].x + p.y * l[i].y;
+        }
+    }
+    return acc;
+}
+
+__device__ void pass_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, const RunDesc &d,
+                             const double2 *tab, uint64_t b, uint64_t e, double (&acc)[kMaxRun])
+{
+    const uint64_t per = (uint64_t)kBlock * kItems;
+    const bool diag = d.x == 0;
+    for (uint64_t j0 = b; j0 < e; j0 += per) {
+#pragma unroll
+        for (int i = 0; i < kItems; i++) {
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            if (j >= e)
+                break;
+            const uint32_t y1 = diag ? (uint32_t)j : insert0((uint32_t)j, d.hbit);
+            const uint32_t y2 = y1 ^ d.x;
+            const double2 a = phi[y1], la = lam[y1];
+            const uint32_t u = run_coords(d, y1);
+            const double2 cs = tab[u];
+            const double c = cs.x, s = cs.y;
+            double q;
+            if (diag) {
+                q = la.x * a.y - la.y * a.x;
+                phi[y1] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
+                lam[y1] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+            } else {
+                const double2 bb = phi[y2], lb = lam[y2];
+                const uint32_t k1 = (d.a0 + 2u * par(y1 & d.z0)) & 3u;
+                const uint32_t k2 = (d.a0 + 2u * par(y2 & d.z0)) & 3u;
+                const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, bb);
+                q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
+                phi[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
+                phi[y2] = make_double2(c * bb.x - s * wa.y, c * bb.y + s * wa.x);
+                const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
+                lam[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
+                lam[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++) {
+                const double v = flip((double)d.s[k] * q, __popc(u & d.e[k]) & 1u);
+                acc[k] += k < d.m ? v : 0.0;
+            }
+        }
+    }
+}
+
+__global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, unsigned *err)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nentries; i += gridDim.x * blockDim.x)
+        sync[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *ticket = 0u;
+        *err = 0u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
+                                                  unsigned total_tickets, const RunDesc *__restrict__ runs,
+                                                  const GroupDesc *__restrict__ groups,
+                                                  const uint32_t *__restrict__ zs, const double *__restrict__ cs,
+                                                  const double *__restrict__ theta, double2 *states,
+                                                  double *partials, unsigned *sync, unsigned *ticket,
+                                                  unsigned *err, double *E_out, double *grad_out,
+                                                  unsigned spin_limit)
+{
+    __shared__ int s_entry, s_rank;
+    __shared__ double2 s_tab[1 << kMaxRank];
+    __shared__ double s_part[kMaxRun];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned t = atomicAdd(ticket, 1u);
+            int e = -1, rank = 0;
+            if (t < total_tickets) {
+                int lo = 0, hi = nentries - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((unsigned)entries[mid].ticket0 <= t)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                e = lo;
+                rank = (int)(t - (unsigned)entries[lo].ticket0);
+            }
+            s_entry = e;
+            s_rank = rank;
+        }
+        __syncthreads();
+        const int ei = s_entry, rank = s_rank;
+        __syncthreads();
+        if (ei < 0)
+            break;
+        const BatchEntry en = entries[ei];
+        const int W = en.W;
+        const uint64_t dim = 1ull << en.n;
+        double2 *phi = states + en.state0;
+        double2 *lam = phi + dim;
+        const double *th = theta + en.theta0;
+        double *part = partials + en.part0;
+        unsigned *ctr = sync + ei;
+        unsigned epoch = 0;
+        uint64_t b, e;
+
+        member_slice(dim, W, rank, b, e);
+        pass_prepare(phi, b, e, en.occ);
+        team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+
+        for (int r = 0; r < en.nruns; r++) {
+            const RunDesc d = runs[en.run0 + r];
+            load_table(d, th, s_tab);
+            member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
+            pass_apply(phi, d, s_tab, b, e);
+            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+        }
+
+        member_slice(dim, W, rank, b, e);
+        {
+            double v[1] = {pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e)};
+            block_sum<1>(v, s_part);
+            if (threadIdx.x == 0)
+                part[2 * W * kMaxRun + rank] = s_part[0];
+        }
+        team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+
+        for (int r = en.nruns - 1; r >= 0; r--) {
+            const RunDesc d = runs[en.run0 + r];
+            load_table(d, th, s_tab);
+            member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
+            double acc[kMaxRun];
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++)
+                acc[k] = 0.0;
+            pass_adjoint(phi, lam, d, s_tab, b, e, acc);
+            block_sum<kMaxRun>(acc, s_part);
+            double *buf = part + (r & 1) * W * kMaxRun;
+            if (threadIdx.x < kMaxRun)
+                buf[rank * kMaxRun + threadIdx.x] = s_part[threadIdx.x];
+            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+            if (rank == 0 && threadIdx.x < d.m) {
+                double s = 0.0;
+                for (int w = 0; w < W; w++)
+                    s += buf[w * kMaxRun + threadIdx.x];
+                grad_out[en.theta0 + d.k0 + threadIdx.x] = 2.0 * s;
+            }
+        }
+        if (rank == 0 && threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < W; w++)
+                s += part[2 * W * kMaxRun + w];
+            E_out[en.out] = s;
+        }
+        __syncthreads();
+    }
+}
+
+} // namespace qf
+
+struct qf_batch {
+    int count = 0;
+    int nentries = 0;
+    unsigned total_tickets = 0;
+    unsigned grid = 0;
+    unsigned spin_limit = 1u << 28;
+    int64_t K_total = 0;
+    std::vector<int64_t> K;       // per caller instance
+    std::vector<int64_t> koff;    // caller order offsets into theta/grad
+    std::vector<int> W;           // per caller instance
+    std::vector<int> nq;
+    qf::BatchEntry *d_entries = nullptr;
+    qf::RunDesc *d_runs = nullptr;
+    qf::GroupDesc *d_groups = nullptr;
+    uint32_t *d_z = nullptr;
+    double *d_c = nullptr;
+    double *d_theta = nullptr;
+    double2 *d_states = nullptr;
+    double *d_partials = nullptr;
+    unsigned *d_sync = nullptr;
+    unsigned *d_ticket = nullptr;
+    unsigned *d_err = nullptr;
+    double *d_E = nullptr;
+    double *d_grad = nullptr;
+    double *h_theta = nullptr;  // pinned staging
+    double *h_E = nullptr;
+    double *h_grad = nullptr;
+    size_t state_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+
+    ~qf_batch()
+    {
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        void *hp[] = {h_theta, h_E, h_grad};
+        for (void *p : hp)
+            if (p)
+                (void)hipHostFree(p);
+        void *dp[] = {d_entries, d_runs, d_groups, d_z, d_c, d_theta, d_states, d_partials,
+                      d_sync, d_ticket, d_err, d_E, d_grad};
+        for (void *p : dp)
+            if (p)
+                (void)hipFree(p);
+    }
+};
+
+namespace qf {
+
+int default_team(int n)
+{
+    int w = n >= 14 ? 1 << (n - 14) : 1;
+    return std::min(w, 256);
+}
+
+unsigned resident_grid()
+{
+    int dev = 0, cus = 0, per = 0;
+    QF_HIP(hipGetDevice(&dev));
+    QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k_batch), kBlock, 0));
+    if (per < 1)
+        per = 1;
+    return (unsigned)(cus * per);
+}
+
+void batch_enqueue(qf_batch &B, hipStream_t s)
+{
+    QF_HIP(hipMemcpyAsync(B.d_theta, B.h_theta, (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries + 255) / 256))), dim3(256), 0, s,
+                       B.d_sync, B.nentries, B.d_ticket, B.d_err);
+    hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBlock), 0, s, B.d_entries, B.nentries, B.total_tickets,
+                       B.d_runs, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit);
+    QF_HIP(hipGetLastError());
+    QF_HIP(hipMemcpyAsync(B.h_E, B.d_E, (size_t)B.count * sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipMemcpyAsync(B.h_grad, B.d_grad, (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+}
+
+} // namespace qf
+
+using namespace qf;
+
+extern "C" int qf_batch_create(int count, const int *n_qubits, const uint64_t *occ_mask, const qf_term *const *A,
+                               const int64_t *K, const qf_term *const *H, const int64_t *const *group_off,
+                               const int64_t *n_groups, const int *team, qf_batch **out)
+{
+    return guarded([&]() -> int {
+        if (!out)
+            return fail(QF_E_ARG, "qf_batch_create: out is NULL");
+        *out = nullptr;
+        if (count < 1 || !n_qubits || !occ_mask || !K || !A || !H || !group_off || !n_groups)
+            return fail(QF_E_ARG, "qf_batch_create: null array or count < 1");
+        qf_batch *B = new qf_batch();
+        try {
+            B->count = count;
+            std::vector<int> order((size_t)count);
+            std::iota(order.begin(), order.end(), 0);
+            B->K.resize((size_t)count);
+            B->koff.resize((size_t)count + 1);
+            B->W.resize((size_t)count);
+            B->nq.resize((size_t)count);
+            B->koff[0] = 0;
+            for (int i = 0; i < count; i++) {
+                const int n = n_qubits[i];
+                if (n < 1 || n > 30)
+                    raise(QF_E_RANGE, "instance " + std::to_string(i) + ": n_qubits out of range [1, 30]");
+                if (occ_mask[i] >> n)
+                    raise(QF_E_RANGE, "instance " + std::to_string(i) + ": occ_mask has a bit >= n_qubits");
+                if (K[i] < 0 || n_groups[i] < 1 || (K[i] > 0 && !A[i]) || !H[i] || !group_off[i])
+                    raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad ansatz or Hamiltonian");
+                B->K[(size_t)i] = K[i];
+                B->koff[(size_t)i + 1] = B->koff[(size_t)i] + K[i];
+                B->nq[(size_t)i] = n;
+                const int w = team ? team[i] : default_team(n);
+                if (w < 1)
+                    raise(QF_E_ARG, "instance " + std::to_string(i) + ": team size < 1");
+                B->W[(size_t)i] = w;
+            }
+            B->grid = resident_grid();
+            for (int i = 0; i < count; i++) {
+                // a team never exceeds one 1024-pair tile per member or the grid
+                const int n = n_qubits[i];
+                const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBlock * kItems));
+                B->W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B->W[(size_t)i], tiles, (int64_t)B->grid});
+            }
+            B->K_total = B->koff[(size_t)count];
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->nq[a] > B->nq[b]; });
+
+            std::vector<BatchEntry> ent;
+            std::vector<RunDesc> runs;
+            std::vector<GroupDesc> groups;
+            std::vector<uint32_t> zs;
+            std::vector<double> cs;
+            uint64_t state_amps = 0;
+            int64_t tickets = 0, parts = 0;
+            for (int i : order) {
+                const int n = n_qubits[i];
+                int tab = 0;
+                std::vector<RunDesc> r;
+                if (K[i] > 0) {
+                    check_terms("batch ansatz", n, A[i], K[i]);
+                    r = make_runs(A[i], K[i], tab);
+                }
+                std::vector<GroupDesc> gd;
+                std::vector<uint32_t> z;
+                std::vector<double> c;
+                build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
+                BatchEntry e;
+                std::memset(&e, 0, sizeof e);
+                e.n = n;
+                e.W = B->W[(size_t)i];
+                e.nruns = (int32_t)r.size();
+                e.G = (int32_t)gd.size();
+                e.occ = (uint32_t)occ_mask[i];
+                e.run0 = (int32_t)runs.size();
+                e.group0 = (int32_t)groups.size();
+                e.term0 = (int32_t)zs.size();
+                e.theta0 = (int32_t)B->koff[(size_t)i];
+                e.ticket0 = (int32_t)tickets;
+                e.part0 = (int32_t)parts;
+                e.out = i;
+                e.state0 = state_amps;
+                ent.push_back(e);
+                runs.insert(runs.end(), r.begin(), r.end());
+                groups.insert(groups.end(), gd.begin(), gd.end());
+                zs.insert(zs.end(), z.begin(), z.end());
+                cs.insert(cs.end(), c.begin(), c.end());
+                state_amps += 2ull << n;
+                tickets += e.W;
+                parts += 2 * e.W * kMaxRun + e.W;
+                if (zs.size() > (size_t)INT32_MAX || tickets > INT32_MAX)
+                    raise(QF_E_ARG, "batch too large");
+            }
+            B->nentries = (int)ent.size();
+            B->total_tickets = (unsigned)tickets;
+            B->grid = std::min<unsigned>(B->grid, B->total_tickets);
+            B->state_bytes = state_amps * sizeof(double2);
+            B->d_entries = dev_alloc<BatchEntry>(ent.size());
+            B->d_runs = dev_alloc<RunDesc>(runs.size());
+            B->d_groups = dev_alloc<GroupDesc>(groups.size());
+            B->d_z = dev_alloc<uint32_t>(zs.size());
+            B->d_c = dev_alloc<double>(cs.size());
+            B->d_theta = dev_alloc<double>((size_t)std::max<int64_t>(B->K_total, 1));
+            B->d_grad = dev_alloc<double>((size_t)std::max<int64_t>(B->K_total, 1));
+            B->d_states = dev_alloc<double2>((size_t)state_amps);
+            B->d_partials = dev_alloc<double>((size_t)parts);
+            B->d_sync = dev_alloc<unsigned>(ent.size());
+            B->d_ticket = dev_alloc<unsigned>(1);
+            B->d_err = dev_alloc<unsigned>(1);
+            B->d_E = dev_alloc<double>((size_t)count);
+            QF_HIP(hipMemcpy(B->d_entries, ent.data(), ent.size() * sizeof(BatchEntry), hipMemcpyHostToDevice));
+            if (!runs.empty())
+                QF_HIP(hipMemcpy(B->d_runs, runs.data(), runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice));
+            QF_HIP(hipMemcpy(B->d_groups, groups.data(), groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+            QF_HIP(hipMemcpy(B->d_z, zs.data(), zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+            QF_HIP(hipMemcpy(B->d_c, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+            QF_HIP(hipMemset(B->d_grad, 0, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double)));
+            QF_HIP(hipHostMalloc((void **)&B->h_theta, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double),
+                                 hipHostMallocDefault));
+            QF_HIP(hipHostMalloc((void **)&B->h_grad, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double),
+                                 hipHostMallocDefault));
+            QF_HIP(hipHostMalloc((void **)&B->h_E, (size_t)count * sizeof(double), hipHostMallocDefault));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_batch_destroy(qf_batch *b)
+{
+    delete b;
+    return QF_OK;
+}
+
+extern "C" int qf_batch_info(const qf_batch *b, int *team, int64_t *state_bytes, int *grid)
+{
+    if (!b)
+        return fail(QF_E_ARG, "qf_batch_info: batch is NULL");
+    if (team)
+        for (int i = 0; i < b->count; i++)
+            team[i] = b->W[(size_t)i];
+    if (state_bytes)
+        *state_bytes = (int64_t)b->state_bytes;
+    if (grid)
+        *grid = (int)b->grid;
+    return QF_OK;
+}
+
+extern "C" int qf_batch_set_spin_limit(qf_batch *b, uint32_t polls)
+{
+    if (!b || polls == 0)
+        return fail(QF_E_ARG, "qf_batch_set_spin_limit: bad arguments");
+    b->spin_limit = polls;
+    if (b->exec) {  // the captured launch holds the old limit
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    return QF_OK;
+}
+
+extern "C" int qf_batch_run(qf_batch *B, const double *theta, double *E_out, double *dE_dtheta, int use_graph,
+                            void *stream)
+{
+    return guarded([&]() -> int {
+        if (!B || !E_out || (B->K_total > 0 && !theta))
+            return fail(QF_E_ARG, "qf_batch_run: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        if (B->K_total > 0)
+            std::memcpy(B->h_theta, theta, (size_t)B->K_total * sizeof(double));
+        if (use_graph) {
+            if (B->exec && B->graph_stream != s) {
+                (void)hipGraphExecDestroy(B->exec);
+                (void)hipGraphDestroy(B->graph);
+                B->exec = nullptr;
+                B->graph = nullptr;
+            }
+            if (!B->exec) {
+                hipStream_t cs = s;
+                bool own = false;
+                if (!cs) {  // the legacy default stream cannot be captured
+                    QF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                    own = true;
+                }
+                QF_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                try {
+                    batch_enqueue(*B, cs);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(cs, &g);
+                    if (g)
+                        (void)hipGraphDestroy(g);
+                    if (own)
+                        (void)hipStreamDestroy(cs);
+                    throw;
+                }
+                QF_HIP(hipStreamEndCapture(cs, &B->graph));
+                if (own)
+                    QF_HIP(hipStreamDestroy(cs));
+                QF_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+                B->graph_stream = s;
+            }
+            QF_HIP(hipGraphLaunch(B->exec, s));
+        } else {
+            batch_enqueue(*B, s);
+        }
+        QF_HIP(hipStreamSynchronize(s));
+        unsigned err = 0;
+        QF_HIP(hipMemcpy(&err, B->d_err, sizeof err, hipMemcpyDeviceToHost));
+        if (err)
+            return fail(QF_E_HIP, "qf_batch_run: a team barrier timed out (spin limit %u polls)", B->spin_limit);
+        std::memcpy(E_out, B->h_E, (size_t)B->count * sizeof(double));
+        if (dE_dtheta && B->K_total > 0)
+            std::memcpy(dE_dtheta, B->h_grad, (size_t)B->K_total * sizeof(double));
+        return QF_OK;
+    });
+}

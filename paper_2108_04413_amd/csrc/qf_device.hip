@@ -28,63 +28,10 @@
 #include <vector>
 
 #include "qf_common.h"
+#include "qf_kernels.h"
+#include "qf_host.h"
 
 namespace qf {
-
-constexpr int kBlock = 256;
-constexpr int kItems = 4;        // amplitude pairs per thread per step
-constexpr int kMaxRun = 8;       // strings per fused run
-constexpr int kMaxRank = 6;      // rank of a run's sign patterns (table <= 64)
-constexpr int kMaxBlocks = 2048; // cap of grid-stride launches (8 blocks / CU)
-
-struct RunDesc {
-    uint32_t x, z0, hbit, a0;
-    uint32_t b[kMaxRank];
-    int32_t r, k0, m, tab;
-    uint8_t e[kMaxRun];
-    int8_t s[kMaxRun];
-};
-
-struct GroupDesc {
-    uint32_t x, hbit;
-    int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
-};
-
-// ------------------------------------------------------------ helpers
-
-__device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)
-{
-    const uint32_t lo = j & ((1u << bit) - 1u);
-    return ((j ^ lo) << 1) | lo;
-}
-
-__device__ __forceinline__ uint32_t par(uint32_t v) { return __popc(v) & 1u; }
-
-// v * i^k
-__device__ __forceinline__ double2 mul_ik(uint32_t k, double2 v)
-{
-    double re = (k & 1u) ? -v.y : v.x;
-    double im = (k & 1u) ? v.x : v.y;
-    if (k & 2u) {
-        re = -re;
-        im = -im;
-    }
-    return make_double2(re, im);
-}
-
-__device__ __forceinline__ double flip(double v, uint32_t p)
-{
-    // multiply by (-1)^p on the sign bit
-    return __hiloint2double(__double2hiint(v) ^ (int)(p << 31), __double2loint(v));
-}
-
-__device__ __forceinline__ uint32_t run_coords(const RunDesc &d, uint32_t y)
-{
-    uint32_t u = 0;
-    for (int q = 0; q < d.r; q++)
-        u |= par(y & d.b[q]) << q;
-    return u;
-}
 
 // Block-wide deterministic sum of M values per thread, then the last block
 // to arrive sums the per-block partials in block order into out[0..M).
@@ -215,34 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_diag(double2 *__restrict__ psi
         const double c = cs.x, s = sgn * cs.y;
         const double2 v = psi[y];
         psi[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
-    }
-}
-
-// D_g(y_i) = sum_{k in g} c_k omega_k(y_i) for kItems indices at once; every
-// string is loaded once (scalar) and applied to all items.
-__device__ __forceinline__ void group_d(const GroupDesc &g, const uint32_t *__restrict__ zs,
-                                        const double *__restrict__ cs, const uint32_t (&y)[kItems],
-                                        double (&dre)[kItems], double (&dim)[kItems])
-{
-#pragma unroll
-    for (int i = 0; i < kItems; i++) {
-        dre[i] = 0.0;
-        dim[i] = 0.0;
-    }
-#pragma unroll 2
-    for (int k = g.k0; k < g.kre; k++) {
-        const uint32_t z = zs[k];
-        const double c = cs[k];
-#pragma unroll
-        for (int i = 0; i < kItems; i++)
-            dre[i] += flip(c, par(y[i] & z));
-    }
-    for (int k = g.kre; k < g.k1; k++) {
-        const uint32_t z = zs[k];
-        const double c = cs[k];
-#pragma unroll
-        for (int i = 0; i < kItems; i++)
-            dim[i] += flip(c, par(y[i] & z));
     }
 }
 
@@ -402,27 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_run(double2 *__restrict__ ph
 
 // ===================================================================== host
 
-#define QF_HIP(expr)                                                                               \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            qf::raise(QF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));                \
-    } while (0)
-
 namespace qf {
-
-template <class T> T *dev_alloc(size_t count)
-{
-    void *p = nullptr;
-    if (count == 0)
-        count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        raise(QF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    return (T *)p;
-}
 
 void check_terms(const char *who, int n, const qf_term *t, int64_t K)
 {
@@ -431,8 +330,6 @@ void check_terms(const char *who, int n, const qf_term *t, int64_t K)
         if ((t[k].x & ~lim) || (t[k].z & ~lim))
             raise(QF_E_RANGE, std::string(who) + ": term " + std::to_string(k) + " has a mask bit >= n_qubits");
 }
-
-inline uint32_t hibit(uint32_t x) { return x ? 31u - (uint32_t)__builtin_clz(x) : 0u; }
 
 // Split a term list into fused runs: consecutive strings with the same flip
 // mask whose Y-parity agrees (so they commute), at most kMaxRun strings and
@@ -489,6 +386,48 @@ std::vector<RunDesc> make_runs(const qf_term *T, int64_t K, int &tab_entries)
         runs.push_back(d);
     }
     return runs;
+}
+
+// Host tables of a grouped Hamiltonian: per group, real-phase strings first,
+// with the sign of i^popcount(x&z) folded into the coefficient.
+void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::vector<GroupDesc> &gd,
+                  std::vector<uint32_t> &zs, std::vector<double> &cs)
+{
+    if (goff[0] != 0)
+        raise(QF_E_ARG, "group_off[0] must be 0");
+    const int64_t KH = goff[G];
+    check_terms("hamiltonian", n, H, KH);
+    gd.assign((size_t)G, GroupDesc{});
+    zs.assign((size_t)KH, 0u);
+    cs.assign((size_t)KH, 0.0);
+    for (int64_t g = 0; g < G; g++) {
+        const int64_t a = goff[g], b = goff[g + 1];
+        if (b < a || b > KH)
+            raise(QF_E_ARG, "group_off is not monotone");
+        if (b == a)
+            raise(QF_E_ARG, "empty group " + std::to_string(g));
+        const uint64_t x = H[a].x;
+        int64_t w = a;
+        for (int pass = 0; pass < 2; pass++) {
+            for (int64_t k = a; k < b; k++) {
+                if (H[k].x != x)
+                    raise(QF_E_ARG, "group " + std::to_string(g) + " mixes flip masks");
+                const int ph = popc64(H[k].x & H[k].z) & 3;
+                if ((ph & 1) != pass)
+                    continue;
+                zs[(size_t)w] = (uint32_t)H[k].z;
+                cs[(size_t)w] = (ph & 2) ? -H[k].c : H[k].c;
+                w++;
+            }
+            if (pass == 0)
+                gd[(size_t)g].kre = (int32_t)w;
+        }
+        gd[(size_t)g].x = (uint32_t)x;
+        gd[(size_t)g].hbit = hibit((uint32_t)x);
+        gd[(size_t)g].k0 = (int32_t)a;
+        gd[(size_t)g].k1 = (int32_t)b;
+        gd[(size_t)g].pad = 0;
+    }
 }
 
 } // namespace qf
@@ -552,42 +491,11 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         QF_HIP(hipEventCreateWithFlags(&P.theta_done, hipEventDisableTiming));
     }
     if (G > 0) {
-        if (goff[0] != 0)
-            raise(QF_E_ARG, "group_off[0] must be 0");
+        std::vector<GroupDesc> gd;
+        std::vector<uint32_t> zs;
+        std::vector<double> cs;
+        build_groups(n, H, goff, G, gd, zs, cs);
         const int64_t KH = goff[G];
-        check_terms("hamiltonian", n, H, KH);
-        std::vector<GroupDesc> gd((size_t)G);
-        std::vector<uint32_t> zs((size_t)KH);
-        std::vector<double> cs((size_t)KH);
-        for (int64_t g = 0; g < G; g++) {
-            const int64_t a = goff[g], b = goff[g + 1];
-            if (b < a || b > KH)
-                raise(QF_E_ARG, "group_off is not monotone");
-            if (b == a)
-                raise(QF_E_ARG, "empty group " + std::to_string(g));
-            const uint64_t x = H[a].x;
-            int64_t w = a;
-            // real-phase strings (even number of Y) first, then imaginary
-            for (int pass = 0; pass < 2; pass++) {
-                for (int64_t k = a; k < b; k++) {
-                    if (H[k].x != x)
-                        raise(QF_E_ARG, "group " + std::to_string(g) + " mixes flip masks");
-                    const int ph = popc64(H[k].x & H[k].z) & 3;
-                    if ((ph & 1) != pass)
-                        continue;
-                    zs[(size_t)w] = (uint32_t)H[k].z;
-                    cs[(size_t)w] = (ph & 2) ? -H[k].c : H[k].c;
-                    w++;
-                }
-                if (pass == 0)
-                    gd[(size_t)g].kre = (int32_t)w;
-            }
-            gd[(size_t)g].x = (uint32_t)x;
-            gd[(size_t)g].hbit = hibit((uint32_t)x);
-            gd[(size_t)g].k0 = (int32_t)a;
-            gd[(size_t)g].k1 = (int32_t)b;
-            gd[(size_t)g].pad = 0;
-        }
         P.G = (int)G;
         P.d_groups = dev_alloc<GroupDesc>((size_t)G);
         P.d_z = dev_alloc<uint32_t>((size_t)KH);

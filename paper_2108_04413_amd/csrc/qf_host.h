@@ -1,0 +1,49 @@
+// Host-side helpers shared by the plan path (qf_device.hip) and the batched
+// path (qf_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "qf_common.h"
+#include "qf_kernels.h"
+
+#define QF_HIP(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            qf::raise(QF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+namespace qf {
+
+template <class T> T *dev_alloc(size_t count)
+{
+    void *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        raise(QF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return (T *)p;
+}
+
+inline uint32_t hibit(uint32_t x) { return x ? 31u - (uint32_t)__builtin_clz(x) : 0u; }
+
+// Reject masks with a bit at or above n.
+void check_terms(const char *who, int n, const qf_term *t, int64_t K);
+
+// Split a term list into fused runs (see qf_device.hip); tab_entries receives
+// the total size of the runs' (cos, sin) tables.
+std::vector<RunDesc> make_runs(const qf_term *T, int64_t K, int &tab_entries);
+
+// Per-group descriptors and the reordered (z, signed c) arrays of a grouped
+// Hamiltonian.
+void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::vector<GroupDesc> &gd,
+                  std::vector<uint32_t> &zs, std::vector<double> &cs);
+
+} // namespace qf

@@ -1,0 +1,94 @@
+// Device-side types and helpers shared by the plain kernels (qf_device.hip)
+// and the persistent batched kernel (qf_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qf {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 4;        // amplitude pairs per thread per step
+constexpr int kMaxRun = 8;       // strings per fused run
+constexpr int kMaxRank = 6;      // rank of a run's sign patterns (table <= 64)
+constexpr int kMaxBlocks = 2048; // cap of grid-stride launches (8 blocks / CU)
+
+struct RunDesc {
+    uint32_t x, z0, hbit, a0;
+    uint32_t b[kMaxRank];
+    int32_t r, k0, m, tab;
+    uint8_t e[kMaxRun];
+    int8_t s[kMaxRun];
+};
+
+struct GroupDesc {
+    uint32_t x, hbit;
+    int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
+};
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)
+{
+    const uint32_t lo = j & ((1u << bit) - 1u);
+    return ((j ^ lo) << 1) | lo;
+}
+
+__device__ __forceinline__ uint32_t par(uint32_t v) { return __popc(v) & 1u; }
+
+// v * i^k
+__device__ __forceinline__ double2 mul_ik(uint32_t k, double2 v)
+{
+    double re = (k & 1u) ? -v.y : v.x;
+    double im = (k & 1u) ? v.x : v.y;
+    if (k & 2u) {
+        re = -re;
+        im = -im;
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double flip(double v, uint32_t p)
+{
+    // multiply by (-1)^p on the sign bit
+    return __hiloint2double(__double2hiint(v) ^ (int)(p << 31), __double2loint(v));
+}
+
+__device__ __forceinline__ uint32_t run_coords(const RunDesc &d, uint32_t y)
+{
+    uint32_t u = 0;
+    for (int q = 0; q < d.r; q++)
+        u |= par(y & d.b[q]) << q;
+    return u;
+}
+
+// D_g(y_i) = sum_{k in g} c_k omega_k(y_i) for kItems indices at once; every
+// string is loaded once (scalar) and applied to all items.
+__device__ __forceinline__ void group_d(const GroupDesc &g, const uint32_t *__restrict__ zs,
+                                        const double *__restrict__ cs, const uint32_t (&y)[kItems],
+                                        double (&dre)[kItems], double (&dim)[kItems])
+{
+#pragma unroll
+    for (int i = 0; i < kItems; i++) {
+        dre[i] = 0.0;
+        dim[i] = 0.0;
+    }
+#pragma unroll 2
+    for (int k = g.k0; k < g.kre; k++) {
+        const uint32_t z = zs[k];
+        const double c = cs[k];
+#pragma unroll
+        for (int i = 0; i < kItems; i++)
+            dre[i] += flip(c, par(y[i] & z));
+    }
+    for (int k = g.kre; k < g.k1; k++) {
+        const uint32_t z = zs[k];
+        const double c = cs[k];
+#pragma unroll
+        for (int i = 0; i < kItems; i++)
+            dim[i] += flip(c, par(y[i] & z));
+    }
+}
+
+} // namespace qf

@@ -188,3 +188,21 @@ def test_device_calls_reject_bad_arguments_before_gpu(qf):
     assert "mixes flip masks" in lib.qf_last_error().decode()
     assert lib.qf_energy_grad(8, 3, None, None, 0, bad.ctypes.data, off.ctypes.data, 0, dummy,
                               ctypes.byref(E), None, None) == -1
+
+
+def test_batch_create_rejects_bad_arguments_before_gpu(qf):
+    lib = qf.lib
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int * 1)(40)
+    occ = (ctypes.c_uint64 * 1)(3)
+    K = (ctypes.c_int64 * 1)(0)
+    G = (ctypes.c_int64 * 1)(1)
+    nulls = (ctypes.c_void_p * 1)(None)
+    assert lib.qf_batch_create(1, n, occ, nulls, K, nulls, nulls, G, None, ctypes.byref(h)) == -2
+    assert lib.qf_batch_create(0, n, occ, nulls, K, nulls, nulls, G, None, ctypes.byref(h)) == -1
+    n[0] = 8
+    occ[0] = 1 << 9
+    assert lib.qf_batch_create(1, n, occ, nulls, K, nulls, nulls, G, None, ctypes.byref(h)) == -2
+    occ[0] = 3
+    assert lib.qf_batch_create(1, n, occ, nulls, K, nulls, nulls, G, None, ctypes.byref(h)) == -1
+    assert lib.qf_batch_run(None, None, None, None, 0, None) == -1
