@@ -117,6 +117,69 @@ def cpu_baseline(qi, sysd, budget_s=20.0):
                       f"{t_used:.1f} s on the host; same algorithmic byte count as the GPU step"}
 
 
+def instance_from_recipe(qf, qi, r):
+    h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
+    H, off, _ = qf.build_paulis("hamiltonian", r["n_orb"], r["n_elec"], h, g)
+    A, aoff, _ = qf.build_paulis("uccsd", r["n_orb"], r["n_elec"])
+    t = qi.amplitudes(len(aoff) - 1, r["seed"], r["t_scale"])
+    return dict(n=2 * r["n_orb"], occ=(1 << r["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff,
+                theta=qf.ansatz_angles(A, aoff, t))
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
+
+
+def batched_leg(qf, qi, count=256, reps=2):
+    """256 (molecule, theta) instances of 12-22 qubits: one persistent graph
+    launch vs the plain path (one plan call per instance, in order)."""
+    import torch
+    t0 = time.perf_counter()
+    insts = [instance_from_recipe(qf, qi, r) for r in qi.batched_instances(count)]
+    log(f"batched: built {count} instances in {time.perf_counter() - t0:.1f} s")
+    thetas = [d["theta"] for d in insts]
+    B = qf.Batch(insts)
+    info = B.info()
+    B.run(thetas, use_graph=True)
+    tb = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        Eb, gb = B.run(thetas, use_graph=True)
+        tb.append(time.perf_counter() - t0)
+    t_batch = min(tb)
+    log(f"batched: {count} energy+grad in {t_batch * 1e3:.1f} ms (grid {info['grid']})")
+    B.close()
+    plans = [qf.Plan(d["n"], d["A"], d["H"], d["off"]) for d in insts]
+    ws = torch.empty(2 << max(d["n"] for d in insts), dtype=torch.complex128, device="cuda")
+    for d, p in list(zip(insts, plans))[:8]:
+        p.energy_grad(d["occ"], d["theta"], ws)
+    lat, done = [], []
+    dE = dG = 0.0
+    t_start = time.perf_counter()
+    for i, (d, p) in enumerate(zip(insts, plans)):
+        t0 = time.perf_counter()
+        e, g = p.energy_grad(d["occ"], d["theta"], ws)
+        t1 = time.perf_counter()
+        lat.append(t1 - t0)
+        done.append(t1 - t_start)
+        dE = max(dE, abs(e - Eb[i]))
+        dG = max(dG, float(np.max(np.abs(g - gb[i]))) if len(g) else 0.0)
+    t_plain = time.perf_counter() - t_start
+    log(f"plain: {count} energy+grad in {t_plain * 1e3:.1f} ms; max |dE| {dE:.2e}, max |dgrad| {dG:.2e}")
+    for p in plans:
+        p.close()
+    del ws
+    torch.cuda.empty_cache()
+    return {"batched_evals_per_s": count / t_batch, "plain_evals_per_s": count / t_plain,
+            "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3, "speedup": t_plain / t_batch,
+            "batched_latency_ms_p50": t_batch * 1e3, "batched_latency_ms_p99": t_batch * 1e3,
+            "plain_latency_from_submit_ms_p50": pct(done, 50) * 1e3,
+            "plain_latency_from_submit_ms_p99": pct(done, 99) * 1e3,
+            "plain_per_call_ms_p50": pct(lat, 50) * 1e3, "plain_per_call_ms_p99": pct(lat, 99) * 1e3,
+            "max_abs_dE_batched_vs_plain": dE, "max_abs_dgrad_batched_vs_plain": dG,
+            "teams": sorted(set(zip((d["n"] for d in insts), info["team"]))), "grid": info["grid"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-20q", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="run one torch copy of one state (4 GiB) first: a plain copy kernel of known "
                          "size for scaling hardware byte counters")
@@ -205,6 +269,10 @@ def main():
         dt = (time.perf_counter() - t0) / reps
         extra.update({"energy_grad_20q_ms": dt * 1e3, "energy_grad_20q_evals_per_s": 1.0 / dt,
                       "energy_20q": e20})
+
+    if not args.no_batch:
+        log("batched leg (256 instances, 12-22 qubits)")
+        extra["batched_256"] = batched_leg(qf, qi)
 
     line = {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -19,6 +19,12 @@ LIB_PATH = os.path.join(_HERE, "libqforte_mi355x.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_04413_amd.build`")
 
+# torch's ROCm build loads its own libamdhip64 (DT_NEEDED "libamdhip64.so",
+# SONAME "libamdhip64.so.7").  Loading torch first lets this library's
+# "libamdhip64.so.7" dependency bind to that same runtime; in the other order
+# the process would hold two HIP runtimes that do not share devices.
+import torch  # noqa: E402,F401
+
 TERM_DTYPE = np.dtype([("x", "<u8"), ("z", "<u8"), ("c", "<f8")])
 
 QF_OK = 0

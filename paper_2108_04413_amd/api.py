@@ -142,7 +142,8 @@ class Batch:
 
     instances: list of dicts with keys n (qubits), occ (int mask), A (ansatz
     terms), H (Hamiltonian terms), off (group offsets).  team: optional list
-    of workgroups per instance.
+    of workgroups per instance (<= 0: library default); None uses the
+    autotuned table for this device when one is committed.
     """
 
     def __init__(self, instances, team=None):
@@ -158,6 +159,11 @@ class Batch:
         H = (ctypes.c_void_p * self.count)(*[ptr(d["H"]) for d in instances])
         O = (ctypes.c_void_p * self.count)(*[ptr(o) for o in offs])
         G = (ctypes.c_int64 * self.count)(*[len(o) - 1 for o in offs])
+        if team is None:
+            from .autotune import device_arch, load_table
+            tab = load_table(device_arch())
+            if tab:
+                team = [tab.get(int(d["n"]), 0) for d in instances]
         T = None if team is None else (ctypes.c_int * self.count)(*[int(w) for w in team])
         h = ctypes.c_void_p()
         check(lib.qf_batch_create(self.count, n, occ, A, K, H, O, G, T, ctypes.byref(h)), "qf_batch_create")

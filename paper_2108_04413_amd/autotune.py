@@ -1,0 +1,108 @@
+"""Autotuner for the persistent batched kernel.
+
+The schedule knob of qf_batch is the team size W(n): how many workgroups
+cooperate on one instance of n qubits.  Small W runs many instances side by
+side (each pass is short and stays in one CU's cache); large W spreads one
+instance over the chip (needed when few large instances remain).  For each
+qubit count the tuner builds `count` seeded instances of that size, runs one
+batch launch per candidate W (powers of two up to the limit the library
+clamps to) and keeps the fastest.  The table is written as JSON
+{"arch": ..., "team": {n: W}, "ms": {n: {W: ms}}} and picked up by
+api.Batch when it matches the running device.
+
+    python -m paper_2108_04413_amd.autotune --out tuned_gfx950.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuned_gfx950.json")
+
+
+def device_arch() -> str:
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    return getattr(props, "gcnArchName", "unknown").split(":")[0]
+
+
+def load_table(arch: str | None = None) -> dict | None:
+    """The committed team table for this architecture, or None."""
+    if not os.path.exists(TABLE):
+        return None
+    with open(TABLE) as f:
+        tab = json.load(f)
+    if arch is not None and tab.get("arch") != arch:
+        return None
+    return {int(k): int(v) for k, v in tab["team"].items()}
+
+
+def _instances(qf, qi, n_qubits: int, count: int, seed0: int):
+    out = []
+    for i in range(count):
+        n_orb = n_qubits // 2
+        seed = seed0 + i
+        h, g = qi.integrals(n_orb, n_orb, seed)
+        H, off, _ = qf.build_paulis("hamiltonian", n_orb, n_orb, h, g)
+        A, aoff, _ = qf.build_paulis("uccsd", n_orb, n_orb)
+        t = qi.amplitudes(len(aoff) - 1, seed, 0.2)
+        out.append(dict(n=n_qubits, occ=(1 << n_orb) - 1, H=H, off=off, A=A,
+                        theta=qf.ansatz_angles(A, aoff, t)))
+    return out
+
+
+def tune(ns=(12, 14, 16, 18, 20, 22), count: int = 43, reps: int = 2, max_team: int = 256,
+         log=print) -> dict:
+    import paper_2108_04413_amd as qf
+    sys.path.insert(0, os.path.dirname(HERE))
+    import qf_inputs as qi
+
+    result = {"arch": device_arch(), "count": count, "team": {}, "ms": {}}
+    for n in ns:
+        insts = _instances(qf, qi, n, count, 9000 + 100 * n)
+        thetas = [d["theta"] for d in insts]
+        tiles = max(1, (1 << (n - 1)) // 1024)
+        cands = [w for w in (1, 2, 4, 8, 16, 32, 64, 128, 256) if w <= min(tiles, max_team)]
+        times = {}
+        for w in cands:
+            B = qf.Batch(insts, team=[w] * count)
+            if B.info()["team"][0] != w:  # clamped by the grid
+                B.close()
+                continue
+            B.run(thetas, use_graph=True)  # capture + warm
+            best = float("inf")
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                B.run(thetas, use_graph=True)
+                best = min(best, time.perf_counter() - t0)
+            B.close()
+            times[w] = best * 1e3
+            log(f"autotune n={n} W={w}: {times[w]:.2f} ms for {count} instances")
+        wbest = min(times, key=times.get)
+        result["team"][str(n)] = int(wbest)
+        result["ms"][str(n)] = {str(k): v for k, v in times.items()}
+        log(f"autotune n={n}: W={wbest}")
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--count", type=int, default=43)
+    ap.add_argument("--ns", default="12,14,16,18,20,22")
+    args = ap.parse_args()
+    res = tune(tuple(int(v) for v in args.ns.split(",")), count=args.count,
+               log=lambda m: print(m, flush=True))
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res["team"]))
+
+
+if __name__ == "__main__":
+    main()

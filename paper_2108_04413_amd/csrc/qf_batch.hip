@@ -488,10 +488,7 @@ extern "C" int qf_batch_create(int count, const int *n_qubits, const uint64_t *o
                 B->K[(size_t)i] = K[i];
                 B->koff[(size_t)i + 1] = B->koff[(size_t)i] + K[i];
                 B->nq[(size_t)i] = n;
-                const int w = team ? team[i] : default_team(n);
-                if (w < 1)
-                    raise(QF_E_ARG, "instance " + std::to_string(i) + ": team size < 1");
-                B->W[(size_t)i] = w;
+                B->W[(size_t)i] = (team && team[i] > 0) ? team[i] : default_team(n);
             }
             B->grid = resident_grid();
             for (int i = 0; i < count; i++) {
