@@ -180,6 +180,30 @@ def batched_leg(qf, qi, count=256, reps=2):
             "teams": sorted(set(zip((d["n"] for d in insts), info["team"]))), "grid": info["grid"]}
 
 
+def serving_leg(qf, qi, n_req=200):
+    """The first n_req requests of the 10k Poisson trace (2000 req/s, 12-24
+    qubits): continuous batching vs the plain one-at-a-time path."""
+    from paper_2108_04413_amd import serve
+    trace = qi.serving_trace(10000)[:n_req]
+    t0 = time.perf_counter()
+    reqs = serve.make_requests(qf, qi, trace)
+    log(f"serving: built {n_req} requests in {time.perf_counter() - t0:.1f} s")
+    srv = serve.Server(arena_bytes=48 << 30, slots=2, max_wave=64)
+    st_b = srv.serve(reqs)
+    log(f"serving (continuous batching): {st_b}")
+    plain = serve.make_requests(qf, qi, trace)
+    st_p = serve.serve_plain(plain, max(r.n for r in plain))
+    log(f"serving (plain serial): {st_p}")
+    dE = max(abs(a.E - b.E) for a, b in zip(reqs, plain))
+    mix = {}
+    for r in reqs:
+        mix[r.n] = mix.get(r.n, 0) + 1
+    return {"requests": n_req, "offered_rate_req_per_s": 2000.0, "qubit_mix": dict(sorted(mix.items())),
+            "continuous_batching": st_b, "plain_serial": st_p,
+            "throughput_ratio": st_b["throughput_req_per_s"] / st_p["throughput_req_per_s"],
+            "max_abs_dE_batched_vs_plain": dE}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +212,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-20q", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calib", action="store_true",
                     help="run one torch copy of one state (4 GiB) first: a plain copy kernel of known "
                          "size for scaling hardware byte counters")
@@ -273,6 +298,10 @@ def main():
     if not args.no_batch:
         log("batched leg (256 instances, 12-22 qubits)")
         extra["batched_256"] = batched_leg(qf, qi)
+
+    if not args.no_serve:
+        log("serving leg (first 200 requests of the 10k trace)")
+        extra["serving_200"] = serving_leg(qf, qi)
 
     line = {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

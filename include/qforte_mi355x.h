@@ -200,6 +200,30 @@ int qf_batch_create(int count, const int *n_qubits, const uint64_t *occ_mask, co
 int qf_batch_run(qf_batch *batch, const double *theta, double *E_out, double *dE_dtheta, int use_graph,
                  void *stream);
 int qf_batch_info(const qf_batch *batch, int *team, int64_t *state_bytes, int *grid);
+
+/*
+ * Arena batches, for serving loops that must not allocate or free device
+ * memory while other work runs (hipFree synchronizes the device).
+ * qf_batch_create_arena: as qf_batch_create, but every device array
+ *   (tables, two states per instance, outputs) is laid out in the caller's
+ *   device buffer `arena` (256-byte aligned, arena_bytes long, owned by the
+ *   caller and not freed by the batch).  *need_bytes receives the size the
+ *   batch needs; with arena == NULL nothing else happens (size query, QF_OK);
+ *   a smaller arena gives QF_E_SIZE.  Tables are uploaded on `stream` before
+ *   the call returns.
+ * qf_batch_launch: queue theta upload and the persistent kernel on `stream`
+ *   and return at once.  qf_batch_poll: QF_OK when the launch has finished,
+ *   1 while it runs.  qf_batch_collect: wait for it and copy E_out (count)
+ *   and dE_dtheta (concatenated, may be NULL) to host memory.
+ * qf_batch_run on an arena batch is launch + collect (no graph).
+ */
+int qf_batch_create_arena(int count, const int *n_qubits, const uint64_t *occ_mask, const qf_term *const *A,
+                          const int64_t *K, const qf_term *const *H, const int64_t *const *group_off,
+                          const int64_t *n_groups, const int *team, void *arena, int64_t arena_bytes,
+                          int64_t *need_bytes, void *stream, qf_batch **out);
+int qf_batch_launch(qf_batch *batch, const double *theta, void *stream);
+int qf_batch_poll(qf_batch *batch);
+int qf_batch_collect(qf_batch *batch, double *E_out, double *dE_dtheta);
 int qf_batch_set_spin_limit(qf_batch *batch, uint32_t polls);
 int qf_batch_destroy(qf_batch *batch);
 

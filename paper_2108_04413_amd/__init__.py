@@ -8,3 +8,4 @@ from .api import (Batch, Plan, ansatz_angles, apply_pauli_exp, build_paulis, ene
                   energy_grad, grad_t, prepare_state)
 
 __version__ = lib.qf_version().decode()
+from .autograd import UCCEnergy  # noqa: E402,F401

@@ -35,7 +35,8 @@ QF_HAMILTONIAN, QF_UCCSD, QF_UCCD, QF_UCCD_TOP, QF_PUCCD = 0, 1, 2, 3, 4
 EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state", "qf_apply_pauli_exp",
            "qf_energy", "qf_energy_grad", "qf_plan_create", "qf_plan_destroy", "qf_plan_apply",
            "qf_plan_energy", "qf_plan_energy_grad", "qf_plan_sigma", "qf_last_error", "qf_version",
-           "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy")
+           "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy",
+           "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect")
 
 
 class QFError(RuntimeError):
@@ -70,6 +71,10 @@ _sig = {
     "qf_batch_info": [_vp, _vp, _vp, _vp],
     "qf_batch_set_spin_limit": [_vp, ctypes.c_uint32],
     "qf_batch_destroy": [_vp],
+    "qf_batch_create_arena": [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp],
+    "qf_batch_launch": [_vp, _vp, _vp],
+    "qf_batch_poll": [_vp],
+    "qf_batch_collect": [_vp, _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)

@@ -68,7 +68,9 @@ def tune(ns=(12, 14, 16, 18, 20, 22), count: int = 43, reps: int = 2, max_team: 
         insts = _instances(qf, qi, n, count, 9000 + 100 * n)
         thetas = [d["theta"] for d in insts]
         tiles = max(1, (1 << (n - 1)) // 1024)
-        cands = [w for w in (1, 2, 4, 8, 16, 32, 64, 128, 256) if w <= min(tiles, max_team)]
+        # a single workgroup per instance is hopeless beyond 20 qubits
+        w_min = 1 << max(0, n - 20)
+        cands = [w for w in (1, 2, 4, 8, 16, 32, 64, 128, 256) if w_min <= w <= min(tiles, max_team)]
         times = {}
         for w in cands:
             B = qf.Batch(insts, team=[w] * count)
@@ -96,9 +98,16 @@ def main():
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--count", type=int, default=43)
     ap.add_argument("--ns", default="12,14,16,18,20,22")
+    ap.add_argument("--merge", action="store_true", help="update the existing table instead of replacing it")
     args = ap.parse_args()
     res = tune(tuple(int(v) for v in args.ns.split(",")), count=args.count,
                log=lambda m: print(m, flush=True))
+    if args.merge and os.path.exists(args.out):
+        with open(args.out) as f:
+            old = json.load(f)
+        old["team"].update(res["team"])
+        old["ms"].update(res["ms"])
+        res = old
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res["team"]))

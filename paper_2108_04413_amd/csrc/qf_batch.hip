@@ -375,11 +375,15 @@ struct qf_batch {
     unsigned total_tickets = 0;
     unsigned grid = 0;
     unsigned spin_limit = 1u << 28;
+    bool owns_device = true;  // false: device data lives in a caller arena
+    void *d_base = nullptr;   // the one device allocation of an owning batch
     int64_t K_total = 0;
-    std::vector<int64_t> K;       // per caller instance
-    std::vector<int64_t> koff;    // caller order offsets into theta/grad
-    std::vector<int> W;           // per caller instance
+    std::vector<int64_t> koff;  // caller-order offsets into theta / grad
+    std::vector<int> W;         // per caller instance
     std::vector<int> nq;
+    size_t state_bytes = 0;
+    size_t device_bytes = 0;
+    // device data (owned or carved from the arena)
     qf::BatchEntry *d_entries = nullptr;
     qf::RunDesc *d_runs = nullptr;
     qf::GroupDesc *d_groups = nullptr;
@@ -393,29 +397,38 @@ struct qf_batch {
     unsigned *d_err = nullptr;
     double *d_E = nullptr;
     double *d_grad = nullptr;
-    double *h_theta = nullptr;  // pinned staging
+    // host side
+    std::vector<double> theta_host;  // arena mode: source of the async theta upload
+    double *h_theta = nullptr;       // owned mode: pinned staging (graph-capturable copies)
     double *h_E = nullptr;
     double *h_grad = nullptr;
-    size_t state_bytes = 0;
+    hipEvent_t done = nullptr;
+    bool launched = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
 
-    ~qf_batch()
+    void drop_graph()
     {
         if (exec)
             (void)hipGraphExecDestroy(exec);
         if (graph)
             (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+
+    ~qf_batch()
+    {
+        drop_graph();
+        if (done)
+            (void)hipEventDestroy(done);
         void *hp[] = {h_theta, h_E, h_grad};
         for (void *p : hp)
             if (p)
                 (void)hipHostFree(p);
-        void *dp[] = {d_entries, d_runs, d_groups, d_z, d_c, d_theta, d_states, d_partials,
-                      d_sync, d_ticket, d_err, d_E, d_grad};
-        for (void *p : dp)
-            if (p)
-                (void)hipFree(p);
+        if (owns_device && d_base)
+            (void)hipFree(d_base);
     }
 };
 
@@ -438,19 +451,186 @@ unsigned resident_grid()
     return (unsigned)(cus * per);
 }
 
-void batch_enqueue(qf_batch &B, hipStream_t s)
+// Host tables of a batch in launch order (largest instance first).
+struct BatchHost {
+    std::vector<BatchEntry> ent;
+    std::vector<RunDesc> runs;
+    std::vector<GroupDesc> groups;
+    std::vector<uint32_t> zs;
+    std::vector<double> cs;
+    uint64_t state_amps = 0;
+    int64_t tickets = 0, parts = 0;
+};
+
+// Validate the instances, pick team sizes and assemble the host tables.
+void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, const uint64_t *occ_mask,
+                    const qf_term *const *A, const int64_t *K, const qf_term *const *H,
+                    const int64_t *const *group_off, const int64_t *n_groups, const int *team)
 {
-    QF_HIP(hipMemcpyAsync(B.d_theta, B.h_theta, (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
-                          hipMemcpyHostToDevice, s));
+    if (count < 1 || !n_qubits || !occ_mask || !K || !A || !H || !group_off || !n_groups)
+        raise(QF_E_ARG, "qf_batch_create: null array or count < 1");
+    B.count = count;
+    B.koff.assign((size_t)count + 1, 0);
+    B.W.assign((size_t)count, 1);
+    B.nq.assign((size_t)count, 0);
+    for (int i = 0; i < count; i++) {
+        const int n = n_qubits[i];
+        if (n < 1 || n > 30)
+            raise(QF_E_RANGE, "instance " + std::to_string(i) + ": n_qubits out of range [1, 30]");
+        if (occ_mask[i] >> n)
+            raise(QF_E_RANGE, "instance " + std::to_string(i) + ": occ_mask has a bit >= n_qubits");
+        if (K[i] < 0 || n_groups[i] < 1 || (K[i] > 0 && !A[i]) || !H[i] || !group_off[i])
+            raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad ansatz or Hamiltonian");
+        B.koff[(size_t)i + 1] = B.koff[(size_t)i] + K[i];
+        B.nq[(size_t)i] = n;
+        B.W[(size_t)i] = (team && team[i] > 0) ? team[i] : default_team(n);
+    }
+    B.K_total = B.koff[(size_t)count];
+    B.grid = resident_grid();
+    for (int i = 0; i < count; i++) {
+        // a team never exceeds one 1024-pair tile per member or the grid
+        const int n = n_qubits[i];
+        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBlock * kItems));
+        B.W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B.W[(size_t)i], tiles, (int64_t)B.grid});
+    }
+    std::vector<int> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.nq[a] > B.nq[b]; });
+    for (int i : order) {
+        const int n = n_qubits[i];
+        int tab = 0;
+        std::vector<RunDesc> r;
+        if (K[i] > 0) {
+            check_terms("batch ansatz", n, A[i], K[i]);
+            r = make_runs(A[i], K[i], tab);
+        }
+        std::vector<GroupDesc> gd;
+        std::vector<uint32_t> z;
+        std::vector<double> c;
+        build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
+        BatchEntry e;
+        std::memset(&e, 0, sizeof e);
+        e.n = n;
+        e.W = B.W[(size_t)i];
+        e.nruns = (int32_t)r.size();
+        e.G = (int32_t)gd.size();
+        e.occ = (uint32_t)occ_mask[i];
+        e.run0 = (int32_t)T.runs.size();
+        e.group0 = (int32_t)T.groups.size();
+        e.term0 = (int32_t)T.zs.size();
+        e.theta0 = (int32_t)B.koff[(size_t)i];
+        e.ticket0 = (int32_t)T.tickets;
+        e.part0 = (int32_t)T.parts;
+        e.out = i;
+        e.state0 = T.state_amps;
+        T.ent.push_back(e);
+        T.runs.insert(T.runs.end(), r.begin(), r.end());
+        T.groups.insert(T.groups.end(), gd.begin(), gd.end());
+        T.zs.insert(T.zs.end(), z.begin(), z.end());
+        T.cs.insert(T.cs.end(), c.begin(), c.end());
+        T.state_amps += 2ull << n;
+        T.tickets += e.W;
+        T.parts += 2 * e.W * kMaxRun + e.W;
+        if (T.zs.size() > (size_t)INT32_MAX || T.tickets > INT32_MAX)
+            raise(QF_E_ARG, "batch too large");
+    }
+    B.nentries = (int)T.ent.size();
+    B.total_tickets = (unsigned)T.tickets;
+    B.grid = std::min<unsigned>(B.grid, B.total_tickets);
+    B.state_bytes = T.state_amps * sizeof(double2);
+}
+
+// Device layout: one contiguous region, every array 256-byte aligned.
+struct Layout {
+    size_t off[13];
+    size_t total;
+};
+
+Layout batch_layout(const qf_batch &B, const BatchHost &T)
+{
+    const size_t sizes[13] = {
+        T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
+        T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
+        (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
+        (size_t)T.parts * sizeof(double), T.ent.size() * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
+        (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double)};
+    Layout L;
+    size_t at = 0;
+    for (int i = 0; i < 13; i++) {
+        L.off[i] = at;
+        at += (sizes[i] + 255) & ~(size_t)255;
+    }
+    L.total = at;
+    return L;
+}
+
+void batch_bind(qf_batch &B, char *base, const Layout &L)
+{
+    B.d_entries = (BatchEntry *)(base + L.off[0]);
+    B.d_runs = (RunDesc *)(base + L.off[1]);
+    B.d_groups = (GroupDesc *)(base + L.off[2]);
+    B.d_z = (uint32_t *)(base + L.off[3]);
+    B.d_c = (double *)(base + L.off[4]);
+    B.d_theta = (double *)(base + L.off[5]);
+    B.d_states = (double2 *)(base + L.off[6]);
+    B.d_partials = (double *)(base + L.off[7]);
+    B.d_sync = (unsigned *)(base + L.off[8]);
+    B.d_ticket = (unsigned *)(base + L.off[9]);
+    B.d_err = (unsigned *)(base + L.off[10]);
+    B.d_E = (double *)(base + L.off[11]);
+    B.d_grad = (double *)(base + L.off[12]);
+}
+
+__global__ void k_fill_zero(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
+{
+    QF_HIP(hipMemcpyAsync(B.d_entries, T.ent.data(), T.ent.size() * sizeof(BatchEntry), hipMemcpyHostToDevice, s));
+    if (!T.runs.empty())
+        QF_HIP(hipMemcpyAsync(B.d_runs, T.runs.data(), T.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, s));
+    QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
+                          s));
+    QF_HIP(hipMemcpyAsync(B.d_z, T.zs.data(), T.zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    QF_HIP(hipMemcpyAsync(B.d_c, T.cs.data(), T.cs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    const int64_t ng = std::max<int64_t>(B.K_total, 1);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(1024, (ng + 255) / 256)), dim3(256), 0, s,
+                       B.d_grad, ng);
+    QF_HIP(hipGetLastError());
+    QF_HIP(hipStreamSynchronize(s));  // the host tables are freed on return
+}
+
+void batch_kernels(qf_batch &B, hipStream_t s)
+{
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBlock), 0, s, B.d_entries, B.nentries, B.total_tickets,
                        B.d_runs, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit);
     QF_HIP(hipGetLastError());
+}
+
+// owned mode, graph-capturable: pinned theta -> device, kernels, results -> pinned
+void batch_enqueue(qf_batch &B, hipStream_t s)
+{
+    QF_HIP(hipMemcpyAsync(B.d_theta, B.h_theta, (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+    batch_kernels(B, s);
     QF_HIP(hipMemcpyAsync(B.h_E, B.d_E, (size_t)B.count * sizeof(double), hipMemcpyDeviceToHost, s));
     QF_HIP(hipMemcpyAsync(B.h_grad, B.d_grad, (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
                           hipMemcpyDeviceToHost, s));
+}
+
+int check_err(qf_batch &B)
+{
+    unsigned err = 0;
+    QF_HIP(hipMemcpy(&err, B.d_err, sizeof err, hipMemcpyDeviceToHost));
+    if (err)
+        return fail(QF_E_HIP, "qf_batch: a team barrier timed out (spin limit %u polls)", B.spin_limit);
+    return QF_OK;
 }
 
 } // namespace qf
@@ -465,115 +645,63 @@ extern "C" int qf_batch_create(int count, const int *n_qubits, const uint64_t *o
         if (!out)
             return fail(QF_E_ARG, "qf_batch_create: out is NULL");
         *out = nullptr;
-        if (count < 1 || !n_qubits || !occ_mask || !K || !A || !H || !group_off || !n_groups)
-            return fail(QF_E_ARG, "qf_batch_create: null array or count < 1");
         qf_batch *B = new qf_batch();
         try {
-            B->count = count;
-            std::vector<int> order((size_t)count);
-            std::iota(order.begin(), order.end(), 0);
-            B->K.resize((size_t)count);
-            B->koff.resize((size_t)count + 1);
-            B->W.resize((size_t)count);
-            B->nq.resize((size_t)count);
-            B->koff[0] = 0;
-            for (int i = 0; i < count; i++) {
-                const int n = n_qubits[i];
-                if (n < 1 || n > 30)
-                    raise(QF_E_RANGE, "instance " + std::to_string(i) + ": n_qubits out of range [1, 30]");
-                if (occ_mask[i] >> n)
-                    raise(QF_E_RANGE, "instance " + std::to_string(i) + ": occ_mask has a bit >= n_qubits");
-                if (K[i] < 0 || n_groups[i] < 1 || (K[i] > 0 && !A[i]) || !H[i] || !group_off[i])
-                    raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad ansatz or Hamiltonian");
-                B->K[(size_t)i] = K[i];
-                B->koff[(size_t)i + 1] = B->koff[(size_t)i] + K[i];
-                B->nq[(size_t)i] = n;
-                B->W[(size_t)i] = (team && team[i] > 0) ? team[i] : default_team(n);
-            }
-            B->grid = resident_grid();
-            for (int i = 0; i < count; i++) {
-                // a team never exceeds one 1024-pair tile per member or the grid
-                const int n = n_qubits[i];
-                const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBlock * kItems));
-                B->W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B->W[(size_t)i], tiles, (int64_t)B->grid});
-            }
-            B->K_total = B->koff[(size_t)count];
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B->nq[a] > B->nq[b]; });
+            BatchHost T;
+            batch_assemble(*B, T, count, n_qubits, occ_mask, A, K, H, group_off, n_groups, team);
+            const Layout L = batch_layout(*B, T);
+            char *base = dev_alloc<char>(L.total);
+            B->owns_device = true;
+            B->d_base = base;
+            batch_bind(*B, base, L);
+            B->device_bytes = L.total;
+            batch_upload(*B, T, nullptr);
+            const size_t nk = (size_t)std::max<int64_t>(B->K_total, 1);
+            QF_HIP(hipHostMalloc((void **)&B->h_theta, nk * sizeof(double), hipHostMallocDefault));
+            QF_HIP(hipHostMalloc((void **)&B->h_grad, nk * sizeof(double), hipHostMallocDefault));
+            QF_HIP(hipHostMalloc((void **)&B->h_E, (size_t)B->count * sizeof(double), hipHostMallocDefault));
+            QF_HIP(hipEventCreateWithFlags(&B->done, hipEventDisableTiming));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+        return QF_OK;
+    });
+}
 
-            std::vector<BatchEntry> ent;
-            std::vector<RunDesc> runs;
-            std::vector<GroupDesc> groups;
-            std::vector<uint32_t> zs;
-            std::vector<double> cs;
-            uint64_t state_amps = 0;
-            int64_t tickets = 0, parts = 0;
-            for (int i : order) {
-                const int n = n_qubits[i];
-                int tab = 0;
-                std::vector<RunDesc> r;
-                if (K[i] > 0) {
-                    check_terms("batch ansatz", n, A[i], K[i]);
-                    r = make_runs(A[i], K[i], tab);
-                }
-                std::vector<GroupDesc> gd;
-                std::vector<uint32_t> z;
-                std::vector<double> c;
-                build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
-                BatchEntry e;
-                std::memset(&e, 0, sizeof e);
-                e.n = n;
-                e.W = B->W[(size_t)i];
-                e.nruns = (int32_t)r.size();
-                e.G = (int32_t)gd.size();
-                e.occ = (uint32_t)occ_mask[i];
-                e.run0 = (int32_t)runs.size();
-                e.group0 = (int32_t)groups.size();
-                e.term0 = (int32_t)zs.size();
-                e.theta0 = (int32_t)B->koff[(size_t)i];
-                e.ticket0 = (int32_t)tickets;
-                e.part0 = (int32_t)parts;
-                e.out = i;
-                e.state0 = state_amps;
-                ent.push_back(e);
-                runs.insert(runs.end(), r.begin(), r.end());
-                groups.insert(groups.end(), gd.begin(), gd.end());
-                zs.insert(zs.end(), z.begin(), z.end());
-                cs.insert(cs.end(), c.begin(), c.end());
-                state_amps += 2ull << n;
-                tickets += e.W;
-                parts += 2 * e.W * kMaxRun + e.W;
-                if (zs.size() > (size_t)INT32_MAX || tickets > INT32_MAX)
-                    raise(QF_E_ARG, "batch too large");
+extern "C" int qf_batch_create_arena(int count, const int *n_qubits, const uint64_t *occ_mask,
+                                     const qf_term *const *A, const int64_t *K, const qf_term *const *H,
+                                     const int64_t *const *group_off, const int64_t *n_groups, const int *team,
+                                     void *arena, int64_t arena_bytes, int64_t *need_bytes, void *stream,
+                                     qf_batch **out)
+{
+    return guarded([&]() -> int {
+        if (out)
+            *out = nullptr;
+        qf_batch *B = new qf_batch();
+        try {
+            BatchHost T;
+            batch_assemble(*B, T, count, n_qubits, occ_mask, A, K, H, group_off, n_groups, team);
+            const Layout L = batch_layout(*B, T);
+            if (need_bytes)
+                *need_bytes = (int64_t)L.total;
+            if (!arena) {
+                delete B;
+                return QF_OK;
             }
-            B->nentries = (int)ent.size();
-            B->total_tickets = (unsigned)tickets;
-            B->grid = std::min<unsigned>(B->grid, B->total_tickets);
-            B->state_bytes = state_amps * sizeof(double2);
-            B->d_entries = dev_alloc<BatchEntry>(ent.size());
-            B->d_runs = dev_alloc<RunDesc>(runs.size());
-            B->d_groups = dev_alloc<GroupDesc>(groups.size());
-            B->d_z = dev_alloc<uint32_t>(zs.size());
-            B->d_c = dev_alloc<double>(cs.size());
-            B->d_theta = dev_alloc<double>((size_t)std::max<int64_t>(B->K_total, 1));
-            B->d_grad = dev_alloc<double>((size_t)std::max<int64_t>(B->K_total, 1));
-            B->d_states = dev_alloc<double2>((size_t)state_amps);
-            B->d_partials = dev_alloc<double>((size_t)parts);
-            B->d_sync = dev_alloc<unsigned>(ent.size());
-            B->d_ticket = dev_alloc<unsigned>(1);
-            B->d_err = dev_alloc<unsigned>(1);
-            B->d_E = dev_alloc<double>((size_t)count);
-            QF_HIP(hipMemcpy(B->d_entries, ent.data(), ent.size() * sizeof(BatchEntry), hipMemcpyHostToDevice));
-            if (!runs.empty())
-                QF_HIP(hipMemcpy(B->d_runs, runs.data(), runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice));
-            QF_HIP(hipMemcpy(B->d_groups, groups.data(), groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
-            QF_HIP(hipMemcpy(B->d_z, zs.data(), zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-            QF_HIP(hipMemcpy(B->d_c, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
-            QF_HIP(hipMemset(B->d_grad, 0, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double)));
-            QF_HIP(hipHostMalloc((void **)&B->h_theta, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double),
-                                 hipHostMallocDefault));
-            QF_HIP(hipHostMalloc((void **)&B->h_grad, (size_t)std::max<int64_t>(B->K_total, 1) * sizeof(double),
-                                 hipHostMallocDefault));
-            QF_HIP(hipHostMalloc((void **)&B->h_E, (size_t)count * sizeof(double), hipHostMallocDefault));
+            if (!out)
+                raise(QF_E_ARG, "qf_batch_create_arena: out is NULL");
+            if ((uintptr_t)arena % 256)
+                raise(QF_E_ARG, "qf_batch_create_arena: arena must be 256-byte aligned");
+            if (arena_bytes < (int64_t)L.total)
+                raise(QF_E_SIZE, "qf_batch_create_arena: arena of " + std::to_string(arena_bytes) +
+                                     " bytes, need " + std::to_string(L.total));
+            B->owns_device = false;
+            batch_bind(*B, (char *)arena, L);
+            B->device_bytes = L.total;
+            batch_upload(*B, T, (hipStream_t)stream);
+            QF_HIP(hipEventCreateWithFlags(&B->done, hipEventDisableTiming));
         } catch (...) {
             delete B;
             throw;
@@ -608,13 +736,55 @@ extern "C" int qf_batch_set_spin_limit(qf_batch *b, uint32_t polls)
     if (!b || polls == 0)
         return fail(QF_E_ARG, "qf_batch_set_spin_limit: bad arguments");
     b->spin_limit = polls;
-    if (b->exec) {  // the captured launch holds the old limit
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-    }
+    b->drop_graph();  // a captured launch holds the old limit
     return QF_OK;
+}
+
+extern "C" int qf_batch_launch(qf_batch *B, const double *theta, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!B || (B->K_total > 0 && !theta))
+            return fail(QF_E_ARG, "qf_batch_launch: null argument");
+        hipStream_t s = (hipStream_t)stream;
+        const size_t nk = (size_t)std::max<int64_t>(B->K_total, 1);
+        B->theta_host.assign(nk, 0.0);
+        if (B->K_total > 0)
+            std::memcpy(B->theta_host.data(), theta, (size_t)B->K_total * sizeof(double));
+        QF_HIP(hipMemcpyAsync(B->d_theta, B->theta_host.data(), nk * sizeof(double), hipMemcpyHostToDevice, s));
+        batch_kernels(*B, s);
+        QF_HIP(hipEventRecord(B->done, s));
+        B->launched = true;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_batch_poll(qf_batch *B)
+{
+    if (!B || !B->launched)
+        return fail(QF_E_ARG, "qf_batch_poll: nothing launched");
+    const hipError_t e = hipEventQuery(B->done);
+    if (e == hipSuccess)
+        return QF_OK;
+    if (e == hipErrorNotReady)
+        return 1;
+    return fail(QF_E_HIP, "qf_batch_poll: %s", hipGetErrorString(e));
+}
+
+extern "C" int qf_batch_collect(qf_batch *B, double *E_out, double *dE_dtheta)
+{
+    return guarded([&]() -> int {
+        if (!B || !B->launched || !E_out)
+            return fail(QF_E_ARG, "qf_batch_collect: nothing launched or E_out is NULL");
+        QF_HIP(hipEventSynchronize(B->done));
+        B->launched = false;
+        const int st = check_err(*B);
+        if (st != QF_OK)
+            return st;
+        QF_HIP(hipMemcpy(E_out, B->d_E, (size_t)B->count * sizeof(double), hipMemcpyDeviceToHost));
+        if (dE_dtheta && B->K_total > 0)
+            QF_HIP(hipMemcpy(dE_dtheta, B->d_grad, (size_t)B->K_total * sizeof(double), hipMemcpyDeviceToHost));
+        return QF_OK;
+    });
 }
 
 extern "C" int qf_batch_run(qf_batch *B, const double *theta, double *E_out, double *dE_dtheta, int use_graph,
@@ -623,16 +793,16 @@ extern "C" int qf_batch_run(qf_batch *B, const double *theta, double *E_out, dou
     return guarded([&]() -> int {
         if (!B || !E_out || (B->K_total > 0 && !theta))
             return fail(QF_E_ARG, "qf_batch_run: null argument");
+        if (!B->owns_device) {
+            int st = qf_batch_launch(B, theta, stream);
+            return st != QF_OK ? st : qf_batch_collect(B, E_out, dE_dtheta);
+        }
         hipStream_t s = (hipStream_t)stream;
         if (B->K_total > 0)
             std::memcpy(B->h_theta, theta, (size_t)B->K_total * sizeof(double));
         if (use_graph) {
-            if (B->exec && B->graph_stream != s) {
-                (void)hipGraphExecDestroy(B->exec);
-                (void)hipGraphDestroy(B->graph);
-                B->exec = nullptr;
-                B->graph = nullptr;
-            }
+            if (B->exec && B->graph_stream != s)
+                B->drop_graph();
             if (!B->exec) {
                 hipStream_t cs = s;
                 bool own = false;
@@ -663,10 +833,9 @@ extern "C" int qf_batch_run(qf_batch *B, const double *theta, double *E_out, dou
             batch_enqueue(*B, s);
         }
         QF_HIP(hipStreamSynchronize(s));
-        unsigned err = 0;
-        QF_HIP(hipMemcpy(&err, B->d_err, sizeof err, hipMemcpyDeviceToHost));
-        if (err)
-            return fail(QF_E_HIP, "qf_batch_run: a team barrier timed out (spin limit %u polls)", B->spin_limit);
+        const int st = check_err(*B);
+        if (st != QF_OK)
+            return st;
         std::memcpy(E_out, B->h_E, (size_t)B->count * sizeof(double));
         if (dE_dtheta && B->K_total > 0)
             std::memcpy(dE_dtheta, B->h_grad, (size_t)B->K_total * sizeof(double));

@@ -1,0 +1,261 @@
+"""Serving loop: continuous batching of energy + gradient requests.
+
+Requests (an instance: qubit count, reference, ansatz strings, grouped
+Hamiltonian, angles) arrive over time.  The server keeps one device arena
+allocated for its lifetime and never allocates or frees device memory while
+serving (hipFree would synchronize the device).  Scheduling:
+
+* admission: requests wait FIFO; the head of the queue is admitted when its
+  device footprint (tables + two states, exact size from
+  qf_batch_create_arena's size query) fits a free range of the arena;
+* continuous batching: whenever one of `slots` launch slots (one HIP stream
+  each) is idle, everything admissible in the queue (up to `max_wave`
+  requests) becomes one wave, a persistent batched launch on that slot's
+  stream.  Waves on different slots overlap on the device: a new wave's
+  workgroups start on compute units as soon as they are free;
+* completion: slots are polled; a finished wave's results are collected and
+  its arena range is returned to the free list.
+
+Latency is measured from a request's arrival to the collection of its wave.
+The plain path (`serve_plain`) runs the same trace one request at a time
+with per-request plans and the single-instance kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import api
+from ._lib import check, lib, ptr, stream_handle
+
+ALIGN = 256
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float
+    n: int
+    occ: int
+    A: np.ndarray
+    H: np.ndarray
+    off: np.ndarray
+    theta: np.ndarray
+    E: float | None = None
+    grad: np.ndarray | None = None
+    t_admit: float | None = None
+    t_done: float | None = None
+    footprint: int = 0
+
+
+class RangeAllocator:
+    """First-fit allocator of 256-byte aligned ranges in [0, nbytes)."""
+
+    def __init__(self, nbytes: int):
+        self.nbytes = (int(nbytes) // ALIGN) * ALIGN
+        self.free = [(0, self.nbytes)]  # sorted, coalesced (offset, size)
+
+    def alloc(self, size: int):
+        size = (int(size) + ALIGN - 1) // ALIGN * ALIGN
+        for i, (o, s) in enumerate(self.free):
+            if s >= size:
+                if s == size:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (o + size, s - size)
+                return o, size
+        return None
+
+    def release(self, off: int, size: int):
+        self.free.append((off, size))
+        self.free.sort()
+        merged = []
+        for o, s in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + s)
+            else:
+                merged.append((o, s))
+        self.free = merged
+
+    def largest(self) -> int:
+        return max((s for _, s in self.free), default=0)
+
+
+class Arena(RangeAllocator):
+    """A RangeAllocator over one device buffer held for the server's lifetime."""
+
+    def __init__(self, nbytes: int):
+        import torch
+        super().__init__(nbytes)
+        self.buf = torch.empty(self.nbytes + ALIGN, dtype=torch.uint8, device="cuda")
+        self.base = (self.buf.data_ptr() + ALIGN - 1) // ALIGN * ALIGN
+
+
+def _arrays(reqs, team_table):
+    c = len(reqs)
+    keep = [np.ascontiguousarray(r.off, dtype=np.int64) for r in reqs]
+    n = (ctypes.c_int * c)(*[r.n for r in reqs])
+    occ = (ctypes.c_uint64 * c)(*[r.occ for r in reqs])
+    K = (ctypes.c_int64 * c)(*[len(r.A) for r in reqs])
+    A = (ctypes.c_void_p * c)(*[ptr(r.A) for r in reqs])
+    H = (ctypes.c_void_p * c)(*[ptr(r.H) for r in reqs])
+    O = (ctypes.c_void_p * c)(*[ptr(o) for o in keep])
+    G = (ctypes.c_int64 * c)(*[len(o) - 1 for o in keep])
+    T = (ctypes.c_int * c)(*[int(team_table.get(r.n, 0)) if team_table else 0 for r in reqs])
+    return (c, n, occ, A, K, H, O, G, T), keep
+
+
+def footprint(reqs, team_table=None) -> int:
+    """Exact arena bytes a wave of these requests needs."""
+    args, keep = _arrays(reqs, team_table)
+    need = ctypes.c_int64()
+    check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "qf_batch_create_arena(size)")
+    return need.value
+
+
+@dataclass
+class Wave:
+    reqs: list
+    handle: ctypes.c_void_p
+    slot: int
+    arena_range: tuple
+    t_launch: float
+    keep: list = field(default_factory=list)
+
+
+class Server:
+    def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None):
+        import torch
+        if team_table is None:
+            from .autotune import device_arch, load_table
+            team_table = load_table(device_arch()) or {}
+        self.team = team_table
+        self.arena = Arena(arena_bytes)
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.busy = [None] * slots
+        self.max_wave = max_wave
+        self.waves = 0
+        self.wave_sizes = []
+        self.max_busy = 0  # most waves in flight at once (overlap on the device)
+
+    def _launch(self, reqs, slot, now):
+        args, keep = _arrays(reqs, self.team)
+        need = ctypes.c_int64()
+        check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "arena size")
+        rng = self.arena.alloc(need.value)
+        if rng is None:
+            return None
+        h = ctypes.c_void_p()
+        st = stream_handle(self.streams[slot])
+        check(lib.qf_batch_create_arena(*args, ctypes.c_void_p(self.arena.base + rng[0]), rng[1],
+                                        ctypes.byref(need), st, ctypes.byref(h)), "qf_batch_create_arena")
+        theta = np.ascontiguousarray(np.concatenate([r.theta for r in reqs]), dtype=np.float64)
+        keep.append(theta)
+        check(lib.qf_batch_launch(h, ptr(theta), st), "qf_batch_launch")
+        for r in reqs:
+            r.t_admit = now
+        self.waves += 1
+        self.wave_sizes.append(len(reqs))
+        return Wave(reqs, h, slot, rng, now, keep)
+
+    def _finish(self, w: Wave, now):
+        E = np.zeros(len(w.reqs))
+        g = np.zeros(max(1, sum(len(r.A) for r in w.reqs)))
+        check(lib.qf_batch_collect(w.handle, ptr(E), ptr(g)), "qf_batch_collect")
+        lib.qf_batch_destroy(w.handle)
+        o = 0
+        for r, e in zip(w.reqs, E):
+            r.E = float(e)
+            r.grad = g[o:o + len(r.A)].copy()
+            o += len(r.A)
+            r.t_done = now
+        self.arena.release(*w.arena_range)
+
+    def serve(self, requests, poll_s: float = 50e-6):
+        """Replay `requests` (sorted by arrival, seconds from start).  Returns stats."""
+        for r in requests:
+            r.footprint = r.footprint or footprint([r], self.team)
+            if r.footprint > self.arena.nbytes:
+                raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena has {self.arena.nbytes}")
+        pending = []
+        nxt = 0
+        done = 0
+        t0 = time.perf_counter()
+        while done < len(requests):
+            now = time.perf_counter() - t0
+            while nxt < len(requests) and requests[nxt].arrival <= now:
+                pending.append(requests[nxt])
+                nxt += 1
+            for s, w in enumerate(self.busy):
+                if w is not None and lib.qf_batch_poll(w.handle) == 0:
+                    self._finish(w, time.perf_counter() - t0)
+                    self.busy[s] = None
+                    done += len(w.reqs)
+            for s in range(len(self.busy)):
+                if self.busy[s] is not None or not pending:
+                    continue
+                # FIFO admission by footprint: the head must fit before anything behind it
+                wave, budget = [], self.arena.largest()
+                for r in pending[:self.max_wave]:
+                    if r.footprint > budget:
+                        break
+                    wave.append(r)
+                    budget -= r.footprint
+                if not wave:
+                    break
+                w = self._launch(wave, s, time.perf_counter() - t0)
+                if w is None:
+                    break
+                self.busy[s] = w
+                pending = pending[len(wave):]
+                self.max_busy = max(self.max_busy, sum(b is not None for b in self.busy))
+            if nxt < len(requests) and not pending and all(b is None for b in self.busy):
+                time.sleep(max(0.0, min(requests[nxt].arrival - (time.perf_counter() - t0), 1e-3)))
+            else:
+                time.sleep(poll_s)
+        out = stats(requests, self.waves, self.wave_sizes)
+        out["max_waves_in_flight"] = self.max_busy
+        return out
+
+
+def serve_plain(requests, max_qubits: int):
+    """One request at a time, FIFO, single-instance kernels (qf_plan_*)."""
+    import torch
+    ws = torch.empty(2 << max_qubits, dtype=torch.complex128, device="cuda")
+    t0 = time.perf_counter()
+    for r in requests:
+        now = time.perf_counter() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        r.t_admit = time.perf_counter() - t0
+        plan = api.Plan(r.n, r.A, r.H, r.off)
+        r.E, r.grad = plan.energy_grad(r.occ, r.theta, ws)
+        plan.close()
+        r.t_done = time.perf_counter() - t0
+    return stats(requests, len(requests), [1] * len(requests))
+
+
+def stats(requests, waves, wave_sizes):
+    lat = np.array([r.t_done - r.arrival for r in requests])
+    span = max(r.t_done for r in requests) - min(r.arrival for r in requests)
+    return {"requests": len(requests), "throughput_req_per_s": len(requests) / span,
+            "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
+            "latency_ms_max": float(lat.max() * 1e3), "makespan_s": span, "waves": waves,
+            "mean_wave_size": float(np.mean(wave_sizes)) if wave_sizes else 0.0}
+
+
+def make_requests(qf, qi, trace):
+    """Requests for (arrival, recipe) pairs; tables are built on the host
+    before the replay (a request carries its tables)."""
+    out = []
+    for j, (t, rcp) in enumerate(trace):
+        h, g = qi.integrals(rcp["n_orb"], rcp["n_elec"], rcp["seed"])
+        H, off, _ = qf.build_paulis("hamiltonian", rcp["n_orb"], rcp["n_elec"], h, g)
+        A, aoff, _ = qf.build_paulis("uccsd", rcp["n_orb"], rcp["n_elec"])
+        theta = qf.ansatz_angles(A, aoff, qi.amplitudes(len(aoff) - 1, rcp["seed"], rcp["t_scale"]))
+        out.append(Request(j, float(t), 2 * rcp["n_orb"], (1 << rcp["n_elec"]) - 1, A, H, off, theta))
+    return out

@@ -1,0 +1,75 @@
+"""Serving loop on the GPU: continuous batching gives the same result for a
+request alone and in the mix (bitwise for the batched kernel with the same
+team size), within tolerance of the oracle and of the plain serial path."""
+import numpy as np
+import pytest
+
+import qf_inputs as qi
+from oracle import core
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def qf():
+    assert torch.cuda.is_available()
+    import paper_2108_04413_amd as qf
+    return qf
+
+
+def trace(n_req, gap_s, qubits, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_req):
+        nq = int(rng.choice(qubits))
+        out.append((j * gap_s, dict(n_orb=nq // 2, n_elec=nq // 2, seed=5000 + j, t_scale=0.1)))
+    return out
+
+
+def alone(qf, r, team):
+    B = qf.Batch([dict(n=r.n, occ=r.occ, A=r.A, H=r.H, off=r.off)], team=[team])
+    E, g = B.run([r.theta], use_graph=False)
+    B.close()
+    return E[0], g[0]
+
+
+def test_serve_mix_equals_alone_oracle_and_plain(qf):
+    from paper_2108_04413_amd import serve
+    reqs = serve.make_requests(qf, qi, trace(24, 2e-4, (8, 10, 12, 14, 16)))
+    srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=6)
+    st = srv.serve(reqs)
+    assert st["requests"] == 24 and st["waves"] >= 4
+    assert st["max_waves_in_flight"] == 2
+    for r in reqs:
+        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        assert e == r.E and np.array_equal(g, r.grad)
+    for r in reqs[:6]:
+        e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
+        assert r.E == pytest.approx(e_o, abs=1e-10)
+        assert np.max(np.abs(r.grad - g_o)) < 1e-9
+    plain = serve.make_requests(qf, qi, trace(24, 2e-4, (8, 10, 12, 14, 16)))
+    serve.serve_plain(plain, 16)
+    for a, b in zip(reqs, plain):
+        assert a.E == pytest.approx(b.E, abs=1e-10)
+        assert np.max(np.abs(a.grad - b.grad)) < 1e-9
+
+
+def test_serve_small_arena_admits_one_at_a_time(qf):
+    from paper_2108_04413_amd import serve
+    reqs = serve.make_requests(qf, qi, trace(6, 0.0, (16,), seed=3))
+    need = max(serve.footprint([r]) for r in reqs)
+    srv = serve.Server(arena_bytes=need + 4096, slots=2, max_wave=8)
+    st = srv.serve(reqs)
+    assert st["mean_wave_size"] == 1.0 and st["max_waves_in_flight"] == 1
+    for r in reqs:
+        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        assert e == r.E and np.array_equal(g, r.grad)
+
+
+def test_serve_rejects_request_larger_than_arena(qf):
+    from paper_2108_04413_amd import serve
+    reqs = serve.make_requests(qf, qi, trace(1, 0.0, (16,)))
+    srv = serve.Server(arena_bytes=1 << 20, slots=1)
+    with pytest.raises(ValueError):
+        srv.serve(reqs)
