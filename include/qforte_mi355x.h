@@ -224,6 +224,24 @@ int qf_batch_create_arena(int count, const int *n_qubits, const uint64_t *occ_ma
 int qf_batch_launch(qf_batch *batch, const double *theta, void *stream);
 int qf_batch_poll(qf_batch *batch);
 int qf_batch_collect(qf_batch *batch, double *E_out, double *dE_dtheta);
+
+/*
+ * Per-instance completion for serving.  A mailbox is coherent pinned host
+ * memory (qf_mailbox_alloc zeroes it; qf_mailbox_free releases it, which may
+ * synchronize the device, so servers allocate mailboxes once).
+ * qf_batch_launch_mailbox is qf_batch_launch that also makes the kernel
+ * publish each instance as soon as its team finishes: layout
+ *   double E[count]; double dE_dtheta[K_total]; uint32 flag[count]
+ * (qf_batch_mailbox_bytes gives the size); results are written first, then
+ * flag[i] = 1 with a system-scope release, so a host that reads flag[i] == 1
+ * may read E[i] and the instance's gradient.  The mailbox must stay
+ * untouched until the launch has finished (qf_batch_poll / collect).
+ */
+int qf_mailbox_alloc(int64_t bytes, void **mailbox);
+int qf_mailbox_free(void *mailbox);
+int qf_batch_mailbox_bytes(const qf_batch *batch, int64_t *bytes);
+int qf_batch_launch_mailbox(qf_batch *batch, const double *theta, void *mailbox, int64_t mailbox_bytes,
+                            void *stream);
 int qf_batch_set_spin_limit(qf_batch *batch, uint32_t polls);
 int qf_batch_destroy(qf_batch *batch);
 

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqforte_mi355x.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_04413_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2108_04413_amd/build.py`")
 
 # torch's ROCm build loads its own libamdhip64 (DT_NEEDED "libamdhip64.so",
 # SONAME "libamdhip64.so.7").  Loading torch first lets this library's
@@ -36,7 +36,8 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_energy", "qf_energy_grad", "qf_plan_create", "qf_plan_destroy", "qf_plan_apply",
            "qf_plan_energy", "qf_plan_energy_grad", "qf_plan_sigma", "qf_last_error", "qf_version",
            "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy",
-           "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect")
+           "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect",
+           "qf_mailbox_alloc", "qf_mailbox_free", "qf_batch_mailbox_bytes", "qf_batch_launch_mailbox")
 
 
 class QFError(RuntimeError):
@@ -75,6 +76,10 @@ _sig = {
     "qf_batch_launch": [_vp, _vp, _vp],
     "qf_batch_poll": [_vp],
     "qf_batch_collect": [_vp, _vp, _vp],
+    "qf_mailbox_alloc": [_i64, _vp],
+    "qf_mailbox_free": [_vp],
+    "qf_batch_mailbox_bytes": [_vp, _vp],
+    "qf_batch_launch_mailbox": [_vp, _vp, _vp, _i64, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)

@@ -1,6 +1,8 @@
 """Compile the HIP/C++ library libqforte_mi355x.so in-tree for gfx950.
 
-    python -m paper_2108_04413_amd.build
+    python paper_2108_04413_amd/build.py
+
+(run it as a script: importing the package loads the library it builds).
 
 Steps: hipcc compiles the device file (kernels + C-ABI entry points), g++
 compiles the host builder, hipcc links the shared library next to this file.

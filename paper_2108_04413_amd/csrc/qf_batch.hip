@@ -44,6 +44,8 @@ struct BatchEntry {
     int32_t ticket0; // first ticket of the team
     int32_t part0;   // partial slots: 2 * W * kMaxRun (adjoint, two buffers) + W (energy)
     int32_t out;     // caller index of the instance
+    int32_t K;       // ansatz strings of the instance
+    int32_t pad;
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
 
@@ -275,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
                                                   const double *__restrict__ theta, double2 *states,
                                                   double *partials, unsigned *sync, unsigned *ticket,
                                                   unsigned *err, double *E_out, double *grad_out,
-                                                  unsigned spin_limit)
+                                                  unsigned spin_limit, double *mb_E, double *mb_grad,
+                                                  unsigned *mb_flag)
 {
     __shared__ int s_entry, s_rank;
     __shared__ double2 s_tab[1 << kMaxRank];
@@ -357,11 +360,25 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
                 grad_out[en.theta0 + d.k0 + threadIdx.x] = 2.0 * s;
             }
         }
-        if (rank == 0 && threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < W; w++)
-                s += part[2 * W * kMaxRun + w];
-            E_out[en.out] = s;
+        if (rank == 0) {
+            if (threadIdx.x == 0) {
+                double s = 0.0;
+                for (int w = 0; w < W; w++)
+                    s += part[2 * W * kMaxRun + w];
+                E_out[en.out] = s;
+                if (mb_E)
+                    mb_E[en.out] = s;
+            }
+            if (mb_flag) {
+                // per-instance completion: results to host memory, then the flag
+                __syncthreads();
+                for (int k = threadIdx.x; k < en.K; k += kBlock)
+                    mb_grad[en.theta0 + k] = grad_out[en.theta0 + k];
+                __threadfence_system();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&mb_flag[en.out], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
         __syncthreads();
     }
@@ -404,6 +421,9 @@ struct qf_batch {
     double *h_grad = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
+    double *mb_E = nullptr;  // mailbox of the current launch (host, coherent), or null
+    double *mb_grad = nullptr;
+    unsigned *mb_flag = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -522,6 +542,7 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         e.ticket0 = (int32_t)T.tickets;
         e.part0 = (int32_t)T.parts;
         e.out = i;
+        e.K = (int32_t)K[i];
         e.state0 = T.state_amps;
         T.ent.push_back(e);
         T.runs.insert(T.runs.end(), r.begin(), r.end());
@@ -609,7 +630,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBlock), 0, s, B.d_entries, B.nentries, B.total_tickets,
                        B.d_runs, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
-                       B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit);
+                       B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }
 
@@ -738,6 +759,61 @@ extern "C" int qf_batch_set_spin_limit(qf_batch *b, uint32_t polls)
     b->spin_limit = polls;
     b->drop_graph();  // a captured launch holds the old limit
     return QF_OK;
+}
+
+extern "C" int qf_mailbox_alloc(int64_t bytes, void **out)
+{
+    return guarded([&]() -> int {
+        if (!out || bytes <= 0)
+            return fail(QF_E_ARG, "qf_mailbox_alloc: bad arguments");
+        *out = nullptr;
+        void *p = nullptr;
+        const hipError_t e = hipHostMalloc(&p, (size_t)bytes, hipHostMallocCoherent | hipHostMallocMapped);
+        if (e != hipSuccess)
+            return fail(QF_E_NOMEM, "qf_mailbox_alloc: %s", hipGetErrorString(e));
+        std::memset(p, 0, (size_t)bytes);
+        *out = p;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_mailbox_free(void *p)
+{
+    if (p)
+        (void)hipHostFree(p);
+    return QF_OK;
+}
+
+extern "C" int qf_batch_mailbox_bytes(const qf_batch *B, int64_t *bytes)
+{
+    if (!B || !bytes)
+        return fail(QF_E_ARG, "qf_batch_mailbox_bytes: null argument");
+    *bytes = 8 * (int64_t)B->count + 8 * B->K_total + 4 * (int64_t)B->count;
+    return QF_OK;
+}
+
+extern "C" int qf_batch_launch_mailbox(qf_batch *B, const double *theta, void *mailbox, int64_t mailbox_bytes,
+                                       void *stream)
+{
+    return guarded([&]() -> int {
+        if (!B)
+            return fail(QF_E_ARG, "qf_batch_launch_mailbox: batch is NULL");
+        int64_t need = 0;
+        qf_batch_mailbox_bytes(B, &need);
+        if (!mailbox || mailbox_bytes < need)
+            return fail(QF_E_SIZE, "qf_batch_launch_mailbox: mailbox of %lld bytes, need %lld",
+                        (long long)mailbox_bytes, (long long)need);
+        char *m = (char *)mailbox;
+        B->mb_E = (double *)m;
+        B->mb_grad = (double *)(m + 8 * (size_t)B->count);
+        B->mb_flag = (unsigned *)(m + 8 * (size_t)B->count + 8 * (size_t)B->K_total);
+        std::memset(B->mb_flag, 0, 4 * (size_t)B->count);
+        const int st = qf_batch_launch(B, theta, stream);
+        B->mb_E = nullptr;
+        B->mb_grad = nullptr;
+        B->mb_flag = nullptr;
+        return st;
+    });
 }
 
 extern "C" int qf_batch_launch(qf_batch *B, const double *theta, void *stream)

@@ -13,8 +13,11 @@ serving (hipFree would synchronize the device).  Scheduling:
   requests) becomes one wave, a persistent batched launch on that slot's
   stream.  Waves on different slots overlap on the device: a new wave's
   workgroups start on compute units as soon as they are free;
-* completion: slots are polled; a finished wave's results are collected and
-  its arena range is returned to the free list.
+* completion per request: each slot owns a mailbox (coherent pinned host
+  memory); the kernel publishes an instance's energy and gradient there and
+  then raises its flag as soon as that instance's team is done, so a short
+  request in a wave completes without waiting for the wave's long ones.  A
+  wave's arena range and slot are released when the whole launch finishes.
 
 Latency is measured from a request's arrival to the collection of its wave.
 The plain path (`serve_plain`) runs the same trace one request at a time
@@ -124,10 +127,20 @@ class Wave:
     arena_range: tuple
     t_launch: float
     keep: list = field(default_factory=list)
+    E: np.ndarray | None = None      # mailbox views
+    grad: np.ndarray | None = None
+    flag: np.ndarray | None = None
+    koff: list = field(default_factory=list)
+    open: int = 0                    # requests not yet published
+
+
+def _view(addr: int, ctype, count: int) -> np.ndarray:
+    return np.ctypeslib.as_array(ctypes.cast(ctypes.c_void_p(addr), ctypes.POINTER(ctype)), shape=(count,))
 
 
 class Server:
-    def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None):
+    def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None,
+                 mailbox_bytes: int = 32 << 20):
         import torch
         if team_table is None:
             from .autotune import device_arch, load_table
@@ -137,9 +150,24 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.busy = [None] * slots
         self.max_wave = max_wave
+        self.mb_bytes = int(mailbox_bytes)
+        self.mailbox = []
+        for _ in range(slots):
+            m = ctypes.c_void_p()
+            check(lib.qf_mailbox_alloc(self.mb_bytes, ctypes.byref(m)), "qf_mailbox_alloc")
+            self.mailbox.append(m)
         self.waves = 0
         self.wave_sizes = []
         self.max_busy = 0  # most waves in flight at once (overlap on the device)
+
+    def close(self):
+        for m in self.mailbox:
+            lib.qf_mailbox_free(m)
+        self.mailbox = []
+
+    def __del__(self):
+        if getattr(self, "mailbox", None):
+            self.close()
 
     def _launch(self, reqs, slot, now):
         args, keep = _arrays(reqs, self.team)
@@ -154,24 +182,36 @@ class Server:
                                         ctypes.byref(need), st, ctypes.byref(h)), "qf_batch_create_arena")
         theta = np.ascontiguousarray(np.concatenate([r.theta for r in reqs]), dtype=np.float64)
         keep.append(theta)
-        check(lib.qf_batch_launch(h, ptr(theta), st), "qf_batch_launch")
+        mb = self.mailbox[slot].value
+        check(lib.qf_batch_launch_mailbox(h, ptr(theta), ctypes.c_void_p(mb), self.mb_bytes, st),
+              "qf_batch_launch_mailbox")
         for r in reqs:
             r.t_admit = now
         self.waves += 1
         self.wave_sizes.append(len(reqs))
-        return Wave(reqs, h, slot, rng, now, keep)
+        c, kt = len(reqs), sum(len(r.A) for r in reqs)
+        koff = np.concatenate([[0], np.cumsum([len(r.A) for r in reqs])]).tolist()
+        return Wave(reqs, h, slot, rng, now, keep, E=_view(mb, ctypes.c_double, c),
+                    grad=_view(mb + 8 * c, ctypes.c_double, max(kt, 1)),
+                    flag=_view(mb + 8 * c + 8 * kt, ctypes.c_uint32, c), koff=koff, open=c)
+
+    def _publish(self, w: Wave, now):
+        """Complete every request of w whose mailbox flag is up."""
+        for i, r in enumerate(w.reqs):
+            if r.t_done is None and w.flag[i] == 1:
+                r.E = float(w.E[i])
+                r.grad = w.grad[w.koff[i]:w.koff[i + 1]].copy()
+                r.t_done = now
+                w.open -= 1
 
     def _finish(self, w: Wave, now):
         E = np.zeros(len(w.reqs))
         g = np.zeros(max(1, sum(len(r.A) for r in w.reqs)))
         check(lib.qf_batch_collect(w.handle, ptr(E), ptr(g)), "qf_batch_collect")
         lib.qf_batch_destroy(w.handle)
-        o = 0
-        for r, e in zip(w.reqs, E):
-            r.E = float(e)
-            r.grad = g[o:o + len(r.A)].copy()
-            o += len(r.A)
-            r.t_done = now
+        self._publish(w, now)
+        if w.open:
+            raise RuntimeError("a finished wave left requests unpublished")
         self.arena.release(*w.arena_range)
 
     def serve(self, requests, poll_s: float = 50e-6):
@@ -190,20 +230,28 @@ class Server:
                 pending.append(requests[nxt])
                 nxt += 1
             for s, w in enumerate(self.busy):
-                if w is not None and lib.qf_batch_poll(w.handle) == 0:
+                if w is None:
+                    continue
+                before = w.open
+                self._publish(w, time.perf_counter() - t0)
+                done += before - w.open
+                if lib.qf_batch_poll(w.handle) == 0:
+                    before = w.open
                     self._finish(w, time.perf_counter() - t0)
+                    done += before
                     self.busy[s] = None
-                    done += len(w.reqs)
             for s in range(len(self.busy)):
                 if self.busy[s] is not None or not pending:
                     continue
                 # FIFO admission by footprint: the head must fit before anything behind it
-                wave, budget = [], self.arena.largest()
+                wave, budget, mb = [], self.arena.largest(), 0
                 for r in pending[:self.max_wave]:
-                    if r.footprint > budget:
+                    mb_r = 12 + 8 * len(r.A)
+                    if r.footprint > budget or mb + mb_r > self.mb_bytes:
                         break
                     wave.append(r)
                     budget -= r.footprint
+                    mb += mb_r
                 if not wave:
                     break
                 w = self._launch(wave, s, time.perf_counter() - t0)

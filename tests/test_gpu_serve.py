@@ -73,3 +73,20 @@ def test_serve_rejects_request_larger_than_arena(qf):
     srv = serve.Server(arena_bytes=1 << 20, slots=1)
     with pytest.raises(ValueError):
         srv.serve(reqs)
+
+
+def test_short_requests_complete_before_long_ones_in_a_wave(qf):
+    """Mailbox completion: a request is published when its own team is done."""
+    from paper_2108_04413_amd import serve
+    tr = [(0.0, dict(n_orb=10, n_elec=10, seed=6000, t_scale=0.1))] + \
+         [(0.0, dict(n_orb=5, n_elec=5, seed=6001 + j, t_scale=0.1)) for j in range(6)]
+    reqs = serve.make_requests(qf, qi, tr)
+    srv = serve.Server(arena_bytes=1 << 30, slots=1, max_wave=16)
+    st = srv.serve(reqs)
+    assert st["waves"] == 1
+    big, small = reqs[0], reqs[1:]
+    assert max(r.t_done for r in small) < big.t_done
+    for r in reqs:
+        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        assert e == r.E and np.array_equal(g, r.grad)
+    srv.close()
