@@ -164,6 +164,21 @@ int qf_plan_energy(qf_plan *plan, const void *psi, double *E_out, void *stream);
 /* as qf_energy_grad with the plan's ansatz and Hamiltonian */
 int qf_plan_energy_grad(qf_plan *plan, uint64_t occ_mask, const double *theta, void *workspace,
                         double *E_out, double *dE_dtheta, void *stream);
+/*
+ * Energy kernel of a plan.  tile_bits = 0: one pass over the state per
+ * flip-mask group.  tile_bits = L in {10, 11, 12}: groups whose flip masks
+ * agree above bit L form a class; one pass per class visits pairs of tiles
+ * of 2^L amplitudes (t, t ^ x_high) with the partner tile staged in LDS and
+ * evaluates every group of the class, so the state is read once per class.
+ * merged != 0 additionally folds each string's sign from the bits above the
+ * tile into a per-tile coefficient, so strings of a group that agree below
+ * bit L are evaluated once.  Plans with n_qubits >= 16 default to L = 11,
+ * merged.  Needs n_qubits > L.
+ */
+int qf_plan_set_energy_tile(qf_plan *plan, int tile_bits, int merged);
+/* tile bits (negative when merged), number of classes, passes over the
+ * state per energy evaluation */
+int qf_plan_info(const qf_plan *plan, int *tile_bits, int64_t *classes, int64_t *energy_passes);
 /* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out) */
 int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
 

@@ -104,13 +104,25 @@ class Plan:
               "qf_plan_create")
         self._h = h
 
-    def close(self):
+    def close(self, _destroy=lib.qf_plan_destroy):
         if getattr(self, "_h", None):
-            lib.qf_plan_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):
         self.close()
+
+    def set_energy_tile(self, tile_bits: int, merged: bool = True) -> None:
+        """0: one pass per flip-mask group; 10-12: tiled passes per class
+        (merged: strings sharing their low Z bits evaluated once per tile)."""
+        check(lib.qf_plan_set_energy_tile(self._h, int(tile_bits), int(merged)), "qf_plan_set_energy_tile")
+
+    def info(self) -> dict:
+        tb = ctypes.c_int()
+        cl = ctypes.c_int64()
+        ps = ctypes.c_int64()
+        check(lib.qf_plan_info(self._h, ctypes.byref(tb), ctypes.byref(cl), ctypes.byref(ps)), "qf_plan_info")
+        return {"tile_bits": tb.value, "classes": cl.value, "energy_passes": ps.value}
 
     def apply(self, psi, theta, inverse: bool = False, stream=None) -> None:
         theta = _f64(theta)
@@ -170,9 +182,9 @@ class Batch:
         self._h = h
         self.koff = np.concatenate([[0], np.cumsum(self.K)]).astype(np.int64)
 
-    def close(self):
+    def close(self, _destroy=lib.qf_batch_destroy):
         if getattr(self, "_h", None):
-            lib.qf_batch_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -210,6 +210,288 @@ __global__ __launch_bounds__(kBlock) void k_energy(const double2 *__restrict__ p
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
+// Tiled energy: tiles of 2^LT amplitudes; a work item is (class c, tile t1)
+// with partner tile t2 = t1 ^ xh_c.  The partner tile is staged in LDS and
+// every group of the class is evaluated on the item, so the state is read
+// once per class instead of once per group.  For xh != 0 the own tile has
+// bit hb of its index clear and each pair (y in t1, y ^ x in t2) counts twice
+// (2 Re); for xh == 0 the partner of y is in the same tile and the sum runs
+// over every y with weight 1 (sum_y conj(psi[y^x]) D(y) psi[y] = <P_g>).
+template <int LT>
+__global__ __launch_bounds__(kBlock) void k_energy_tiled(const double2 *__restrict__ psi,
+                                                         const ClassDesc *__restrict__ classes,
+                                                         const uint64_t *__restrict__ work_off,
+                                                         uint64_t total_work,
+                                                         const GroupDesc *__restrict__ groups,
+                                                         const uint32_t *__restrict__ zs,
+                                                         const double *__restrict__ cs, double *partials,
+                                                         unsigned *counter, double *result)
+{
+    constexpr uint32_t T = 1u << LT;
+    constexpr int kChunk = kBlock * kItems;
+    __shared__ double2 tile[T];
+    double acc = 0.0;
+    int c = 0;
+    for (uint64_t w = blockIdx.x; w < total_work; w += gridDim.x) {
+        while (w >= work_off[c + 1])
+            c++;
+        const ClassDesc cd = classes[c];
+        const uint32_t j = (uint32_t)(w - work_off[c]);
+        const uint32_t t1 = cd.xh ? insert0(j, cd.hb) : j;
+        const uint32_t t2 = t1 ^ cd.xh;
+        const double wt = cd.xh ? 2.0 : 1.0;
+        __syncthreads();  // the previous item's LDS reads are done
+        const double2 *src = psi + ((size_t)t2 << LT);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < T; i += kBlock)
+            tile[i] = src[i];
+        __syncthreads();
+        const double2 *own = psi + ((size_t)t1 << LT);
+        for (uint32_t base = 0; base < T; base += kChunk) {
+            uint32_t ylo[kItems], y[kItems];
+            double2 a[kItems];
+#pragma unroll
+            for (int i = 0; i < kItems; i++) {
+                ylo[i] = base + threadIdx.x + (uint32_t)i * kBlock;
+                y[i] = (t1 << LT) | ylo[i];
+            }
+            if (cd.xh) {
+#pragma unroll
+                for (int i = 0; i < kItems; i++)
+                    a[i] = own[ylo[i]];
+            } else {
+#pragma unroll
+                for (int i = 0; i < kItems; i++)
+                    a[i] = tile[ylo[i]];
+            }
+            for (int gi = cd.g0; gi < cd.g1; gi++) {
+                const GroupDesc g = groups[gi];
+                const uint32_t xl = g.x & (T - 1u);
+                double2 b[kItems];
+#pragma unroll
+                for (int i = 0; i < kItems; i++)
+                    b[i] = tile[ylo[i] ^ xl];
+                double dre[kItems], dim[kItems];
+                group_d(g, zs, cs, y, dre, dim);
+#pragma unroll
+                for (int i = 0; i < kItems; i++) {
+                    const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
+                    const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
+                    acc += wt * (b[i].x * tr + b[i].y * ti);
+                }
+            }
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
+}
+
+// Merged tiled energy (same schedule as k_energy_tiled).  Group descriptors
+// index string records: [k0, kre) real phase, [kre, k1) imaginary phase.
+// Per work item the coefficient of a lo-term, sum_k c_k (-1)^popcount(t1 & zhi_k),
+// is uniform across the block; each own amplitude then needs one parity and
+// one FMA with +-1.0 per lo-term.  Own amplitudes are processed NI at a time.
+template <int NI>
+__device__ __forceinline__ void apply_lo_terms(const ERec *__restrict__ recs, int r0, int r1, uint32_t t1,
+                                               const uint32_t (&ylo)[NI], double (&sg)[NI], double (&d)[NI])
+{
+    if (r0 >= r1)
+        return;
+    double ce = 0.0;
+    ERec e = recs[r0];
+    for (int r = r0; r < r1; r++) {
+        const ERec en = recs[r + 1 < r1 ? r + 1 : r];  // prefetch
+        ce += flip(e.c, par(t1 & e.zhi));
+        if (e.emit) {
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                sg[i] = __hiloint2double((int)(0x3FF00000u | (__popc(ylo[i] & e.zlo) << 31)), __double2loint(sg[i]));
+                d[i] = fma(sg[i], ce, d[i]);
+            }
+            ce = 0.0;
+        }
+        e = en;
+    }
+}
+
+template <int LT, int NI>
+__global__ __launch_bounds__(kBlock) void k_energy_merged(const double2 *__restrict__ psi,
+                                                          const ClassDesc *__restrict__ classes,
+                                                          const uint64_t *__restrict__ work_off,
+                                                          uint64_t total_work,
+                                                          const GroupDesc *__restrict__ groups,
+                                                          const ERec *__restrict__ recs, double *partials,
+                                                          unsigned *counter, double *result)
+{
+    constexpr uint32_t T = 1u << LT;
+    constexpr uint32_t kChunk = (uint32_t)kBlock * NI;
+    static_assert(T % kChunk == 0, "tile must be a multiple of the chunk");
+    __shared__ double2 tile[T];
+    double acc = 0.0;
+    double sg[NI];  // +-1.0: only the high word changes
+#pragma unroll
+    for (int i = 0; i < NI; i++)
+        sg[i] = 1.0;
+    int c = 0;
+    for (uint64_t w = blockIdx.x; w < total_work; w += gridDim.x) {
+        while (w >= work_off[c + 1])
+            c++;
+        const ClassDesc cd = classes[c];
+        const uint32_t j = (uint32_t)(w - work_off[c]);
+        const uint32_t t1 = cd.xh ? insert0(j, cd.hb) : j;
+        const uint32_t t2 = t1 ^ cd.xh;
+        const double wt = cd.xh ? 2.0 : 1.0;
+        __syncthreads();
+        const double2 *src = psi + ((size_t)t2 << LT);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < T; i += kBlock)
+            tile[i] = src[i];
+        __syncthreads();
+        const double2 *own = psi + ((size_t)t1 << LT);
+        for (uint32_t base = 0; base < T; base += kChunk) {
+            uint32_t ylo[NI];
+            double2 a[NI];
+#pragma unroll
+            for (int i = 0; i < NI; i++)
+                ylo[i] = base + threadIdx.x + (uint32_t)i * kBlock;
+            if (cd.xh) {  // uniform branch: global loads, or LDS when the pair is in one tile
+#pragma unroll
+                for (int i = 0; i < NI; i++)
+                    a[i] = own[ylo[i]];
+            } else {
+#pragma unroll
+                for (int i = 0; i < NI; i++)
+                    a[i] = tile[ylo[i]];
+            }
+            for (int gi = cd.g0; gi < cd.g1; gi++) {
+                const GroupDesc g = groups[gi];
+                const uint32_t xl = g.x & (T - 1u);
+                double2 b[NI];
+#pragma unroll
+                for (int i = 0; i < NI; i++)
+                    b[i] = tile[ylo[i] ^ xl];
+                double dre[NI], dim[NI];
+#pragma unroll
+                for (int i = 0; i < NI; i++) {
+                    dre[i] = 0.0;
+                    dim[i] = 0.0;
+                }
+                apply_lo_terms<NI>(recs, g.k0, g.kre, t1, ylo, sg, dre);
+                apply_lo_terms<NI>(recs, g.kre, g.k1, t1, ylo, sg, dim);
+#pragma unroll
+                for (int i = 0; i < NI; i++) {
+                    const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
+                    const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
+                    acc += wt * (b[i].x * tr + b[i].y * ti);
+                }
+            }
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
+}
+
+// Pipelined merged tiled energy for tiles of 2^11 amplitudes (8 per thread):
+// while a work item is evaluated from LDS and registers, the loads of the
+// next item's partner tile and own amplitudes are already in flight.  With
+// IMAG == false every string has real phase (real Hamiltonians), and the
+// imaginary accumulators are dropped.
+template <bool IMAG>
+__global__ __launch_bounds__(kBlock) void k_energy_pipe(const double2 *__restrict__ psi,
+                                                        const ClassDesc *__restrict__ classes,
+                                                        const uint64_t *__restrict__ work_off,
+                                                        uint64_t total_work,
+                                                        const GroupDesc *__restrict__ groups,
+                                                        const ERec *__restrict__ recs, double *partials,
+                                                        unsigned *counter, double *result)
+{
+    constexpr int LT = 11;
+    constexpr int NI = 8;
+    constexpr uint32_t T = 1u << LT;
+    static_assert(T == (uint32_t)kBlock * NI, "one tile per block pass");
+    __shared__ double2 tile[T];
+    double acc = 0.0;
+    double sg[NI];
+#pragma unroll
+    for (int i = 0; i < NI; i++)
+        sg[i] = 1.0;
+    uint32_t ylo[NI];
+#pragma unroll
+    for (int i = 0; i < NI; i++)
+        ylo[i] = threadIdx.x + (uint32_t)i * kBlock;
+
+    // next item's data, loaded one iteration ahead
+    double2 pn[NI], on[NI];
+    int c = 0;
+    uint32_t t1n = 0;
+    bool xhn = false;
+    uint64_t w = blockIdx.x;
+    auto fetch = [&](uint64_t wi) {
+        while (wi >= work_off[c + 1])
+            c++;
+        const ClassDesc cd = classes[c];
+        const uint32_t j = (uint32_t)(wi - work_off[c]);
+        const uint32_t t1 = cd.xh ? insert0(j, cd.hb) : j;
+        const double2 *p2 = psi + ((size_t)(t1 ^ cd.xh) << LT);
+        const double2 *p1 = psi + ((size_t)t1 << LT);
+#pragma unroll
+        for (int i = 0; i < NI; i++)
+            pn[i] = p2[ylo[i]];
+        if (cd.xh) {
+#pragma unroll
+            for (int i = 0; i < NI; i++)
+                on[i] = p1[ylo[i]];
+        }
+        t1n = t1;
+        xhn = cd.xh != 0;
+    };
+    if (w < total_work)
+        fetch(w);
+    for (; w < total_work; w += gridDim.x) {
+        const int cc = c;
+        const uint32_t t1 = t1n;
+        const bool xh = xhn;
+        const double wt = xh ? 2.0 : 1.0;
+        double2 a[NI];
+        __syncthreads();  // the previous item's LDS reads are done
+#pragma unroll
+        for (int i = 0; i < NI; i++) {
+            tile[ylo[i]] = pn[i];
+            a[i] = xh ? on[i] : pn[i];
+        }
+        __syncthreads();
+        const ClassDesc cd = classes[cc];
+        if (w + gridDim.x < total_work)
+            fetch(w + gridDim.x);
+        for (int gi = cd.g0; gi < cd.g1; gi++) {
+            const GroupDesc g = groups[gi];
+            const uint32_t xl = g.x & (T - 1u);
+            double dre[NI], dim[NI];
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                dre[i] = 0.0;
+                dim[i] = 0.0;
+            }
+            apply_lo_terms<NI>(recs, g.k0, g.kre, t1, ylo, sg, dre);
+            if (IMAG)
+                apply_lo_terms<NI>(recs, g.kre, g.k1, t1, ylo, sg, dim);
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                const double2 b = tile[ylo[i] ^ xl];
+                if (IMAG) {
+                    const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
+                    const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
+                    acc += wt * (b.x * tr + b.y * ti);
+                } else {
+                    acc += wt * dre[i] * (b.x * a[i].x + b.y * a[i].y);
+                }
+            }
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
+}
+
 // lambda[y] = sum_g D_g(y ^ x_g) psi[y ^ x_g];  E = Re sum_y conj(psi[y]) lambda[y]
 __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ psi, double2 *__restrict__ lam,
                                                   int n, const GroupDesc *__restrict__ groups, int G,
@@ -444,6 +726,19 @@ struct qf_plan {
     double2 *d_tab = nullptr;
     double *d_grad = nullptr;
     int G = 0;
+    int tile_bits = 0;                 // 0: one pass per group; else tiled energy
+    bool merged = false;               // tiled with per-item merged lo-terms
+    bool has_imag = false;             // some Hamiltonian string has an odd number of Y
+    bool pipelined = true;             // 2^11 merged tiles: prefetching kernel
+    std::vector<qf::GroupDesc> groups; // host copies, for re-tiling
+    std::vector<uint32_t> hz;
+    std::vector<double> hc;
+    qf::ERec *d_recs = nullptr;
+    int64_t tiled_classes = 0;
+    uint64_t tiled_work = 0;
+    qf::ClassDesc *d_classes = nullptr;
+    uint64_t *d_work_off = nullptr;
+    qf::GroupDesc *d_tgroups = nullptr;
     qf::GroupDesc *d_groups = nullptr;
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
@@ -457,7 +752,8 @@ struct qf_plan {
             (void)hipEventDestroy(theta_done);
         if (h_theta)
             (void)hipHostFree(h_theta);
-        void *bufs[] = {d_runs, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result};
+        void *bufs[] = {d_runs, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+                        d_classes, d_work_off, d_tgroups, d_recs};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -465,6 +761,93 @@ struct qf_plan {
 };
 
 namespace qf {
+
+// Classes of groups sharing the flip bits above a tile of 2^L amplitudes,
+// and the work-item offsets of the tiled energy kernel.
+void set_energy_tile(qf_plan &P, int L, bool merged)
+{
+    if (L != 0 && L != 10 && L != 11 && L != 12)
+        raise(QF_E_ARG, "energy tile bits must be 0, 10, 11 or 12");
+    if (L && P.n < L + 1)
+        raise(QF_E_RANGE, "energy tile of 2^" + std::to_string(L) + " amplitudes needs n_qubits > " +
+                              std::to_string(L));
+    void *old[] = {P.d_classes, P.d_work_off, P.d_tgroups, P.d_recs};
+    for (void *p : old)
+        if (p)
+            QF_HIP(hipFree(p));
+    P.d_classes = nullptr;
+    P.d_work_off = nullptr;
+    P.d_tgroups = nullptr;
+    P.d_recs = nullptr;
+    P.tile_bits = L;
+    P.merged = L != 0 && merged;
+    P.tiled_classes = 0;
+    P.tiled_work = 0;
+    if (!L || P.G == 0)
+        return;
+    std::vector<GroupDesc> tg(P.groups);
+    std::stable_sort(tg.begin(), tg.end(),
+                     [L](const GroupDesc &a, const GroupDesc &b) { return (a.x >> L) < (b.x >> L); });
+    std::vector<ClassDesc> cls;
+    std::vector<uint64_t> woff(1, 0);
+    for (size_t g = 0; g < tg.size(); g++) {
+        const uint32_t xh = tg[g].x >> L;
+        if (cls.empty() || cls.back().xh != xh) {
+            ClassDesc c;
+            c.xh = xh;
+            c.hb = hibit(xh);
+            c.g0 = (int32_t)g;
+            c.g1 = (int32_t)g;
+            cls.push_back(c);
+            woff.push_back(woff.back() + (xh ? (1ull << (P.n - L - 1)) : (1ull << (P.n - L))));
+        }
+        cls.back().g1 = (int32_t)g + 1;
+    }
+    if (P.merged) {
+        // records of each phase part sorted by (z_lo, z_hi); the last record
+        // of every run of equal z_lo closes a lo-term
+        std::vector<ERec> recs;
+        const uint32_t lomask = (1u << L) - 1u;
+        for (GroupDesc &g : tg) {
+            const int32_t ranges[2][2] = {{g.k0, g.kre}, {g.kre, g.k1}};
+            GroupDesc ng = g;
+            ng.k0 = (int32_t)recs.size();
+            for (int part = 0; part < 2; part++) {
+                std::vector<int32_t> ks;
+                for (int32_t k = ranges[part][0]; k < ranges[part][1]; k++)
+                    ks.push_back(k);
+                std::stable_sort(ks.begin(), ks.end(), [&](int32_t a, int32_t b) {
+                    const uint32_t la = P.hz[(size_t)a] & lomask, lb = P.hz[(size_t)b] & lomask;
+                    return la != lb ? la < lb : (P.hz[(size_t)a] >> L) < (P.hz[(size_t)b] >> L);
+                });
+                for (size_t i = 0; i < ks.size(); i++) {
+                    const uint32_t z = P.hz[(size_t)ks[i]];
+                    ERec e;
+                    std::memset(&e, 0, sizeof e);
+                    e.zlo = z & lomask;
+                    e.zhi = z >> L;
+                    e.c = P.hc[(size_t)ks[i]];
+                    e.emit = (i + 1 == ks.size() || (P.hz[(size_t)ks[i + 1]] & lomask) != e.zlo) ? 1u : 0u;
+                    recs.push_back(e);
+                }
+                if (part == 0)
+                    ng.kre = (int32_t)recs.size();
+            }
+            ng.k1 = (int32_t)recs.size();
+            g = ng;
+        }
+        P.d_recs = dev_alloc<ERec>(recs.size());
+        QF_HIP(hipMemcpy(P.d_recs, recs.data(), recs.size() * sizeof(ERec), hipMemcpyHostToDevice));
+    }
+    P.d_classes = dev_alloc<ClassDesc>(cls.size());
+    P.d_work_off = dev_alloc<uint64_t>(woff.size());
+    P.d_tgroups = dev_alloc<GroupDesc>(tg.size());
+    QF_HIP(hipMemcpy(P.d_classes, cls.data(), cls.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
+    QF_HIP(hipMemcpy(P.d_work_off, woff.data(), woff.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    QF_HIP(hipMemcpy(P.d_tgroups, tg.data(), tg.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+    P.tiled_classes = (int64_t)cls.size();
+    P.tiled_work = woff.back();
+}
 
 void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H, const int64_t *goff,
                int64_t G)
@@ -503,6 +886,13 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         QF_HIP(hipMemcpy(P.d_groups, gd.data(), gd.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
         QF_HIP(hipMemcpy(P.d_z, zs.data(), zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         QF_HIP(hipMemcpy(P.d_c, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+        P.groups = gd;
+        P.hz = zs;
+        P.hc = cs;
+        for (const GroupDesc &g : gd)
+            if (g.k1 > g.kre)
+                P.has_imag = true;
+        set_energy_tile(P, n >= 16 ? 11 : 0, true);
     }
     P.d_partials = dev_alloc<double>((size_t)kMaxBlocks * kMaxRun);
     P.d_counter = dev_alloc<unsigned>(1);
@@ -560,8 +950,89 @@ void launch_prepare(double2 *psi, int n, uint64_t occ, hipStream_t s)
     QF_HIP(hipGetLastError());
 }
 
+template <int LT> unsigned tiled_grid(uint64_t work)
+{
+    static unsigned cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0, per = 0;
+        QF_HIP(hipGetDevice(&dev));
+        QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(k_energy_tiled<LT>), kBlock, 0));
+        cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
+    }
+    return (unsigned)std::min<uint64_t>(cached, std::max<uint64_t>(work, 1));
+}
+
+constexpr int ni_for(int LT) { return ((1 << LT) / kBlock) >= 8 ? 8 : ((1 << LT) / kBlock); }
+
+template <int LT> unsigned merged_grid(uint64_t work)
+{
+    static unsigned cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0, per = 0;
+        QF_HIP(hipGetDevice(&dev));
+        QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(k_energy_merged<LT, ni_for(LT)>), kBlock, 0));
+        cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
+    }
+    return (unsigned)std::min<uint64_t>(cached, std::max<uint64_t>(work, 1));
+}
+
+template <bool IMAG> unsigned pipe_grid(uint64_t work)
+{
+    static unsigned cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0, per = 0;
+        QF_HIP(hipGetDevice(&dev));
+        QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(k_energy_pipe<IMAG>), kBlock, 0));
+        cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
+    }
+    return (unsigned)std::min<uint64_t>(cached, std::max<uint64_t>(work, 1));
+}
+
+template <int LT> void launch_energy_tiled(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t s)
+{
+    if (P.merged && LT == 11 && P.pipelined) {
+        if (P.has_imag)
+            hipLaunchKernelGGL(k_energy_pipe<true>, dim3(pipe_grid<true>(P.tiled_work)), dim3(kBlock), 0, s, psi,
+                               P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_recs, P.d_partials,
+                               P.d_counter, dev_out);
+        else
+            hipLaunchKernelGGL(k_energy_pipe<false>, dim3(pipe_grid<false>(P.tiled_work)), dim3(kBlock), 0, s,
+                               psi, P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_recs,
+                               P.d_partials, P.d_counter, dev_out);
+        QF_HIP(hipGetLastError());
+        return;
+    }
+    if (P.merged) {
+        hipLaunchKernelGGL((k_energy_merged<LT, ni_for(LT)>), dim3(merged_grid<LT>(P.tiled_work)), dim3(kBlock), 0, s,
+                           psi, P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_recs,
+                           P.d_partials, P.d_counter, dev_out);
+        QF_HIP(hipGetLastError());
+        return;
+    }
+    hipLaunchKernelGGL(k_energy_tiled<LT>, dim3(tiled_grid<LT>(P.tiled_work)), dim3(kBlock), 0, s, psi,
+                       P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_z, P.d_c, P.d_partials,
+                       P.d_counter, dev_out);
+    QF_HIP(hipGetLastError());
+}
+
 void launch_energy(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t s)
 {
+    switch (P.tile_bits) {
+    case 10:
+        return launch_energy_tiled<10>(P, psi, dev_out, s);
+    case 11:
+        return launch_energy_tiled<11>(P, psi, dev_out, s);
+    case 12:
+        return launch_energy_tiled<12>(P, psi, dev_out, s);
+    default:
+        break;
+    }
     const uint64_t np = 1ull << (P.n - 1 > 0 ? P.n - 1 : 0);
     const unsigned nb = grid_for(np, (uint64_t)kBlock * kItems, kMaxBlocks);
     hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kBlock), 0, s, psi, P.n, P.d_groups, P.G, P.d_z, P.d_c,
@@ -784,4 +1255,27 @@ extern "C" int qf_energy_grad(int n_qubits, uint64_t occ_mask, const qf_term *A,
         energy_grad_impl(P, occ_mask, theta, workspace, E_out, dE_dtheta, (hipStream_t)stream);
         return QF_OK;
     });
+}
+
+extern "C" int qf_plan_set_energy_tile(qf_plan *P, int tile_bits, int merged)
+{
+    return guarded([&]() -> int {
+        if (!P)
+            return fail(QF_E_ARG, "qf_plan_set_energy_tile: plan is NULL");
+        set_energy_tile(*P, tile_bits, merged != 0);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_info(const qf_plan *P, int *tile_bits, int64_t *classes, int64_t *energy_passes)
+{
+    if (!P)
+        return fail(QF_E_ARG, "qf_plan_info: plan is NULL");
+    if (tile_bits)
+        *tile_bits = P->merged ? -P->tile_bits : P->tile_bits;
+    if (classes)
+        *classes = P->tiled_classes;
+    if (energy_passes)
+        *energy_passes = P->tile_bits ? P->tiled_classes : P->G;
+    return QF_OK;
 }

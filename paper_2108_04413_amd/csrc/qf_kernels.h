@@ -27,6 +27,29 @@ struct GroupDesc {
     int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
 };
 
+// Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
+// are fixed, so the factor (-1)^popcount(y_hi & z_hi) of every string is a
+// per-item constant: strings of a group that share (phase, z_lo) merge into
+// one "lo-term" whose coefficient is summed per work item.  A group's strings
+// are records sorted by (phase, z_lo); the last record of each lo-term has
+// `emit` set.
+struct ERec {
+    uint32_t zlo;   // z & (2^L - 1)
+    uint32_t emit;  // 1 on the last string of a lo-term
+    uint32_t zhi;   // z >> L, as a tile-index mask
+    uint32_t pad;
+    double c;       // coefficient with the sign of i^popcount(x&z) folded in
+    double pad2;
+};
+
+// Groups whose flip masks share the bits above the tile (x >> L == xh):
+// one tiled energy pass covers all of them.
+struct ClassDesc {
+    uint32_t xh;     // flip bits above the tile, as a tile-index mask
+    uint32_t hb;     // highest set bit of xh (0 if xh == 0)
+    int32_t g0, g1;  // group range
+};
+
 // ------------------------------------------------------------ helpers
 
 __device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)

@@ -290,3 +290,33 @@ def test_28q_energy_vs_golden(qf):
     assert norm == pytest.approx(1.0, abs=1e-12)
     del psi
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("L,merged", [(0, False), (10, False), (11, False), (12, False),
+                                      (10, True), (11, True), (12, True)])
+def test_energy_tile_variants_match_oracle(qf, L, merged):
+    n = 14
+    xs, zs, cs = qi.random_paulis(n, 500, 90)
+    xs[:40] = 0                        # diagonal group
+    xs[40:120] &= np.uint64(0x3FF)     # flip bits inside a tile
+    xs[120:200] &= np.uint64(0x3C00)   # flip bits only above the tile
+    xs, zs, cs, off = grouped(xs, zs, cs)
+    psi0 = qi.random_state(n, 91)
+    plan = qf.Plan(n, None, qf.terms_array(xs, zs, cs), off)
+    plan.set_energy_tile(L, merged)
+    info = plan.info()
+    assert info["tile_bits"] == (-L if merged else L)
+    e = plan.energy(dev(psi0))
+    assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
+
+
+def test_20q_energy_untiled_and_tiled_agree_with_golden(qf):
+    gold = _golden("20q")
+    w, n, occ, H, off, A, aoff, th = _build_device_system(qf, "20q")
+    plan = qf.Plan(n, A, H, off)
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    qf.prepare_state(psi, n, occ)
+    plan.apply(psi, th)
+    for L, merged in ((0, False), (11, False), (11, True), (12, True)):
+        plan.set_energy_tile(L, merged)
+        assert plan.energy(psi) == pytest.approx(gold["energy"], abs=E_TOL)
