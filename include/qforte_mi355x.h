@@ -179,6 +179,19 @@ int qf_plan_set_energy_tile(qf_plan *plan, int tile_bits, int merged);
 /* tile bits (negative when merged), number of classes, passes over the
  * state per energy evaluation */
 int qf_plan_info(const qf_plan *plan, int *tile_bits, int64_t *classes, int64_t *energy_passes);
+
+/*
+ * Forward application of a plan's ansatz.  block_bits = 0: one pass over
+ * the state per fused run.  block_bits = B in 6..min(12, n_qubits):
+ * consecutive runs whose flip masks fit, together with the lowest qubits, in
+ * a set of B qubits form a segment; each segment is one pass in which every
+ * sub-cube of 2^B amplitudes is loaded into LDS, updated by all the
+ * segment's runs in order, and stored.  Default: B = min(12, n_qubits) for
+ * n_qubits >= 6.  The adjoint sweep of qf_plan_energy_grad is not affected.
+ */
+int qf_plan_set_block_bits(qf_plan *plan, int block_bits);
+/* block bits, number of fused runs, passes over the state per application */
+int qf_plan_apply_info(const qf_plan *plan, int *block_bits, int64_t *runs, int64_t *passes);
 /* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out) */
 int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
 

@@ -38,7 +38,7 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy",
            "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect",
            "qf_mailbox_alloc", "qf_mailbox_free", "qf_batch_mailbox_bytes", "qf_batch_launch_mailbox",
-           "qf_plan_set_energy_tile", "qf_plan_info")
+           "qf_plan_set_energy_tile", "qf_plan_info", "qf_plan_set_block_bits", "qf_plan_apply_info")
 
 
 class QFError(RuntimeError):
@@ -83,6 +83,8 @@ _sig = {
     "qf_batch_launch_mailbox": [_vp, _vp, _vp, _i64, _vp],
     "qf_plan_set_energy_tile": [_vp, _int, _int],
     "qf_plan_info": [_vp, _vp, _vp, _vp],
+    "qf_plan_set_block_bits": [_vp, _int],
+    "qf_plan_apply_info": [_vp, _vp, _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)

@@ -124,6 +124,18 @@ class Plan:
         check(lib.qf_plan_info(self._h, ctypes.byref(tb), ctypes.byref(cl), ctypes.byref(ps)), "qf_plan_info")
         return {"tile_bits": tb.value, "classes": cl.value, "energy_passes": ps.value}
 
+    def set_block_bits(self, block_bits: int) -> None:
+        """0: one pass per fused run; 6-12: runs applied in LDS sub-cubes of 2^B amplitudes."""
+        check(lib.qf_plan_set_block_bits(self._h, int(block_bits)), "qf_plan_set_block_bits")
+
+    def apply_info(self) -> dict:
+        bb = ctypes.c_int()
+        r = ctypes.c_int64()
+        ps = ctypes.c_int64()
+        check(lib.qf_plan_apply_info(self._h, ctypes.byref(bb), ctypes.byref(r), ctypes.byref(ps)),
+              "qf_plan_apply_info")
+        return {"block_bits": bb.value, "runs": r.value, "passes": ps.value}
+
     def apply(self, psi, theta, inverse: bool = False, stream=None) -> None:
         theta = _f64(theta)
         check(lib.qf_plan_apply(self._h, ptr(psi), ptr(theta), int(inverse), stream_handle(stream)),

@@ -95,9 +95,12 @@ __device__ void load_table(const RunDesc &d, const double *__restrict__ theta, d
 {
     for (int u = threadIdx.x; u < (1 << d.r); u += kBlock) {
         double th = 0.0;
-        for (int k = 0; k < d.m; k++) {
-            const double v = (double)d.s[k] * theta[d.k0 + k];
-            th += (__popc((uint32_t)u & d.e[k]) & 1) ? -v : v;
+#pragma unroll
+        for (int k = 0; k < kMaxRun; k++) {
+            if (k < d.m) {
+                const double v = (double)d.s[k] * theta[d.k0 + k];
+                th += (__popc((uint32_t)u & d.e[k]) & 1) ? -v : v;
+            }
         }
         double sn, cs;
         sincos(th, &sn, &cs);

@@ -151,6 +151,101 @@ __global__ __launch_bounds__(kBlock) void k_apply_run(double2 *__restrict__ psi,
     }
 }
 
+// Blocked apply: one workgroup per sub-cube of 2^B amplitudes.  Runs of the
+// segment are applied in order (or reversed, with sgn = -1, for U^dagger);
+// the pairs (y, y ^ x) of a run never leave the sub-cube because x is in Q.
+// The segment's (cos, sin) tables are staged in LDS with the sub-cube.
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, int n, Segment sg,
+                                                        const LocalRun *__restrict__ lruns,
+                                                        const double2 *__restrict__ tab, double sgn)
+{
+    constexpr uint32_t NB = 1u << B;
+    static_assert(NT <= (int)NB && NB % NT == 0, "the workgroup must tile the sub-cube");
+    constexpr int PER = (int)(NB / NT);
+    __shared__ double2 st[NB];
+    __shared__ uint32_t hoff[64];
+    __shared__ double2 stab[kSegTab];
+    // base: the block index scattered into the qubits outside Q
+    uint32_t base = 0;
+    {
+        uint32_t k = 0;
+        for (int p = 0; p < n; p++)
+            if (!((sg.Q >> p) & 1u)) {
+                base |= ((blockIdx.x >> k) & 1u) << p;
+                k++;
+            }
+    }
+    const uint32_t lomask = (1u << sg.q0) - 1u;
+    if (threadIdx.x < (1u << sg.nhi)) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (q < sg.nhi)
+                o |= ((threadIdx.x >> q) & 1u) << sg.hi[q];
+        hoff[threadIdx.x] = o;
+    }
+    for (int t = threadIdx.x; t < sg.ntab; t += NT)
+        stab[t] = tab[sg.tab0 + t];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const uint32_t l = threadIdx.x + (uint32_t)i * NT;
+        st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
+    }
+    const int nr = sg.r1 - sg.r0;
+    for (int ri = 0; ri < nr; ri++) {
+        const LocalRun d = lruns[sgn > 0 ? sg.r0 + ri : sg.r1 - 1 - ri];
+        const int toff = d.tab - sg.tab0;
+        // Masks of ranks above d.r are zero, so the loops below run to the
+        // constant maximum and the descriptor stays in registers.
+        uint32_t bm[kMaxRank];
+        uint32_t pb = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxRank; q++) {
+            bm[q] = q < d.r ? d.b[q] : 0u;
+            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
+        }
+        const uint32_t pz = par(base & d.z0f);
+        __syncthreads();
+        if (d.x) {
+#pragma unroll 2
+            for (uint32_t j = threadIdx.x; j < NB / 2; j += NT) {
+                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y1 & bm[q]) << q;
+                const double2 cs = stab[toff + u];
+                const double c = cs.x, s = sgn * cs.y;
+                const double2 a = st[y1], b = st[y2];
+                const double2 pbv = mul_ik((d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u, b);
+                const double2 pav = mul_ik((d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u, a);
+                st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
+                st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
+            }
+        } else {
+#pragma unroll 2
+            for (uint32_t y = threadIdx.x; y < NB; y += NT) {
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y & bm[q]) << q;
+                const double2 cs = stab[toff + u];
+                const double c = cs.x, s = sgn * cs.y;
+                const double2 v = st[y];
+                st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        const uint32_t l = threadIdx.x + (uint32_t)i * NT;
+        psi[base | (l & lomask) | hoff[l >> sg.q0]] = st[l];
+    }
+}
+
 // Diagonal run (x == 0): psi[y] *= cos(Theta) - i sgn sin(Theta).
 __global__ __launch_bounds__(kBlock) void k_apply_diag(double2 *__restrict__ psi, uint64_t dim, RunDesc d,
                                                        const double2 *__restrict__ tab, double sgn)
@@ -712,6 +807,89 @@ void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::
     }
 }
 
+namespace {
+
+uint32_t pext32(uint32_t v, uint32_t mask)
+{
+    uint32_t out = 0, k = 0;
+    for (int p = 0; p < 32; p++)
+        if ((mask >> p) & 1u) {
+            out |= ((v >> p) & 1u) << k;
+            k++;
+        }
+    return out;
+}
+
+} // namespace
+
+// Greedy segmentation of the run sequence for blocked application: extend a
+// segment while the union of its flip masks and the lowest q0 qubits has at
+// most B qubits; pad Q with the lowest free qubits to exactly B.  A run whose
+// mask alone does not fit becomes a segment with Q = 0 (applied by itself).
+void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std::vector<Segment> &segs,
+                    std::vector<LocalRun> &lr)
+{
+    segs.clear();
+    lr.clear();
+    const uint32_t low = (1u << q0) - 1u;
+    size_t i = 0;
+    while (i < runs.size()) {
+        uint32_t cur = low;
+        size_t j = i;
+        int ntab = 0;
+        while (j < runs.size() && __builtin_popcount(cur | runs[j].x) <= B && ntab + (1 << runs[j].r) <= kSegTab) {
+            cur |= runs[j].x;
+            ntab += 1 << runs[j].r;
+            j++;
+        }
+        Segment sg;
+        std::memset(&sg, 0, sizeof sg);
+        if (j == i) {  // does not fit a sub-cube
+            sg.Q = 0;
+            sg.r0 = (int32_t)i;
+            sg.r1 = (int32_t)i + 1;
+            segs.push_back(sg);
+            i++;
+            continue;
+        }
+        uint32_t Q = cur;
+        for (int p = 0; p < n && __builtin_popcount(Q) < B; p++)
+            Q |= 1u << p;
+        int qlow = 0;
+        while (qlow < 32 && ((Q >> qlow) & 1u))
+            qlow++;
+        sg.Q = Q;
+        sg.q0 = qlow;
+        sg.nhi = 0;
+        for (int p = qlow; p < n; p++)
+            if ((Q >> p) & 1u)
+                sg.hi[sg.nhi++] = (uint32_t)p;
+        sg.r0 = (int32_t)lr.size();
+        sg.tab0 = runs[i].tab;  // run tables are laid out in run order
+        sg.ntab = runs[j - 1].tab + (1 << runs[j - 1].r) - runs[i].tab;
+        for (size_t k = i; k < j; k++) {
+            const RunDesc &d = runs[k];
+            LocalRun L;
+            std::memset(&L, 0, sizeof L);
+            L.x = pext32(d.x, Q);
+            L.hbit = hibit(L.x);
+            L.z0 = pext32(d.z0, Q);
+            L.a0 = d.a0;
+            L.z0f = d.z0;
+            for (int q = 0; q < d.r; q++) {
+                L.b[q] = pext32(d.b[q], Q);
+                L.bf[q] = d.b[q];
+            }
+            L.r = d.r;
+            L.tab = d.tab;
+            lr.push_back(L);
+        }
+        sg.r1 = (int32_t)lr.size();
+        segs.push_back(sg);
+        i = j;
+    }
+}
+
 } // namespace qf
 
 struct qf_plan {
@@ -720,6 +898,9 @@ struct qf_plan {
     std::vector<qf::RunDesc> runs;
     int tab_entries = 0;
     qf::RunDesc *d_runs = nullptr;
+    int block_bits = 0;                 // sub-cube size of blocked apply (0: per-run passes)
+    std::vector<qf::Segment> segs;      // Q == 0: a run applied on its own (index r0)
+    qf::LocalRun *d_lruns = nullptr;
     double *d_theta = nullptr;
     double *h_theta = nullptr;  // pinned staging for theta uploads
     hipEvent_t theta_done = nullptr;
@@ -752,7 +933,7 @@ struct qf_plan {
             (void)hipEventDestroy(theta_done);
         if (h_theta)
             (void)hipHostFree(h_theta);
-        void *bufs[] = {d_runs, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+        void *bufs[] = {d_runs, d_lruns, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs};
         for (void *p : bufs)
             if (p)
@@ -849,6 +1030,24 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
     P.tiled_work = woff.back();
 }
 
+void set_block_bits(qf_plan &P, int B)
+{
+    if (B != 0 && (B < 6 || B > 12 || B > P.n))
+        raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
+    if (P.d_lruns)
+        QF_HIP(hipFree(P.d_lruns));
+    P.d_lruns = nullptr;
+    P.segs.clear();
+    P.block_bits = B;
+    if (!B || P.runs.empty())
+        return;
+    std::vector<LocalRun> lr;
+    build_segments(P.runs, P.n, B, std::min(6, B), P.segs, lr);
+    P.d_lruns = dev_alloc<LocalRun>(lr.size());
+    if (!lr.empty())
+        QF_HIP(hipMemcpy(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun), hipMemcpyHostToDevice));
+}
+
 void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H, const int64_t *goff,
                int64_t G)
 {
@@ -870,6 +1069,7 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         P.d_tab = dev_alloc<double2>((size_t)P.tab_entries);
         P.d_grad = dev_alloc<double>((size_t)K);
         QF_HIP(hipMemcpy(P.d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice));
+        set_block_bits(P, n >= 6 ? std::min(n, 12) : 0);
         QF_HIP(hipHostMalloc((void **)&P.h_theta, (size_t)K * sizeof(double), hipHostMallocDefault));
         QF_HIP(hipEventCreateWithFlags(&P.theta_done, hipEventDisableTiming));
     }
@@ -923,9 +1123,53 @@ void upload_theta(qf_plan &P, const double *theta, hipStream_t s)
     QF_HIP(hipGetLastError());
 }
 
+void launch_one_run(qf_plan &P, double2 *psi, const RunDesc &d, double sgn, hipStream_t s)
+{
+    const uint64_t dim = 1ull << P.n;
+    if (d.x) {
+        const uint64_t np = dim >> 1;
+        hipLaunchKernelGGL(k_apply_run, dim3(grid_for(np, (uint64_t)kBlock * kItems, 0)), dim3(kBlock), 0, s, psi,
+                           np, d, P.d_tab, sgn);
+    } else {
+        hipLaunchKernelGGL(k_apply_diag, dim3(grid_for(dim, kBlock, 8 * kMaxBlocks)), dim3(kBlock), 0, s, psi, dim,
+                           d, P.d_tab, sgn);
+    }
+}
+
+template <int B> void launch_block(qf_plan &P, double2 *psi, const Segment &sg, double sgn, hipStream_t s)
+{
+    // 512 threads (8 waves) per sub-cube: enough loads in flight per CU at
+    // 2^11..2^12 elements while the LDS image still admits two workgroups.
+    constexpr int NT = (1 << B) < 512 ? (1 << B) : 512;
+    hipLaunchKernelGGL((k_apply_block<B, NT>), dim3((unsigned)(1ull << (P.n - B))), dim3(NT), 0, s, psi, P.n, sg,
+                       P.d_lruns, P.d_tab, sgn);
+}
+
 void launch_runs(qf_plan &P, double2 *psi, bool inverse, hipStream_t s)
 {
     const uint64_t dim = 1ull << P.n;
+    if (P.block_bits) {
+        const size_t S = P.segs.size();
+        const double sgn = inverse ? -1.0 : 1.0;
+        for (size_t i = 0; i < S; i++) {
+            const Segment &sg = P.segs[inverse ? S - 1 - i : i];
+            if (!sg.Q) {
+                launch_one_run(P, psi, P.runs[(size_t)sg.r0], sgn, s);
+                continue;
+            }
+            switch (P.block_bits) {
+            case 6: launch_block<6>(P, psi, sg, sgn, s); break;
+            case 7: launch_block<7>(P, psi, sg, sgn, s); break;
+            case 8: launch_block<8>(P, psi, sg, sgn, s); break;
+            case 9: launch_block<9>(P, psi, sg, sgn, s); break;
+            case 10: launch_block<10>(P, psi, sg, sgn, s); break;
+            case 11: launch_block<11>(P, psi, sg, sgn, s); break;
+            default: launch_block<12>(P, psi, sg, sgn, s); break;
+            }
+        }
+        QF_HIP(hipGetLastError());
+        return;
+    }
     const size_t R = P.runs.size();
     for (size_t i = 0; i < R; i++) {
         const RunDesc &d = P.runs[inverse ? R - 1 - i : i];
@@ -1277,5 +1521,28 @@ extern "C" int qf_plan_info(const qf_plan *P, int *tile_bits, int64_t *classes, 
         *classes = P->tiled_classes;
     if (energy_passes)
         *energy_passes = P->tile_bits ? P->tiled_classes : P->G;
+    return QF_OK;
+}
+
+extern "C" int qf_plan_set_block_bits(qf_plan *P, int block_bits)
+{
+    return guarded([&]() -> int {
+        if (!P)
+            return fail(QF_E_ARG, "qf_plan_set_block_bits: plan is NULL");
+        set_block_bits(*P, block_bits);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_apply_info(const qf_plan *P, int *block_bits, int64_t *runs, int64_t *passes)
+{
+    if (!P)
+        return fail(QF_E_ARG, "qf_plan_apply_info: plan is NULL");
+    if (block_bits)
+        *block_bits = P->block_bits;
+    if (runs)
+        *runs = (int64_t)P->runs.size();
+    if (passes)
+        *passes = P->block_bits ? (int64_t)P->segs.size() : (int64_t)P->runs.size();
     return QF_OK;
 }

@@ -27,6 +27,32 @@ struct GroupDesc {
     int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
 };
 
+// Blocked application of consecutive runs.  A segment is a range of runs
+// whose flip masks all lie inside a set Q of B qubits that contains the
+// lowest q0 qubits; the state splits into 2^(n-B) sub-cubes (fixed values of
+// the other qubits), each loaded into LDS once, updated by every run of the
+// segment, and written back.  Masks of a run are given both in the full
+// index space (for the sub-cube's fixed bits) and compressed to Q (pext).
+constexpr int kSegTab = 512;  // (cos, sin) entries of one segment, staged in LDS
+
+struct Segment {
+    uint32_t Q;      // qubits of the sub-cube
+    int32_t q0;      // Q contains qubits 0 .. q0-1 (q0 >= min(6, B))
+    int32_t r0, r1;  // runs [r0, r1) of the segment (LocalRun array)
+    uint32_t hi[8];  // positions of Q's qubits above q0, ascending
+    int32_t nhi;
+    int32_t tab0, ntab;  // the segment's runs use tab[tab0, tab0 + ntab)
+    int32_t pad;
+};
+
+struct LocalRun {
+    uint32_t x, hbit, z0, a0;       // local flip mask, its highest bit, local z0, i^a0
+    uint32_t b[kMaxRank];           // local GF(2) basis masks
+    uint32_t z0f;                   // full-space z0
+    uint32_t bf[kMaxRank];          // full-space basis masks
+    int32_t r, tab, pad0, pad1;
+};
+
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
 // are fixed, so the factor (-1)^popcount(y_hi & z_hi) of every string is a
 // per-item constant: strings of a group that share (phase, z_lo) merge into
@@ -80,9 +106,13 @@ __device__ __forceinline__ double flip(double v, uint32_t p)
 
 __device__ __forceinline__ uint32_t run_coords(const RunDesc &d, uint32_t y)
 {
+    // Unrolled to the maximum rank so that every index is a constant: a
+    // descriptor copied out of global memory then stays in registers.
     uint32_t u = 0;
-    for (int q = 0; q < d.r; q++)
-        u |= par(y & d.b[q]) << q;
+#pragma unroll
+    for (int q = 0; q < kMaxRank; q++)
+        if (q < d.r)
+            u |= par(y & d.b[q]) << q;
     return u;
 }
 

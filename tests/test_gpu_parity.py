@@ -320,3 +320,42 @@ def test_20q_energy_untiled_and_tiled_agree_with_golden(qf):
     for L, merged in ((0, False), (11, False), (11, True), (12, True)):
         plan.set_energy_tile(L, merged)
         assert plan.energy(psi) == pytest.approx(gold["energy"], abs=E_TOL)
+
+
+@pytest.mark.parametrize("B", [0, 6, 9, 12])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_blocked_apply_matches_oracle(qf, B, inverse):
+    """Sub-cube application: segments of runs, incl. runs too wide to fit."""
+    n = 14
+    xs, zs = runs_of_terms(n, 40 + B, 160)
+    # a block of low-mask excitation-like runs so that segments hold many runs
+    rng = np.random.default_rng(7 + B)
+    lowx = [int(v) for v in rng.choice([0b1111, 0b110011, 0b101000101, 0b11], 40)]
+    xs = np.concatenate([np.array(lowx, dtype=np.uint64), xs])
+    zs = np.concatenate([rng.integers(0, 1 << n, 40).astype(np.uint64), zs])
+    th = qi.random_angles(len(xs), 60 + B)
+    psi0 = qi.random_state(n, 61)
+    A = qf.terms_array(xs, zs, np.ones(len(xs)))
+    plan = qf.Plan(n, A)
+    plan.set_block_bits(B)
+    info = plan.apply_info()
+    assert info["block_bits"] == B and info["passes"] <= info["runs"]
+    psi = dev(psi0)
+    plan.apply(psi, th, inverse=inverse)
+    want = sv.apply_product(psi0, n, xs, zs, th, inverse=inverse)
+    assert np.max(np.abs(host(psi) - want)) < A_TOL
+
+
+def test_blocked_apply_20q_ansatz_matches_golden_samples(qf):
+    gold = _golden("20q")
+    w, n, occ, H, off, A, aoff, th = _build_device_system(qf, "20q")
+    plan = qf.Plan(n, A, H, off)
+    info = plan.apply_info()
+    assert info["block_bits"] == 12 and info["passes"] < info["runs"] // 10
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    qf.prepare_state(psi, n, occ)
+    plan.apply(psi, th)
+    idx = np.array(gold["sample_index"])
+    want = np.array(gold["sample_re"]) + 1j * np.array(gold["sample_im"])
+    assert np.max(np.abs(host(psi)[idx] - want)) < A_TOL
+    assert plan.energy(psi) == pytest.approx(gold["energy"], abs=E_TOL)
