@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "qf_common.h"
@@ -486,102 +487,263 @@ __global__ __launch_bounds__(kBlock) void k_energy_merged(const double2 *__restr
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
-// Pipelined merged tiled energy for tiles of 2^11 amplitudes (8 per thread):
-// while a work item is evaluated from LDS and registers, the loads of the
-// next item's partner tile and own amplitudes are already in flight.  With
-// IMAG == false every string has real phase (real Hamiltonians), and the
-// imaginary accumulators are dropped.
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Streaming form of the merged 2^11-tile energy.  Work items follow the
+// interleaved piece order, and the descriptor of the item after the fetched
+// one is read a step ahead.  The fetch of an item also loads one of its group
+// descriptors and one of its records per thread; at the item's start these go
+// to LDS beside the partner tile, and every wave then pulls them 64 at a time
+// into registers and broadcasts them with readlane.  Vector loads that the
+// compute waits for are therefore always older than the next item's tile
+// loads, which stay in flight during the compute.  Items with more than 256
+// groups or records restage the rest from global memory.
+//
+// With y_lo = tid + 256 i, the lo-term sign (-1)^popcount(y_lo & z_lo) splits
+// into a per-thread factor (bits 0..7 of z_lo) and a wave-uniform factor per
+// element slot i (bits 8..10), so an element costs one FMA per lo-term.
 template <bool IMAG>
-__global__ __launch_bounds__(kBlock) void k_energy_pipe(const double2 *__restrict__ psi,
-                                                        const ClassDesc *__restrict__ classes,
-                                                        const uint64_t *__restrict__ work_off,
-                                                        uint64_t total_work,
-                                                        const GroupDesc *__restrict__ groups,
-                                                        const ERec *__restrict__ recs, double *partials,
-                                                        unsigned *counter, double *result)
+__global__ __launch_bounds__(kBlock) void k_energy_stream(const double2 *__restrict__ psi,
+                                                          const VClass *__restrict__ vcls, uint32_t nv,
+                                                          uint32_t per_v, const GroupDesc *__restrict__ groups,
+                                                          const ERec *__restrict__ recs, double *partials,
+                                                          unsigned *counter, double *result)
 {
     constexpr int LT = 11;
     constexpr int NI = 8;
     constexpr uint32_t T = 1u << LT;
+    constexpr int W = kBlock;  // staged groups / records per window
     static_assert(T == (uint32_t)kBlock * NI, "one tile per block pass");
     __shared__ double2 tile[T];
+    __shared__ uint4 sgrp[W];  // x & (T-1), kre, k1
+    __shared__ uint4 srec[W];  // z_lo | emit << 31, z_hi, c (lo, hi word)
+    const uint32_t tid = threadIdx.x;
+    const int lane = (int)(tid & 63u);
     double acc = 0.0;
-    double sg[NI];
-#pragma unroll
-    for (int i = 0; i < NI; i++)
-        sg[i] = 1.0;
-    uint32_t ylo[NI];
-#pragma unroll
-    for (int i = 0; i < NI; i++)
-        ylo[i] = threadIdx.x + (uint32_t)i * kBlock;
 
-    // next item's data, loaded one iteration ahead
-    double2 pn[NI], on[NI];
-    int c = 0;
+    auto load_group = [&](int gi) __attribute__((always_inline)) {
+        const GroupDesc g = groups[gi];
+        return make_uint4(g.x & (T - 1u), (uint32_t)g.kre, (uint32_t)g.k1, 0u);
+    };
+    auto load_rec = [&](int ri) __attribute__((always_inline)) {
+        const ERec e = recs[ri];
+        return make_uint4(e.zlo | (e.emit << 31), e.zhi, (uint32_t)__double2loint(e.c),
+                          (uint32_t)__double2hiint(e.c));
+    };
+
+    // items in order (p, round): piece vcls[p] at tile pair vcls[p].j0 + round
+    const uint32_t dp = gridDim.x % nv, dj = gridDim.x / nv;
+    uint32_t pf = blockIdx.x % nv, jf = blockIdx.x / nv;  // the item to fetch next
+    bool hf = jf < per_v;
+    VClass vf = vcls[hf ? pf : 0u];  // nv >= 1: a valid piece even for an idle block
+    VClass vc = vf;                  // the item whose data is in flight
+    bool hc = false;
+
+    double2 pn[NI], on[NI];  // partner and own tile of the fetched item
+    // one group and one record of it, raw: no arithmetic on loaded values
+    // before the next item's start, so the fetch never waits on its loads
+    uint32_t qg_x = 0, qg_re = 0, qg_end = 0, qr_zlo = 0, qr_emit = 0, qr_zhi = 0;
+    double qr_c = 0.0;
     uint32_t t1n = 0;
-    bool xhn = false;
-    uint64_t w = blockIdx.x;
-    auto fetch = [&](uint64_t wi) {
-        while (wi >= work_off[c + 1])
-            c++;
-        const ClassDesc cd = classes[c];
-        const uint32_t j = (uint32_t)(wi - work_off[c]);
-        const uint32_t t1 = cd.xh ? insert0(j, cd.hb) : j;
-        const double2 *p2 = psi + ((size_t)(t1 ^ cd.xh) << LT);
-        const double2 *p1 = psi + ((size_t)t1 << LT);
 #pragma unroll
-        for (int i = 0; i < NI; i++)
-            pn[i] = p2[ylo[i]];
-        if (cd.xh) {
+    for (int i = 0; i < NI; i++) {
+        pn[i] = make_double2(0.0, 0.0);
+        on[i] = pn[i];
+    }
+
+    while (hc || hf) {
+        uint32_t p3 = pf + dp, j3 = jf + dj;
+        if (p3 >= nv) {
+            p3 -= nv;
+            j3++;
+        }
+        const bool h3 = hf && j3 < per_v;
+        const VClass v3 = vcls[h3 ? p3 : pf];
+
+        const uint32_t t1 = t1n;
+        double2 a[NI];
+        if (hc) {
+            __syncthreads();  // the previous item's LDS reads are done
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                tile[tid + (uint32_t)i * kBlock] = pn[i];
+                a[i] = on[i];
+            }
+            sgrp[tid] = make_uint4(qg_x & (T - 1u), qg_re, qg_end, 0u);
+            srec[tid] = make_uint4(qr_zlo | (qr_emit << 31), qr_zhi, (uint32_t)__double2loint(qr_c),
+                                   (uint32_t)__double2hiint(qr_c));
+            __syncthreads();
+        }
+        {
+            // unconditional, so the in-flight registers need no merge copies
+            // (a copy would wait on the loads); past the end this re-reads
+            // the last valid tile pair of the piece
+            const uint32_t j = vf.j0 + min(jf, per_v - 1u);
+            const uint32_t t1f = vf.xh ? insert0(j, vf.hb) : j;
+            const double2 *q2 = psi + ((size_t)(t1f ^ vf.xh) << LT);
+            const double2 *q1 = psi + ((size_t)t1f << LT);
 #pragma unroll
             for (int i = 0; i < NI; i++)
-                on[i] = p1[ylo[i]];
-        }
-        t1n = t1;
-        xhn = cd.xh != 0;
-    };
-    if (w < total_work)
-        fetch(w);
-    for (; w < total_work; w += gridDim.x) {
-        const int cc = c;
-        const uint32_t t1 = t1n;
-        const bool xh = xhn;
-        const double wt = xh ? 2.0 : 1.0;
-        double2 a[NI];
-        __syncthreads();  // the previous item's LDS reads are done
+                pn[i] = q2[tid + (uint32_t)i * kBlock];
 #pragma unroll
-        for (int i = 0; i < NI; i++) {
-            tile[ylo[i]] = pn[i];
-            a[i] = xh ? on[i] : pn[i];
-        }
-        __syncthreads();
-        const ClassDesc cd = classes[cc];
-        if (w + gridDim.x < total_work)
-            fetch(w + gridDim.x);
-        for (int gi = cd.g0; gi < cd.g1; gi++) {
-            const GroupDesc g = groups[gi];
-            const uint32_t xl = g.x & (T - 1u);
-            double dre[NI], dim[NI];
-#pragma unroll
-            for (int i = 0; i < NI; i++) {
-                dre[i] = 0.0;
-                dim[i] = 0.0;
+            for (int i = 0; i < NI; i++)
+                on[i] = q1[tid + (uint32_t)i * kBlock];
+            {
+                const GroupDesc &g = groups[min(vf.g0 + (int)tid, vf.g1 - 1)];
+                qg_x = g.x;
+                qg_re = (uint32_t)g.kre;
+                qg_end = (uint32_t)g.k1;
+                const ERec &e = recs[min(vf.r0 + (int)tid, vf.r1 - 1)];
+                qr_zlo = e.zlo;
+                qr_emit = e.emit;
+                qr_zhi = e.zhi;
+                qr_c = e.c;
             }
-            apply_lo_terms<NI>(recs, g.k0, g.kre, t1, ylo, sg, dre);
-            if (IMAG)
-                apply_lo_terms<NI>(recs, g.kre, g.k1, t1, ylo, sg, dim);
+            t1n = t1f;
+        }
+        if (hc) {
+            // ---- record cursor: chunk [rc, rc + 64) of the item's records, one
+            // per lane; cv holds the segmented prefix sums of the signed
+            // coefficients (segments end at lo-term emits), so at an emit lane
+            // it is that lo-term's coefficient for this tile pair
+            int wr = vc.r0, rc = vc.r0 - 64;
+            uint64_t emask = 0;
+            uint32_t cz = 0;
+            double cv = 0.0;
+            auto prep = [&]() __attribute__((always_inline)) {
+                double cin = 0.0;  // open lo-term carried from the previous chunk
+                if (rc >= vc.r0) {
+                    const uint32_t z63 = (uint32_t)__builtin_amdgcn_readlane((int)cz, 63);
+                    cin = (z63 >> 31) ? 0.0 : readlane_d(cv, 63);
+                }
+                rc += 64;
+                if (rc - wr == W) {
+                    __syncthreads();
+                    srec[tid] = load_rec(min(rc + (int)tid, vc.r1 - 1));
+                    wr = rc;
+                    __syncthreads();
+                }
+                const uint4 e = srec[rc - wr + lane];
+                const bool valid = rc + lane < vc.r1;
+                const uint32_t z = valid ? e.x : 0u;
+                double sv = valid ? flip(__hiloint2double((int)e.w, (int)e.z), par(t1 & e.y)) : 0.0;
+                const uint64_t em = __ballot((z >> 31) != 0u);
+                // segment start: lane 0 or the lane after an emit
+                int sf = lane == 0 || ((em >> (lane - 1)) & 1ull);
 #pragma unroll
-            for (int i = 0; i < NI; i++) {
-                const double2 b = tile[ylo[i] ^ xl];
+                for (int off = 1; off < 64; off <<= 1) {
+                    const double up = __shfl_up(sv, (unsigned)off, 64);
+                    const int upf = __shfl_up(sf, (unsigned)off, 64);
+                    if (lane >= off) {
+                        if (!sf)
+                            sv += up;
+                        sf |= upf;
+                    }
+                }
+                const int first = em ? __builtin_ctzll(em) : 63;
+                if (lane <= first)
+                    sv += cin;
+                emask = em;
+                cz = z;
+                cv = sv;
+            };
+            int r = vc.r0;  // next record to consume
+            auto next_lo = [&](uint32_t &z, double &ce) __attribute__((always_inline)) {
+                while (emask == 0)
+                    prep();
+                const int k = __builtin_ctzll(emask);
+                emask &= emask - 1;
+                z = (uint32_t)__builtin_amdgcn_readlane((int)cz, k);
+                ce = readlane_d(cv, k);
+                r = rc + k + 1;
+            };
+
+            // lo-terms of one phase part, up to record rend, into d[i]; the
+            // slot factor (-1)^popcount(i & zi) is a compile-time sign per case
+            auto part = [&](int rend, double(&d)[NI]) __attribute__((always_inline)) {
+                while (r < rend) {
+                    uint32_t z;
+                    double ce;
+                    next_lo(z, ce);
+                    const uint32_t zl = z & (T - 1u);
+                    const double s0 = __hiloint2double((int)(0x3FF00000u | (__popc(tid & zl) << 31)), 0);
+#define QF_LO_CASE(K)                                                                               \
+    case K:                                                                                         \
+        _Pragma("unroll") for (int i = 0; i < NI; i++) d[i] =                                       \
+            fma(s0, (__builtin_popcount((unsigned)(i & K)) & 1) ? -ce : ce, d[i]);                  \
+        break;
+                    switch (zl >> 8) {
+                        QF_LO_CASE(0)
+                        QF_LO_CASE(1)
+                        QF_LO_CASE(2)
+                        QF_LO_CASE(3)
+                        QF_LO_CASE(4)
+                        QF_LO_CASE(5)
+                        QF_LO_CASE(6)
+                    default:
+                        QF_LO_CASE(7)
+                    }
+#undef QF_LO_CASE
+                }
+            };
+
+            double item = 0.0;
+            int wg = vc.g0, gc = vc.g0;
+            uint4 gch = sgrp[lane];
+            for (int gi = vc.g0; gi < vc.g1; gi++) {
+                if (gi - gc == 64) {
+                    gc = gi;
+                    if (gc - wg == W) {
+                        __syncthreads();
+                        sgrp[tid] = load_group(min(gc + (int)tid, vc.g1 - 1));
+                        wg = gc;
+                        __syncthreads();
+                    }
+                    gch = sgrp[gc - wg + lane];
+                }
+                const int k = gi - gc;
+                const uint32_t xl = (uint32_t)__builtin_amdgcn_readlane((int)gch.x, k);
+                const int kre = __builtin_amdgcn_readlane((int)gch.y, k);
+                const int k1 = __builtin_amdgcn_readlane((int)gch.z, k);
+                double dre[NI];
+#pragma unroll
+                for (int i = 0; i < NI; i++)
+                    dre[i] = 0.0;
+                part(kre, dre);
                 if (IMAG) {
-                    const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
-                    const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
-                    acc += wt * (b.x * tr + b.y * ti);
+                    double dim[NI];
+#pragma unroll
+                    for (int i = 0; i < NI; i++)
+                        dim[i] = 0.0;
+                    part(k1, dim);
+#pragma unroll
+                    for (int i = 0; i < NI; i++) {
+                        const double2 b = tile[(tid + (uint32_t)i * kBlock) ^ xl];
+                        const double tr = dre[i] * a[i].x - dim[i] * a[i].y;
+                        const double ti = dre[i] * a[i].y + dim[i] * a[i].x;
+                        item += b.x * tr + b.y * ti;
+                    }
                 } else {
-                    acc += wt * dre[i] * (b.x * a[i].x + b.y * a[i].y);
+#pragma unroll
+                    for (int i = 0; i < NI; i++) {
+                        const double2 b = tile[(tid + (uint32_t)i * kBlock) ^ xl];
+                        item = fma(dre[i], b.x * a[i].x + b.y * a[i].y, item);
+                    }
                 }
             }
+            acc += (vc.xh ? 2.0 : 1.0) * item;
         }
+        vc = vf;
+        hc = hf;
+        vf = v3;
+        pf = p3;
+        jf = j3;
+        hf = h3;
     }
     double vals[1] = {acc};
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
@@ -910,7 +1072,8 @@ struct qf_plan {
     int tile_bits = 0;                 // 0: one pass per group; else tiled energy
     bool merged = false;               // tiled with per-item merged lo-terms
     bool has_imag = false;             // some Hamiltonian string has an odd number of Y
-    bool pipelined = true;             // 2^11 merged tiles: prefetching kernel
+    qf::VClass *d_vcls = nullptr;      // 2^11 merged tiles: interleaved pieces of the streaming kernel
+    uint32_t n_vcls = 0, per_vcls = 0;
     std::vector<qf::GroupDesc> groups; // host copies, for re-tiling
     std::vector<uint32_t> hz;
     std::vector<double> hc;
@@ -934,7 +1097,7 @@ struct qf_plan {
         if (h_theta)
             (void)hipHostFree(h_theta);
         void *bufs[] = {d_runs, d_lruns, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
-                        d_classes, d_work_off, d_tgroups, d_recs};
+                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -945,6 +1108,48 @@ namespace qf {
 
 // Classes of groups sharing the flip bits above a tile of 2^L amplitudes,
 // and the work-item offsets of the tiled energy kernel.
+// Pieces of the streaming energy kernel, placed so that the costly ones
+// (many records and groups per tile) are evenly spaced in every round.
+void build_pieces(qf_plan &P, const std::vector<ClassDesc> &cls, const std::vector<GroupDesc> &tg)
+{
+    const uint32_t per = 1u << (P.n - 12);
+    std::vector<VClass> pieces;
+    std::vector<int64_t> cost;
+    for (const ClassDesc &c : cls) {
+        VClass v;
+        std::memset(&v, 0, sizeof v);
+        v.xh = c.xh;
+        v.hb = c.hb;
+        v.g0 = c.g0;
+        v.g1 = c.g1;
+        v.r0 = tg[(size_t)c.g0].k0;
+        v.r1 = tg[(size_t)c.g1 - 1].k1;
+        const int64_t w = (int64_t)(v.r1 - v.r0) + 2 * (int64_t)(v.g1 - v.g0);
+        for (uint32_t h = 0; h < (c.xh ? 1u : 2u); h++) {
+            v.j0 = h * per;
+            pieces.push_back(v);
+            cost.push_back(w);
+        }
+    }
+    const uint32_t nv = (uint32_t)pieces.size();
+    std::vector<VClass> placed(nv);
+    std::vector<uint32_t> rank(nv);
+    for (uint32_t i = 0; i < nv; i++)
+        rank[i] = i;
+    std::stable_sort(rank.begin(), rank.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    // rank i goes to position i * stride mod nv: consecutive ranks land about
+    // 0.618 nv apart, so every window of positions holds its share of costly pieces
+    uint32_t stride = std::max<uint32_t>(1, (uint32_t)(0.6180339887 * nv));
+    while (std::gcd(stride, nv) != 1)
+        stride++;
+    for (uint32_t i = 0; i < nv; i++)
+        placed[(uint64_t)i * stride % nv] = pieces[rank[i]];
+    P.d_vcls = dev_alloc<VClass>(nv);
+    QF_HIP(hipMemcpy(P.d_vcls, placed.data(), nv * sizeof(VClass), hipMemcpyHostToDevice));
+    P.n_vcls = nv;
+    P.per_vcls = per;
+}
+
 void set_energy_tile(qf_plan &P, int L, bool merged)
 {
     if (L != 0 && L != 10 && L != 11 && L != 12)
@@ -952,7 +1157,7 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
     if (L && P.n < L + 1)
         raise(QF_E_RANGE, "energy tile of 2^" + std::to_string(L) + " amplitudes needs n_qubits > " +
                               std::to_string(L));
-    void *old[] = {P.d_classes, P.d_work_off, P.d_tgroups, P.d_recs};
+    void *old[] = {P.d_classes, P.d_work_off, P.d_tgroups, P.d_recs, P.d_vcls};
     for (void *p : old)
         if (p)
             QF_HIP(hipFree(p));
@@ -960,6 +1165,9 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
     P.d_work_off = nullptr;
     P.d_tgroups = nullptr;
     P.d_recs = nullptr;
+    P.d_vcls = nullptr;
+    P.n_vcls = 0;
+    P.per_vcls = 0;
     P.tile_bits = L;
     P.merged = L != 0 && merged;
     P.tiled_classes = 0;
@@ -1019,6 +1227,8 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
         }
         P.d_recs = dev_alloc<ERec>(recs.size());
         QF_HIP(hipMemcpy(P.d_recs, recs.data(), recs.size() * sizeof(ERec), hipMemcpyHostToDevice));
+        if (L == 11)
+            build_pieces(P, cls, tg);
     }
     P.d_classes = dev_alloc<ClassDesc>(cls.size());
     P.d_work_off = dev_alloc<uint64_t>(woff.size());
@@ -1224,7 +1434,7 @@ template <int LT> unsigned merged_grid(uint64_t work)
     return (unsigned)std::min<uint64_t>(cached, std::max<uint64_t>(work, 1));
 }
 
-template <bool IMAG> unsigned pipe_grid(uint64_t work)
+template <bool IMAG> unsigned stream_grid()
 {
     static unsigned cached = 0;
     if (!cached) {
@@ -1232,23 +1442,22 @@ template <bool IMAG> unsigned pipe_grid(uint64_t work)
         QF_HIP(hipGetDevice(&dev));
         QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per, reinterpret_cast<const void *>(k_energy_pipe<IMAG>), kBlock, 0));
+            &per, reinterpret_cast<const void *>(k_energy_stream<IMAG>), kBlock, 0));
         cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
     }
-    return (unsigned)std::min<uint64_t>(cached, std::max<uint64_t>(work, 1));
+    return cached;
 }
 
 template <int LT> void launch_energy_tiled(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t s)
 {
-    if (P.merged && LT == 11 && P.pipelined) {
+    if (P.merged && LT == 11 && P.d_vcls) {
         if (P.has_imag)
-            hipLaunchKernelGGL(k_energy_pipe<true>, dim3(pipe_grid<true>(P.tiled_work)), dim3(kBlock), 0, s, psi,
-                               P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_recs, P.d_partials,
-                               P.d_counter, dev_out);
+            hipLaunchKernelGGL(k_energy_stream<true>, dim3(stream_grid<true>()), dim3(kBlock), 0, s, psi, P.d_vcls,
+                               P.n_vcls, P.per_vcls, P.d_tgroups, P.d_recs, P.d_partials, P.d_counter, dev_out);
         else
-            hipLaunchKernelGGL(k_energy_pipe<false>, dim3(pipe_grid<false>(P.tiled_work)), dim3(kBlock), 0, s,
-                               psi, P.d_classes, P.d_work_off, P.tiled_work, P.d_tgroups, P.d_recs,
-                               P.d_partials, P.d_counter, dev_out);
+            hipLaunchKernelGGL(k_energy_stream<false>, dim3(stream_grid<false>()), dim3(kBlock), 0, s, psi,
+                               P.d_vcls, P.n_vcls, P.per_vcls, P.d_tgroups, P.d_recs, P.d_partials, P.d_counter,
+                               dev_out);
         QF_HIP(hipGetLastError());
         return;
     }

@@ -76,6 +76,19 @@ struct ClassDesc {
     int32_t g0, g1;  // group range
 };
 
+// Streaming energy: the work order interleaves the classes.  Each class is cut
+// into pieces of 2^(n-L-1) tile pairs (the class with no flip bits above the
+// tile has 2^(n-L) tiles and so two pieces); a round visits every piece once,
+// at the same tile-pair offset, so ALU-heavy classes are spread over the whole
+// launch instead of running back to back.
+struct VClass {
+    uint32_t xh, hb;  // as in ClassDesc
+    uint32_t j0;      // first tile-pair index of the piece
+    int32_t g0, g1;   // groups of the class
+    int32_t r0, r1;   // records of the class (merged form)
+    uint32_t pad;
+};
+
 // ------------------------------------------------------------ helpers
 
 __device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)
