@@ -856,6 +856,236 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_run(double2 *__restrict__ ph
     reduce_finish<kMaxRun>(acc, partials, counter, grad + d.k0, 2.0, d.m);
 }
 
+
+// Blocked reverse sweep over one segment of runs: each workgroup holds one
+// 2^B sub-cube of phi and of lambda in LDS and walks the segment's runs in
+// reverse; for each run it first accumulates 2 Im <lambda|P_k|phi> of the
+// run's strings over the sub-cube (before the run is undone), then undoes the
+// run on both states.  The grid is persistent (resident workgroups, each
+// looping over sub-cubes) and keeps per-string sums in LDS; the last
+// workgroup to finish sums the per-workgroup sums in workgroup order.
+constexpr int adj_threads(int B) { return B >= 11 ? 512 : (1 << B) / 2 >= 256 ? 256 : 64; }
+
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
+                                                      Segment sg, const LocalRun *__restrict__ lruns,
+                                                      const double2 *__restrict__ tab, int sk0, int nstr,
+                                                      double *__restrict__ part, int K)
+{
+    constexpr uint32_t NB = 1u << B;
+    static_assert(NT <= (int)NB && NB % NT == 0 && NT % 64 == 0, "the workgroup must tile the sub-cube");
+    constexpr int PER = (int)(NB / NT);
+    constexpr int NW = NT / 64;
+    __shared__ double2 sp[NB], sl[NB];
+    __shared__ uint32_t hoff[64];
+    __shared__ double2 stab[kSegTab];
+    __shared__ double lacc[kSegStr];
+    __shared__ double red[NW][kMaxRun];
+    const uint32_t tid = threadIdx.x;
+    const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
+    const uint32_t lomask = (1u << sg.q0) - 1u;
+    if (tid < (1u << sg.nhi)) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (q < sg.nhi)
+                o |= ((tid >> q) & 1u) << sg.hi[q];
+        hoff[tid] = o;
+    }
+    for (int t = (int)tid; t < sg.ntab; t += NT)
+        stab[t] = tab[sg.tab0 + t];
+    for (int t = (int)tid; t < nstr; t += NT)
+        lacc[t] = 0.0;
+    const uint32_t nsub = 1u << (n - B);
+    const int nr = sg.r1 - sg.r0;
+    for (uint32_t sc = blockIdx.x; sc < nsub; sc += gridDim.x) {
+        uint32_t base = 0;
+        {
+            uint32_t k = 0;
+            for (int p = 0; p < n; p++)
+                if (!((sg.Q >> p) & 1u)) {
+                    base |= ((sc >> k) & 1u) << p;
+                    k++;
+                }
+        }
+        __syncthreads();  // tables staged; the previous sub-cube is written back
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const uint32_t l = tid + (uint32_t)i * NT;
+            const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
+            sp[l] = phi[y];
+            sl[l] = lam[y];
+        }
+        // descriptors are read one run ahead, so their load overlaps a run
+        LocalRun dnext = lruns[sg.r1 - 1];
+        for (int ri = nr - 1; ri >= 0; ri--) {
+            const LocalRun d = dnext;
+            if (ri > 0)
+                dnext = lruns[sg.r0 + ri - 1];
+            const int toff = d.tab - sg.tab0;
+            uint32_t bm[kMaxRank];
+            uint32_t pb = 0;
+#pragma unroll
+            for (int q = 0; q < kMaxRank; q++) {
+                bm[q] = q < d.r ? d.b[q] : 0u;
+                pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
+            }
+            const uint32_t pz = par(base & d.z0f);
+            // string k's weight is eps_k = s_k (-1)^popcount(u & e_k) with
+            // s_k = +-1 and e_k < 2^r.  For r <= 3 the pass accumulates the 8
+            // Walsh sums W[e] = sum (-1)^popcount(u & e) q (acc[e]) and string
+            // k takes s_k W[e_k] afterwards; for r > 3, acc[k] is string k's sum.
+            const bool walsh = d.r <= 3;
+            uint32_t em[kMaxRun], sneg[kMaxRun];
+            double acc[kMaxRun];
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++) {
+                em[k] = d.e[k];
+                sneg[k] = d.s[k] < 0 ? 1u : 0u;
+                acc[k] = 0.0;
+            }
+            auto accumulate = [&](uint32_t u, double q) __attribute__((always_inline)) {
+                if (walsh) {
+                    const uint32_t b1 = u << 31, b2 = (u >> 1) << 31, b4 = (u >> 2) << 31;
+                    const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
+#pragma unroll
+                    for (int e = 0; e < kMaxRun; e++)
+                        acc[e] += __hiloint2double(__double2hiint(q) ^ (int)sb[e], __double2loint(q));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kMaxRun; k++)
+                        acc[k] += flip(q, (__popc(u & em[k]) ^ sneg[k]) & 1u);
+                }
+            };
+            __syncthreads();  // the previous run's updates are visible
+            if (d.x) {
+#pragma unroll
+                for (uint32_t j = tid; j < NB / 2; j += NT) {
+                    const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
+                    uint32_t u = pb;
+#pragma unroll
+                    for (int q = 0; q < kMaxRank; q++)
+                        u ^= par(y1 & bm[q]) << q;
+                    const double2 cs = stab[toff + u];
+                    const double c = cs.x, s = cs.y;
+                    const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+                    const uint32_t k1 = (d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u;
+                    const uint32_t k2 = (d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u;
+                    const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
+                    const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
+                    sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
+                    sp[y2] = make_double2(c * b.x - s * wa.y, c * b.y + s * wa.x);
+                    const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
+                    sl[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
+                    sl[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
+                    accumulate(u, q);
+                }
+            } else {
+#pragma unroll
+                for (uint32_t y = tid; y < NB; y += NT) {
+                    uint32_t u = pb;
+#pragma unroll
+                    for (int q = 0; q < kMaxRank; q++)
+                        u ^= par(y & bm[q]) << q;
+                    const double2 cs = stab[toff + u];
+                    const double c = cs.x, s = cs.y;
+                    const double2 a = sp[y], la = sl[y];
+                    const double q = la.x * a.y - la.y * a.x;
+                    sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
+                    sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+                    accumulate(u, q);
+                }
+            }
+            // wavefront sums of all accumulators, one shuffle step at a time
+            // so that the eight exchanges of a step are in flight together
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                double o[kMaxRun];
+#pragma unroll
+                for (int k = 0; k < kMaxRun; k++)
+                    o[k] = __shfl_xor(acc[k], off, 64);
+#pragma unroll
+                for (int k = 0; k < kMaxRun; k++)
+                    acc[k] += o[k];
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < kMaxRun; k++)
+                    red[wave][k] = acc[k];
+            }
+            __syncthreads();
+            if (tid < (uint32_t)d.m) {
+                // lane k's string fields from the uniform descriptor, packed
+                // into 64-bit words (indexing its register copy by lane would
+                // go through scratch memory)
+                uint64_t epk = 0, spk = 0;
+#pragma unroll
+                for (int k = 0; k < kMaxRun; k++) {
+                    epk |= (uint64_t)d.e[k] << (8 * k);
+                    spk |= (uint64_t)(d.s[k] < 0 ? 1u : 0u) << (8 * k);
+                }
+                const int col = walsh ? (int)((epk >> (8 * tid)) & 0xffu) : (int)tid;
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    v += red[w][col];
+                if (walsh && ((spk >> (8 * tid)) & 1u))
+                    v = -v;
+                lacc[d.k0 - sk0 + (int)tid] += v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const uint32_t l = tid + (uint32_t)i * NT;
+            const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
+            phi[y] = sp[l];
+            lam[y] = sl[l];
+        }
+    }
+    // this workgroup's sums; k_grad_reduce adds the workgroups after the
+    // sweep (no cross-workgroup fence here: on a multi-XCD device a release
+    // at agent scope writes back the whole L2, sub-cube stores included)
+    __syncthreads();
+    for (int t = (int)tid; t < nstr; t += NT)
+        part[(size_t)blockIdx.x * K + sk0 + t] = lacc[t];
+}
+
+// grad[k] = 2 sum_b part[b][k] in workgroup order, for the strings of
+// blocked segments: 64 strings per workgroup (one per lane), the four waves
+// split the workgroup range with 4 loads in flight each.
+__global__ __launch_bounds__(kBlock) void k_grad_reduce(const double *__restrict__ part, int nb, int K,
+                                                        const uint8_t *__restrict__ blocked, double *grad)
+{
+    __shared__ double ws[kBlock / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = kBlock / 64;
+    const int k = blockIdx.x * 64 + lane;
+    double v = 0.0;
+    if (k < K) {
+        int b = wave;
+        for (; b + 3 * NW < nb; b += 4 * NW) {
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                t[u] = part[(size_t)(b + u * NW) * K + k];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                v += t[u];
+        }
+        for (; b < nb; b += NW)
+            v += part[(size_t)b * K + k];
+    }
+    ws[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && k < K && blocked[k]) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+            t += ws[w][lane];
+        grad[k] = 2.0 * t;
+    }
+}
 } // namespace qf
 
 // ===================================================================== host
@@ -999,9 +1229,12 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
         uint32_t cur = low;
         size_t j = i;
         int ntab = 0;
-        while (j < runs.size() && __builtin_popcount(cur | runs[j].x) <= B && ntab + (1 << runs[j].r) <= kSegTab) {
+        int nstr = 0;
+        while (j < runs.size() && __builtin_popcount(cur | runs[j].x) <= B && ntab + (1 << runs[j].r) <= kSegTab &&
+               nstr + runs[j].m <= kSegStr) {
             cur |= runs[j].x;
             ntab += 1 << runs[j].r;
+            nstr += runs[j].m;
             j++;
         }
         Segment sg;
@@ -1044,6 +1277,12 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
             }
             L.r = d.r;
             L.tab = d.tab;
+            L.k0 = d.k0;
+            L.m = d.m;
+            for (int k = 0; k < kMaxRun; k++) {
+                L.e[k] = d.e[k];
+                L.s[k] = d.s[k];
+            }
             lr.push_back(L);
         }
         sg.r1 = (int32_t)lr.size();
@@ -1063,6 +1302,13 @@ struct qf_plan {
     int block_bits = 0;                 // sub-cube size of blocked apply (0: per-run passes)
     std::vector<qf::Segment> segs;      // Q == 0: a run applied on its own (index r0)
     qf::LocalRun *d_lruns = nullptr;
+    int adj_bits = 0;                   // sub-cube size of the blocked adjoint (0: per-run passes)
+    std::vector<qf::Segment> asegs;     // segments of the blocked adjoint
+    std::vector<int> aseg_k0, aseg_nstr; // their strings (contiguous: runs are in string order)
+    qf::LocalRun *d_alruns = nullptr;
+    double *d_apart = nullptr;          // per-block string sums of the blocked adjoint [adj_grid][K]
+    uint8_t *d_ablocked = nullptr;      // 1 for strings of blocked adjoint segments
+    unsigned adj_grid = 0;
     double *d_theta = nullptr;
     double *h_theta = nullptr;  // pinned staging for theta uploads
     hipEvent_t theta_done = nullptr;
@@ -1096,7 +1342,7 @@ struct qf_plan {
             (void)hipEventDestroy(theta_done);
         if (h_theta)
             (void)hipHostFree(h_theta);
-        void *bufs[] = {d_runs, d_lruns, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+        void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs, d_vcls};
         for (void *p : bufs)
             if (p)
@@ -1240,15 +1486,40 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
     P.tiled_work = woff.back();
 }
 
+template <int B> unsigned adj_grid(int n)
+{
+    static unsigned cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0, per = 0;
+        QF_HIP(hipGetDevice(&dev));
+        QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(k_adjoint_block<B, adj_threads(B)>), adj_threads(B), 0));
+        cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
+    }
+    return (unsigned)std::min<uint64_t>(cached, 1ull << (n - B));
+}
+
 void set_block_bits(qf_plan &P, int B)
 {
     if (B != 0 && (B < 6 || B > 12 || B > P.n))
         raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
-    if (P.d_lruns)
-        QF_HIP(hipFree(P.d_lruns));
+    void *old[] = {P.d_lruns, P.d_alruns, P.d_apart, P.d_ablocked};
+    for (void *p : old)
+        if (p)
+            QF_HIP(hipFree(p));
     P.d_lruns = nullptr;
+    P.d_alruns = nullptr;
+    P.d_apart = nullptr;
+    P.d_ablocked = nullptr;
+    P.adj_grid = 0;
     P.segs.clear();
+    P.asegs.clear();
+    P.aseg_k0.clear();
+    P.aseg_nstr.clear();
     P.block_bits = B;
+    // the adjoint holds two sub-cubes (phi, lambda) in LDS: at most 2^11 each
+    P.adj_bits = B >= 10 ? std::min(B, 11) : 0;
     if (!B || P.runs.empty())
         return;
     std::vector<LocalRun> lr;
@@ -1256,6 +1527,25 @@ void set_block_bits(qf_plan &P, int B)
     P.d_lruns = dev_alloc<LocalRun>(lr.size());
     if (!lr.empty())
         QF_HIP(hipMemcpy(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun), hipMemcpyHostToDevice));
+    if (P.adj_bits) {
+        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr);
+        for (const Segment &sg : P.asegs) {
+            const int k0 = sg.Q ? lr[(size_t)sg.r0].k0 : 0;
+            P.aseg_k0.push_back(k0);
+            P.aseg_nstr.push_back(sg.Q ? lr[(size_t)sg.r1 - 1].k0 + lr[(size_t)sg.r1 - 1].m - k0 : 0);
+        }
+        P.d_alruns = dev_alloc<LocalRun>(lr.size());
+        if (!lr.empty())
+            QF_HIP(hipMemcpy(P.d_alruns, lr.data(), lr.size() * sizeof(LocalRun), hipMemcpyHostToDevice));
+        std::vector<uint8_t> blocked((size_t)P.K, 0);
+        for (size_t i = 0; i < P.asegs.size(); i++)
+            for (int t = 0; t < P.aseg_nstr[i]; t++)
+                blocked[(size_t)(P.aseg_k0[i] + t)] = 1;
+        P.d_ablocked = dev_alloc<uint8_t>((size_t)P.K);
+        QF_HIP(hipMemcpy(P.d_ablocked, blocked.data(), blocked.size(), hipMemcpyHostToDevice));
+        P.adj_grid = P.adj_bits == 10 ? adj_grid<10>(P.n) : adj_grid<11>(P.n);
+        P.d_apart = dev_alloc<double>((size_t)P.adj_grid * (size_t)P.K);
+    }
 }
 
 void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H, const int64_t *goff,
@@ -1502,15 +1792,38 @@ void launch_sigma(qf_plan &P, const double2 *psi, double2 *lam, double *dev_out,
     QF_HIP(hipGetLastError());
 }
 
+void launch_adjoint_run(qf_plan &P, double2 *phi, double2 *lam, const RunDesc &d, hipStream_t s)
+{
+    const uint64_t np = d.x ? (1ull << P.n) >> 1 : 1ull << P.n;
+    hipLaunchKernelGGL(k_adjoint_run, dim3(grid_for(np, (uint64_t)kBlock * kItems, kMaxBlocks)), dim3(kBlock), 0, s,
+                       phi, lam, np, d, P.d_tab, P.d_partials, P.d_counter, P.d_grad);
+}
+
+
 void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
 {
-    const uint64_t dim = 1ull << P.n;
-    for (size_t i = P.runs.size(); i-- > 0;) {
-        const RunDesc &d = P.runs[i];
-        const uint64_t np = d.x ? dim >> 1 : dim;
-        hipLaunchKernelGGL(k_adjoint_run, dim3(grid_for(np, (uint64_t)kBlock * kItems, kMaxBlocks)), dim3(kBlock),
-                           0, s, phi, lam, np, d, P.d_tab, P.d_partials, P.d_counter, P.d_grad);
+    if (P.adj_bits) {
+        for (size_t i = P.asegs.size(); i-- > 0;) {
+            const Segment &sg = P.asegs[i];
+            if (!sg.Q) {
+                launch_adjoint_run(P, phi, lam, P.runs[(size_t)sg.r0], s);
+                continue;
+            }
+            const int sk0 = P.aseg_k0[i], nstr = P.aseg_nstr[i];
+            if (P.adj_bits == 10)
+                hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10)>), dim3(P.adj_grid), dim3(adj_threads(10)),
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_tab, sk0, nstr, P.d_apart, (int)P.K);
+            else
+                hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11)>), dim3(P.adj_grid), dim3(adj_threads(11)),
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_tab, sk0, nstr, P.d_apart, (int)P.K);
+        }
+        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((P.K + 63) / 64)), dim3(kBlock), 0, s, P.d_apart,
+                           (int)P.adj_grid, (int)P.K, P.d_ablocked, P.d_grad);
+        QF_HIP(hipGetLastError());
+        return;
     }
+    for (size_t i = P.runs.size(); i-- > 0;)
+        launch_adjoint_run(P, phi, lam, P.runs[i], s);
     QF_HIP(hipGetLastError());
 }
 

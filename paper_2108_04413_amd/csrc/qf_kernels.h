@@ -34,6 +34,7 @@ struct GroupDesc {
 // segment, and written back.  Masks of a run are given both in the full
 // index space (for the sub-cube's fixed bits) and compressed to Q (pext).
 constexpr int kSegTab = 512;  // (cos, sin) entries of one segment, staged in LDS
+constexpr int kSegStr = 512;  // strings of one segment (blocked adjoint accumulators in LDS)
 
 struct Segment {
     uint32_t Q;      // qubits of the sub-cube
@@ -50,7 +51,10 @@ struct LocalRun {
     uint32_t b[kMaxRank];           // local GF(2) basis masks
     uint32_t z0f;                   // full-space z0
     uint32_t bf[kMaxRank];          // full-space basis masks
-    int32_t r, tab, pad0, pad1;
+    int32_t r, tab;
+    int32_t k0, m;                  // the run's strings (as in RunDesc)
+    uint8_t e[kMaxRun];
+    int8_t s[kMaxRun];
 };
 
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile

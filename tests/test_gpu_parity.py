@@ -359,3 +359,42 @@ def test_blocked_apply_20q_ansatz_matches_golden_samples(qf):
     want = np.array(gold["sample_re"]) + 1j * np.array(gold["sample_im"])
     assert np.max(np.abs(host(psi)[idx] - want)) < A_TOL
     assert plan.energy(psi) == pytest.approx(gold["energy"], abs=E_TOL)
+
+
+@pytest.mark.parametrize("B", [0, 10, 11, 12])
+def test_blocked_adjoint_matches_oracle(qf, B):
+    """Blocked reverse sweep (segments of runs undone in LDS sub-cubes of phi
+    and lambda), incl. diagonal runs and runs too wide for a sub-cube."""
+    n = 13
+    xs, zs = runs_of_terms(n, 80 + B, 150)
+    rng = np.random.default_rng(9 + B)
+    lowx = [int(v) for v in rng.choice([0, 0b1111, 0b110011, 0b101000101, 0b11], 40)]
+    xs = np.concatenate([np.array(lowx, dtype=np.uint64), xs])
+    zs = np.concatenate([rng.integers(0, 1 << n, 40).astype(np.uint64), zs])
+    th = qi.random_angles(len(xs), 90 + B, 1.0)
+    hx, hz, hc = qi.random_paulis(n, 150, 91 + B)
+    hx, hz, hc, off = grouped(hx, hz, hc)
+    occ = (1 << 6) - 1
+    plan = qf.Plan(n, qf.terms_array(xs, zs, np.ones(len(xs))), qf.terms_array(hx, hz, hc), off)
+    plan.set_block_bits(B)
+    ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+    e, g = plan.energy_grad(occ, th, ws)
+    e_o, g_o = core.energy_grad(n, occ, xs, zs, th, hx, hz, hc)
+    assert e == pytest.approx(e_o, abs=E_TOL)
+    assert np.max(np.abs(g - g_o)) < G_TOL
+
+
+@pytest.mark.parametrize("B", [10, 11])
+def test_blocked_adjoint_20q_matches_golden(qf, B):
+    """20 qubits: more sub-cubes than resident workgroups at B = 10, so
+    workgroups loop over several sub-cubes; gradient against the oracle run."""
+    gold = _golden("20q")
+    w, n, occ, H, off, A, aoff, th = _build_device_system(qf, "20q")
+    plan = qf.Plan(n, A, H, off)
+    plan.set_block_bits(B)
+    ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+    e_g, g = plan.energy_grad(occ, th, ws)
+    assert e_g == pytest.approx(gold["energy"], abs=E_TOL)
+    assert np.max(np.abs(g - np.array(gold["grad_theta"]))) < G_TOL
+    e2, g2 = plan.energy_grad(occ, th, ws)
+    assert e2 == e_g and np.array_equal(g2, g)
