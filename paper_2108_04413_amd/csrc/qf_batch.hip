@@ -42,10 +42,12 @@ struct BatchEntry {
     int32_t term0;   // first Hamiltonian string (GroupDesc ranges are instance-relative)
     int32_t theta0;  // first ansatz string (RunDesc.k0 is instance-relative)
     int32_t ticket0; // first ticket of the team
-    int32_t part0;   // partial slots: 2 * W * kMaxRun (adjoint, two buffers) + W (energy)
+    int32_t part0;   // partial slots: W * K string sums, then W energy sums
     int32_t out;     // caller index of the instance
     int32_t K;       // ansatz strings of the instance
-    int32_t pad;
+    int32_t aseg0, naseg, alr0;  // forward segments (Segment, LocalRun offsets)
+    int32_t dseg0, ndseg, dlr0;  // reverse-sweep segments
+    int32_t Bapp, Badj;          // their sub-cube sizes (qubits)
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
 
@@ -77,10 +79,17 @@ __device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target,
     }
 }
 
-// member's slice [b, e) of `units`, in whole tiles of kBlock * kItems
+// Workgroup shape of the batched kernel: 512 threads, and LDS for one
+// 2^12-amplitude sub-cube (blocked apply) or one 2^11 sub-cube of each of
+// phi and lambda (blocked adjoint), two workgroups per CU.
+constexpr int kBT = 512;
+constexpr int kBW = kBT / 64;
+constexpr int kSub = 4096;
+
+// member's slice [b, e) of `units`, in whole tiles of kBT * kItems
 __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
 {
-    const uint64_t per = (uint64_t)kBlock * kItems;
+    const uint64_t per = (uint64_t)kBT * kItems;
     const uint64_t tiles = (units + per - 1) / per;
     const uint64_t tpm = (tiles + (uint64_t)W - 1) / (uint64_t)W;
     b = (uint64_t)rank * tpm * per;
@@ -93,7 +102,7 @@ __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, ui
 
 __device__ void load_table(const RunDesc &d, const double *__restrict__ theta, double2 *tab)
 {
-    for (int u = threadIdx.x; u < (1 << d.r); u += kBlock) {
+    for (int u = threadIdx.x; u < (1 << d.r); u += kBT) {
         double th = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxRun; k++) {
@@ -109,9 +118,241 @@ __device__ void load_table(const RunDesc &d, const double *__restrict__ theta, d
     __syncthreads();
 }
 
+// (cos, sin) entries of a segment's runs from theta: run d's entry u goes to
+// tab[d.tab - tab0 + u] (the same values as load_table for that run)
+__device__ void seg_tables(const LocalRun *__restrict__ lr, int r0, int r1, int tab0,
+                           const double *__restrict__ theta, double2 *tab)
+{
+    for (int ri = r0; ri < r1; ri++) {
+        const LocalRun &d = lr[ri];
+        const uint32_t u = threadIdx.x;
+        if (u < (1u << d.r)) {
+            double th = 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++) {
+                if (k < d.m) {
+                    const double v = (double)d.s[k] * theta[d.k0 + k];
+                    th += (__popc(u & d.e[k]) & 1) ? -v : v;
+                }
+            }
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            tab[d.tab - tab0 + (int)u] = make_double2(cs, sn);
+        }
+    }
+}
+
+// offsets of the sub-cube's rows: the qubits of Q above q0, spread
+__device__ void seg_hoff(const Segment &sg, uint32_t *hoff)
+{
+    if (threadIdx.x < (1u << sg.nhi)) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (q < sg.nhi)
+                o |= ((threadIdx.x >> q) & 1u) << sg.hi[q];
+        hoff[threadIdx.x] = o;
+    }
+}
+
+// sub-cube sc: its index bits scattered into the qubits outside Q
+__device__ __forceinline__ uint32_t subcube_base(uint32_t sc, uint32_t Q, int n)
+{
+    uint32_t base = 0, k = 0;
+    for (int p = 0; p < n; p++)
+        if (!((Q >> p) & 1u)) {
+            base |= ((sc >> k) & 1u) << p;
+            k++;
+        }
+    return base;
+}
+
+// Apply a segment's runs to one 2^B sub-cube held in st (LDS).
+__device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const Segment &sg,
+                          const LocalRun *__restrict__ lr, const double2 *tab, const uint32_t *hoff, double2 *st)
+{
+    const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
+    __syncthreads();  // the previous sub-cube's LDS image is written back
+    for (uint32_t l = threadIdx.x; l < NB; l += kBT)
+        st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
+    for (int ri = sg.r0; ri < sg.r1; ri++) {
+        const LocalRun d = lr[ri];
+        const int toff = d.tab - sg.tab0;
+        uint32_t bm[kMaxRank];
+        uint32_t pb = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxRank; q++) {
+            bm[q] = q < d.r ? d.b[q] : 0u;
+            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
+        }
+        const uint32_t pz = par(base & d.z0f);
+        __syncthreads();
+        if (d.x) {
+            for (uint32_t j = threadIdx.x; j < NB / 2; j += kBT) {
+                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y1 & bm[q]) << q;
+                const double2 cs = tab[toff + u];
+                const double c = cs.x, s = cs.y;
+                const double2 a = st[y1], b = st[y2];
+                const double2 pbv = mul_ik((d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u, b);
+                const double2 pav = mul_ik((d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u, a);
+                st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
+                st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
+            }
+        } else {
+            for (uint32_t y = threadIdx.x; y < NB; y += kBT) {
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y & bm[q]) << q;
+                const double2 cs = tab[toff + u];
+                const double c = cs.x, s = cs.y;
+                const double2 v = st[y];
+                st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t l = threadIdx.x; l < NB; l += kBT)
+        psi[base | (l & lomask) | hoff[l >> sg.q0]] = st[l];
+}
+
+// Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and
+// lambda (sl), adding each run's 2 Im <lambda|P_k|phi> / 2 per string to
+// lacc[k - sk0] before the run is undone.
+__device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, int B, uint32_t base,
+                            const Segment &sg, const LocalRun *__restrict__ lr, const double2 *tab,
+                            const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc, double (*red)[kMaxRun],
+                            int sk0)
+{
+    const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
+    const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    __syncthreads();  // the previous sub-cube's LDS images are written back
+    for (uint32_t l = threadIdx.x; l < NB; l += kBT) {
+        const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
+        sp[l] = phi[y];
+        sl[l] = lam[y];
+    }
+    for (int ri = sg.r1 - 1; ri >= sg.r0; ri--) {
+        const LocalRun d = lr[ri];
+        const int toff = d.tab - sg.tab0;
+        uint32_t bm[kMaxRank];
+        uint32_t pb = 0;
+#pragma unroll
+        for (int q = 0; q < kMaxRank; q++) {
+            bm[q] = q < d.r ? d.b[q] : 0u;
+            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
+        }
+        const uint32_t pz = par(base & d.z0f);
+        // string k's weight is s_k (-1)^popcount(u & e_k): for rank <= 3 the
+        // pass sums the 8 Walsh terms (-1)^popcount(u & e) q and string k
+        // takes s_k times term e_k; otherwise acc[k] is string k's own sum
+        const bool walsh = d.r <= 3;
+        uint32_t em[kMaxRun], sneg[kMaxRun];
+        double acc[kMaxRun];
+#pragma unroll
+        for (int k = 0; k < kMaxRun; k++) {
+            em[k] = d.e[k];
+            sneg[k] = d.s[k] < 0 ? 1u : 0u;
+            acc[k] = 0.0;
+        }
+        auto accumulate = [&](uint32_t u, double q) __attribute__((always_inline)) {
+            if (walsh) {
+                const uint32_t b1 = u << 31, b2 = (u >> 1) << 31, b4 = (u >> 2) << 31;
+                const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
+#pragma unroll
+                for (int e = 0; e < kMaxRun; e++)
+                    acc[e] += __hiloint2double(__double2hiint(q) ^ (int)sb[e], __double2loint(q));
+            } else {
+#pragma unroll
+                for (int k = 0; k < kMaxRun; k++)
+                    acc[k] += flip(q, (__popc(u & em[k]) ^ sneg[k]) & 1u);
+            }
+        };
+        __syncthreads();  // the previous run's updates are visible
+        if (d.x) {
+            for (uint32_t j = threadIdx.x; j < NB / 2; j += kBT) {
+                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y1 & bm[q]) << q;
+                const double2 cs = tab[toff + u];
+                const double c = cs.x, s = cs.y;
+                const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+                const uint32_t k1 = (d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u;
+                const uint32_t k2 = (d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u;
+                const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
+                const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
+                sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
+                sp[y2] = make_double2(c * b.x - s * wa.y, c * b.y + s * wa.x);
+                const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
+                sl[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
+                sl[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
+                accumulate(u, q);
+            }
+        } else {
+            for (uint32_t y = threadIdx.x; y < NB; y += kBT) {
+                uint32_t u = pb;
+#pragma unroll
+                for (int q = 0; q < kMaxRank; q++)
+                    u ^= par(y & bm[q]) << q;
+                const double2 cs = tab[toff + u];
+                const double c = cs.x, s = cs.y;
+                const double2 a = sp[y], la = sl[y];
+                const double q = la.x * a.y - la.y * a.x;
+                sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
+                sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+                accumulate(u, q);
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            double o[kMaxRun];
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++)
+                o[k] = __shfl_xor(acc[k], off, 64);
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++)
+                acc[k] += o[k];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++)
+                red[wave][k] = acc[k];
+        }
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)d.m) {
+            uint64_t epk = 0, spk = 0;
+#pragma unroll
+            for (int k = 0; k < kMaxRun; k++) {
+                epk |= (uint64_t)d.e[k] << (8 * k);
+                spk |= (uint64_t)(d.s[k] < 0 ? 1u : 0u) << (8 * k);
+            }
+            const int col = walsh ? (int)((epk >> (8 * threadIdx.x)) & 0xffu) : (int)threadIdx.x;
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBW; w++)
+                v += red[w][col];
+            if (walsh && ((spk >> (8 * threadIdx.x)) & 1u))
+                v = -v;
+            lacc[d.k0 - sk0 + (int)threadIdx.x] += v;
+        }
+    }
+    __syncthreads();
+    for (uint32_t l = threadIdx.x; l < NB; l += kBT) {
+        const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
+        phi[y] = sp[l];
+        lam[y] = sl[l];
+    }
+}
+
 template <int M> __device__ void block_sum(double (&v)[M], double *out)
 {
-    __shared__ double lds[kBlock / 64][kMaxRun];
+    __shared__ double lds[kBW][kMaxRun];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < M; k++) {
@@ -124,7 +365,7 @@ template <int M> __device__ void block_sum(double (&v)[M], double *out)
     __syncthreads();
     if (threadIdx.x < M) {
         double s = 0.0;
-        for (int w = 0; w < kBlock / 64; w++)
+        for (int w = 0; w < kBW; w++)
             s += lds[w][threadIdx.x];
         out[threadIdx.x] = s;
     }
@@ -133,14 +374,14 @@ template <int M> __device__ void block_sum(double (&v)[M], double *out)
 
 __device__ void pass_prepare(double2 *__restrict__ psi, uint64_t b, uint64_t e, uint32_t occ)
 {
-    for (uint64_t y = b + threadIdx.x; y < e; y += kBlock)
+    for (uint64_t y = b + threadIdx.x; y < e; y += kBT)
         psi[y] = make_double2(y == occ ? 1.0 : 0.0, 0.0);
 }
 
 __device__ void pass_apply(double2 *__restrict__ psi, const RunDesc &d, const double2 *tab, uint64_t b,
                            uint64_t e)
 {
-    const uint64_t per = (uint64_t)kBlock * kItems;
+    const uint64_t per = (uint64_t)kBT * kItems;
     const bool diag = d.x == 0;
     for (uint64_t j0 = b; j0 < e; j0 += per) {
         uint32_t y[kItems];
@@ -148,7 +389,7 @@ __device__ void pass_apply(double2 *__restrict__ psi, const RunDesc &d, const do
         bool ok[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; i++) {
-            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBT;
             ok[i] = j < e;
             const uint32_t jj = (uint32_t)(ok[i] ? j : b);
             y[i] = diag ? jj : insert0(jj, d.hbit);
@@ -178,7 +419,7 @@ __device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restric
                              const GroupDesc *__restrict__ groups, int G, const uint32_t *__restrict__ zs,
                              const double *__restrict__ cs, uint64_t b, uint64_t e)
 {
-    const uint64_t per = (uint64_t)kBlock * kItems;
+    const uint64_t per = (uint64_t)kBT * kItems;
     double acc = 0.0;
     for (uint64_t j0 = b; j0 < e; j0 += per) {
         uint32_t y[kItems];
@@ -186,7 +427,7 @@ __device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restric
         double2 l[kItems];
 #pragma unroll
         for (int i = 0; i < kItems; i++) {
-            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBT;
             ok[i] = j < e;
             y[i] = (uint32_t)(ok[i] ? j : b);
             l[i] = make_double2(0.0, 0.0);
@@ -223,12 +464,12 @@ __device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restric
 __device__ void pass_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, const RunDesc &d,
                              const double2 *tab, uint64_t b, uint64_t e, double (&acc)[kMaxRun])
 {
-    const uint64_t per = (uint64_t)kBlock * kItems;
+    const uint64_t per = (uint64_t)kBT * kItems;
     const bool diag = d.x == 0;
     for (uint64_t j0 = b; j0 < e; j0 += per) {
 #pragma unroll
         for (int i = 0; i < kItems; i++) {
-            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBlock;
+            const uint64_t j = j0 + threadIdx.x + (uint64_t)i * kBT;
             if (j >= e)
                 break;
             const uint32_t y1 = diag ? (uint32_t)j : insert0((uint32_t)j, d.hbit);
@@ -273,18 +514,21 @@ __global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, un
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
-                                                  unsigned total_tickets, const RunDesc *__restrict__ runs,
-                                                  const GroupDesc *__restrict__ groups,
-                                                  const uint32_t *__restrict__ zs, const double *__restrict__ cs,
-                                                  const double *__restrict__ theta, double2 *states,
-                                                  double *partials, unsigned *sync, unsigned *ticket,
-                                                  unsigned *err, double *E_out, double *grad_out,
-                                                  unsigned spin_limit, double *mb_E, double *mb_grad,
-                                                  unsigned *mb_flag)
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
+                                               unsigned total_tickets, const RunDesc *__restrict__ runs,
+                                               const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
+                                               const GroupDesc *__restrict__ groups, const uint32_t *__restrict__ zs,
+                                               const double *__restrict__ cs, const double *__restrict__ theta,
+                                               double2 *states, double *partials, unsigned *sync, unsigned *ticket,
+                                               unsigned *err, double *E_out, double *grad_out, unsigned spin_limit,
+                                               double *mb_E, double *mb_grad, unsigned *mb_flag)
 {
     __shared__ int s_entry, s_rank;
-    __shared__ double2 s_tab[1 << kMaxRank];
+    __shared__ double2 s_sub[kSub];
+    __shared__ double2 s_tab[kSegTab];
+    __shared__ uint32_t s_hoff[64];
+    __shared__ double s_lacc[kSegStr];
+    __shared__ double s_red[kBW][kMaxRun];
     __shared__ double s_part[kMaxRun];
     for (;;) {
         if (threadIdx.x == 0) {
@@ -311,12 +555,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
         if (ei < 0)
             break;
         const BatchEntry en = entries[ei];
-        const int W = en.W;
-        const uint64_t dim = 1ull << en.n;
+        const int W = en.W, n = en.n;
+        const uint64_t dim = 1ull << n;
         double2 *phi = states + en.state0;
         double2 *lam = phi + dim;
         const double *th = theta + en.theta0;
-        double *part = partials + en.part0;
+        double *gpart = partials + en.part0;     // [W][K] string sums
+        double *epart = gpart + (size_t)W * en.K; // [W] energy sums
         unsigned *ctr = sync + ei;
         unsigned epoch = 0;
         uint64_t b, e;
@@ -325,11 +570,22 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
         pass_prepare(phi, b, e, en.occ);
         team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
 
-        for (int r = 0; r < en.nruns; r++) {
-            const RunDesc d = runs[en.run0 + r];
-            load_table(d, th, s_tab);
-            member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
-            pass_apply(phi, d, s_tab, b, e);
+        // forward: segments of runs on sub-cubes, members take sub-cubes rank, rank + W, ...
+        for (int si = 0; si < en.naseg; si++) {
+            const Segment sg = segs[en.aseg0 + si];
+            if (!sg.Q) {
+                const RunDesc d = runs[en.run0 + sg.r0];
+                load_table(d, th, s_tab);
+                member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
+                pass_apply(phi, d, s_tab, b, e);
+            } else {
+                const LocalRun *lr = lruns + en.alr0;
+                seg_tables(lr, sg.r0, sg.r1, sg.tab0, th, s_tab);
+                seg_hoff(sg, s_hoff);
+                const uint32_t nsub = 1u << (n - en.Bapp);
+                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
+                    sub_apply(phi, en.Bapp, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub);
+            }
             team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
         }
 
@@ -338,36 +594,54 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
             double v[1] = {pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e)};
             block_sum<1>(v, s_part);
             if (threadIdx.x == 0)
-                part[2 * W * kMaxRun + rank] = s_part[0];
+                epart[rank] = s_part[0];
         }
         team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
 
-        for (int r = en.nruns - 1; r >= 0; r--) {
-            const RunDesc d = runs[en.run0 + r];
-            load_table(d, th, s_tab);
-            member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
-            double acc[kMaxRun];
+        // reverse sweep: segments last first; each member leaves its string sums in gpart[rank]
+        for (int si = en.ndseg - 1; si >= 0; si--) {
+            const Segment sg = segs[en.dseg0 + si];
+            if (!sg.Q) {
+                const RunDesc d = runs[en.run0 + sg.r0];
+                load_table(d, th, s_tab);
+                member_slice(d.x ? dim >> 1 : dim, W, rank, b, e);
+                double acc[kMaxRun];
 #pragma unroll
-            for (int k = 0; k < kMaxRun; k++)
-                acc[k] = 0.0;
-            pass_adjoint(phi, lam, d, s_tab, b, e, acc);
-            block_sum<kMaxRun>(acc, s_part);
-            double *buf = part + (r & 1) * W * kMaxRun;
-            if (threadIdx.x < kMaxRun)
-                buf[rank * kMaxRun + threadIdx.x] = s_part[threadIdx.x];
-            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
-            if (rank == 0 && threadIdx.x < d.m) {
-                double s = 0.0;
-                for (int w = 0; w < W; w++)
-                    s += buf[w * kMaxRun + threadIdx.x];
-                grad_out[en.theta0 + d.k0 + threadIdx.x] = 2.0 * s;
+                for (int k = 0; k < kMaxRun; k++)
+                    acc[k] = 0.0;
+                pass_adjoint(phi, lam, d, s_tab, b, e, acc);
+                block_sum<kMaxRun>(acc, s_part);
+                if (threadIdx.x < (uint32_t)d.m)
+                    gpart[(size_t)rank * en.K + d.k0 + threadIdx.x] = s_part[threadIdx.x];
+            } else {
+                const LocalRun *lr = lruns + en.dlr0;
+                const int sk0 = lr[sg.r0].k0;
+                const int nstr = lr[sg.r1 - 1].k0 + lr[sg.r1 - 1].m - sk0;
+                seg_tables(lr, sg.r0, sg.r1, sg.tab0, th, s_tab);
+                seg_hoff(sg, s_hoff);
+                for (int t = (int)threadIdx.x; t < nstr; t += kBT)
+                    s_lacc[t] = 0.0;
+                const uint32_t nsub = 1u << (n - en.Badj);
+                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
+                    sub_adjoint(phi, lam, en.Badj, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub,
+                                s_sub + (kSub / 2), s_lacc, s_red, sk0);
+                __syncthreads();
+                for (int t = (int)threadIdx.x; t < nstr; t += kBT)
+                    gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];
             }
+            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
         }
         if (rank == 0) {
+            for (int k = threadIdx.x; k < en.K; k += kBT) {
+                double s = 0.0;
+                for (int w = 0; w < W; w++)
+                    s += gpart[(size_t)w * en.K + k];
+                grad_out[en.theta0 + k] = 2.0 * s;
+            }
             if (threadIdx.x == 0) {
                 double s = 0.0;
                 for (int w = 0; w < W; w++)
-                    s += part[2 * W * kMaxRun + w];
+                    s += epart[w];
                 E_out[en.out] = s;
                 if (mb_E)
                     mb_E[en.out] = s;
@@ -375,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BatchEntry *__restrict__
             if (mb_flag) {
                 // per-instance completion: results to host memory, then the flag
                 __syncthreads();
-                for (int k = threadIdx.x; k < en.K; k += kBlock)
+                for (int k = threadIdx.x; k < en.K; k += kBT)
                     mb_grad[en.theta0 + k] = grad_out[en.theta0 + k];
                 __threadfence_system();
                 __syncthreads();
@@ -406,6 +680,8 @@ struct qf_batch {
     // device data (owned or carved from the arena)
     qf::BatchEntry *d_entries = nullptr;
     qf::RunDesc *d_runs = nullptr;
+    qf::Segment *d_segs = nullptr;
+    qf::LocalRun *d_lruns = nullptr;
     qf::GroupDesc *d_groups = nullptr;
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
@@ -468,7 +744,7 @@ unsigned resident_grid()
     int dev = 0, cus = 0, per = 0;
     QF_HIP(hipGetDevice(&dev));
     QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k_batch), kBlock, 0));
+    QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k_batch), kBT, 0));
     if (per < 1)
         per = 1;
     return (unsigned)(cus * per);
@@ -478,6 +754,8 @@ unsigned resident_grid()
 struct BatchHost {
     std::vector<BatchEntry> ent;
     std::vector<RunDesc> runs;
+    std::vector<Segment> segs;
+    std::vector<LocalRun> lruns;
     std::vector<GroupDesc> groups;
     std::vector<uint32_t> zs;
     std::vector<double> cs;
@@ -511,9 +789,10 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
     B.K_total = B.koff[(size_t)count];
     B.grid = resident_grid();
     for (int i = 0; i < count; i++) {
-        // a team never exceeds one 1024-pair tile per member or the grid
+        // a team never exceeds one 2048-pair tile (one 2^12 sub-cube) per
+        // member or the grid
         const int n = n_qubits[i];
-        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBlock * kItems));
+        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBT * kItems));
         B.W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B.W[(size_t)i], tiles, (int64_t)B.grid});
     }
     std::vector<int> order((size_t)count);
@@ -531,9 +810,30 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::vector<uint32_t> z;
         std::vector<double> c;
         build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
+        // forward segments on 2^min(n,12) sub-cubes, reverse on 2^min(n,11)
+        // (phi and lambda share the LDS image)
+        const int Bapp = std::min(n, 12), Badj = std::min(n, 11);
+        std::vector<Segment> sa, sd;
+        std::vector<LocalRun> la, ld;
+        if (!r.empty()) {
+            build_segments(r, n, Bapp, std::min(6, Bapp), sa, la);
+            build_segments(r, n, Badj, std::min(6, Badj), sd, ld);
+        }
         BatchEntry e;
         std::memset(&e, 0, sizeof e);
         e.n = n;
+        e.Bapp = Bapp;
+        e.Badj = Badj;
+        e.aseg0 = (int32_t)T.segs.size();
+        e.naseg = (int32_t)sa.size();
+        e.alr0 = (int32_t)T.lruns.size();
+        e.dseg0 = e.aseg0 + e.naseg;
+        e.ndseg = (int32_t)sd.size();
+        e.dlr0 = e.alr0 + (int32_t)la.size();
+        T.segs.insert(T.segs.end(), sa.begin(), sa.end());
+        T.segs.insert(T.segs.end(), sd.begin(), sd.end());
+        T.lruns.insert(T.lruns.end(), la.begin(), la.end());
+        T.lruns.insert(T.lruns.end(), ld.begin(), ld.end());
         e.W = B.W[(size_t)i];
         e.nruns = (int32_t)r.size();
         e.G = (int32_t)gd.size();
@@ -554,8 +854,9 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.cs.insert(T.cs.end(), c.begin(), c.end());
         T.state_amps += 2ull << n;
         T.tickets += e.W;
-        T.parts += 2 * e.W * kMaxRun + e.W;
-        if (T.zs.size() > (size_t)INT32_MAX || T.tickets > INT32_MAX)
+        T.parts += (int64_t)e.W * e.K + e.W;
+        if (T.zs.size() > (size_t)INT32_MAX || T.tickets > INT32_MAX || T.parts > INT32_MAX ||
+            T.lruns.size() > (size_t)INT32_MAX)
             raise(QF_E_ARG, "batch too large");
     }
     B.nentries = (int)T.ent.size();
@@ -566,21 +867,22 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[13];
+    size_t off[15];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[13] = {
+    const size_t sizes[15] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
         (size_t)T.parts * sizeof(double), T.ent.size() * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
-        (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double)};
+        (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
+        std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 13; i++) {
+    for (int i = 0; i < 15; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -603,6 +905,8 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_err = (unsigned *)(base + L.off[10]);
     B.d_E = (double *)(base + L.off[11]);
     B.d_grad = (double *)(base + L.off[12]);
+    B.d_segs = (Segment *)(base + L.off[13]);
+    B.d_lruns = (LocalRun *)(base + L.off[14]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -616,6 +920,11 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
     QF_HIP(hipMemcpyAsync(B.d_entries, T.ent.data(), T.ent.size() * sizeof(BatchEntry), hipMemcpyHostToDevice, s));
     if (!T.runs.empty())
         QF_HIP(hipMemcpyAsync(B.d_runs, T.runs.data(), T.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, s));
+    if (!T.segs.empty())
+        QF_HIP(hipMemcpyAsync(B.d_segs, T.segs.data(), T.segs.size() * sizeof(Segment), hipMemcpyHostToDevice, s));
+    if (!T.lruns.empty())
+        QF_HIP(hipMemcpyAsync(B.d_lruns, T.lruns.data(), T.lruns.size() * sizeof(LocalRun), hipMemcpyHostToDevice,
+                              s));
     QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
                           s));
     QF_HIP(hipMemcpyAsync(B.d_z, T.zs.data(), T.zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
@@ -631,8 +940,8 @@ void batch_kernels(qf_batch &B, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
-    hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBlock), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+    hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }

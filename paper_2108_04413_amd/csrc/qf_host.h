@@ -46,4 +46,11 @@ std::vector<RunDesc> make_runs(const qf_term *T, int64_t K, int &tab_entries);
 void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::vector<GroupDesc> &gd,
                   std::vector<uint32_t> &zs, std::vector<double> &cs);
 
+// Greedy split of a run sequence into segments whose flip masks fit one set
+// of B qubits containing qubits 0..q0-1 (see qf_device.hip); appends the
+// segments' LocalRuns to lr (cleared first).  A Segment with Q == 0 holds
+// one run too wide for a sub-cube; its r0 indexes `runs`.
+void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std::vector<Segment> &segs,
+                    std::vector<LocalRun> &lr);
+
 } // namespace qf
