@@ -57,7 +57,7 @@ def _instances(qf, qi, n_qubits: int, count: int, seed0: int):
     return out
 
 
-def tune(ns=(12, 14, 16, 18, 20, 22), count: int = 43, reps: int = 2, max_team: int = 256,
+def tune(ns=(12, 14, 16, 18, 20, 22, 24), count: int = 43, reps: int = 2, max_team: int = 256,
          log=print) -> dict:
     import paper_2108_04413_amd as qf
     sys.path.insert(0, os.path.dirname(HERE))
@@ -67,7 +67,7 @@ def tune(ns=(12, 14, 16, 18, 20, 22), count: int = 43, reps: int = 2, max_team: 
     for n in ns:
         insts = _instances(qf, qi, n, count, 9000 + 100 * n)
         thetas = [d["theta"] for d in insts]
-        tiles = max(1, (1 << (n - 1)) // 1024)
+        tiles = max(1, (1 << (n - 1)) // 2048)  # the library's clamp: one 2^12 sub-cube per member
         # a single workgroup per instance is hopeless beyond 20 qubits
         w_min = 1 << max(0, n - 20)
         cands = [w for w in (1, 2, 4, 8, 16, 32, 64, 128, 256) if w_min <= w <= min(tiles, max_team)]
@@ -97,7 +97,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--count", type=int, default=43)
-    ap.add_argument("--ns", default="12,14,16,18,20,22")
+    ap.add_argument("--ns", default="12,14,16,18,20,22,24")
     ap.add_argument("--merge", action="store_true", help="update the existing table instead of replacing it")
     args = ap.parse_args()
     res = tune(tuple(int(v) for v in args.ns.split(",")), count=args.count,

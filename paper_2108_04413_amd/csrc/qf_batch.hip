@@ -785,9 +785,25 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         B.koff[(size_t)i + 1] = B.koff[(size_t)i] + K[i];
         B.nq[(size_t)i] = n;
         B.W[(size_t)i] = (team && team[i] > 0) ? team[i] : default_team(n);
+        if (team && team[i] < 0 && group_off[i] && n_groups[i] >= 1 && group_off[i][n_groups[i]] < 0)
+            raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad group offsets");
     }
     B.K_total = B.koff[(size_t)count];
     B.grid = resident_grid();
+    // team[i] < 0: share the grid by work, 2^n (K + Hamiltonian strings),
+    // among the instances that ask for it, with at least -team[i] members
+    if (team) {
+        double total = 0.0;
+        for (int i = 0; i < count; i++)
+            if (team[i] < 0)
+                total += std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
+        for (int i = 0; i < count; i++)
+            if (team[i] < 0) {
+                const double w = std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
+                const int share = (int)std::min<double>((double)B.grid, std::floor((double)B.grid * w / total));
+                B.W[(size_t)i] = std::max(-team[i], share);
+            }
+    }
     for (int i = 0; i < count; i++) {
         // a team never exceeds one 2048-pair tile (one 2^12 sub-cube) per
         // member or the grid

@@ -52,6 +52,7 @@ class Request:
     t_admit: float | None = None
     t_done: float | None = None
     footprint: int = 0
+    team: int = 0  # workgroups the request's instance ran with
 
 
 class RangeAllocator:
@@ -97,7 +98,9 @@ class Arena(RangeAllocator):
         self.base = (self.buf.data_ptr() + ALIGN - 1) // ALIGN * ALIGN
 
 
-def _arrays(reqs, team_table):
+def _arrays(reqs, team_table, share: bool = False):
+    """C arrays of a wave.  share: ask the library to split the resident grid
+    by work (team < 0), with the table's team size as each floor."""
     c = len(reqs)
     keep = [np.ascontiguousarray(r.off, dtype=np.int64) for r in reqs]
     n = (ctypes.c_int * c)(*[r.n for r in reqs])
@@ -107,13 +110,22 @@ def _arrays(reqs, team_table):
     H = (ctypes.c_void_p * c)(*[ptr(r.H) for r in reqs])
     O = (ctypes.c_void_p * c)(*[ptr(o) for o in keep])
     G = (ctypes.c_int64 * c)(*[len(o) - 1 for o in keep])
-    T = (ctypes.c_int * c)(*[int(team_table.get(r.n, 0)) if team_table else 0 for r in reqs])
+    base = [int(team_table.get(r.n, 0)) if team_table else 0 for r in reqs]
+    T = (ctypes.c_int * c)(*[-max(1, w) if share else w for w in base])
     return (c, n, occ, A, K, H, O, G, T), keep
 
 
-def footprint(reqs, team_table=None) -> int:
-    """Exact arena bytes a wave of these requests needs."""
-    args, keep = _arrays(reqs, team_table)
+def default_team_table() -> dict:
+    """The tuned team sizes for this device ({} if none match it)."""
+    from .autotune import device_arch, load_table
+    return load_table(device_arch()) or {}
+
+
+def footprint(reqs, team_table=None, share: bool = False) -> int:
+    """Exact arena bytes a wave of these requests needs (with the same team
+    policy as the launch).  With share, a request's team in a wave is never
+    larger than alone, so footprint([r], ..., share=True) bounds its part."""
+    args, keep = _arrays(reqs, team_table, share)
     need = ctypes.c_int64()
     check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "qf_batch_create_arena(size)")
     return need.value
@@ -140,12 +152,12 @@ def _view(addr: int, ctype, count: int) -> np.ndarray:
 
 class Server:
     def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None,
-                 mailbox_bytes: int = 32 << 20):
+                 mailbox_bytes: int = 32 << 20, share: bool = True):
         import torch
         if team_table is None:
-            from .autotune import device_arch, load_table
-            team_table = load_table(device_arch()) or {}
+            team_table = default_team_table()
         self.team = team_table
+        self.share = share  # split the grid among a wave's requests by work
         self.arena = Arena(arena_bytes)
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.busy = [None] * slots
@@ -170,7 +182,7 @@ class Server:
             self.close()
 
     def _launch(self, reqs, slot, now):
-        args, keep = _arrays(reqs, self.team)
+        args, keep = _arrays(reqs, self.team, self.share)
         need = ctypes.c_int64()
         check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "arena size")
         rng = self.arena.alloc(need.value)
@@ -180,6 +192,10 @@ class Server:
         st = stream_handle(self.streams[slot])
         check(lib.qf_batch_create_arena(*args, ctypes.c_void_p(self.arena.base + rng[0]), rng[1],
                                         ctypes.byref(need), st, ctypes.byref(h)), "qf_batch_create_arena")
+        teams = (ctypes.c_int * len(reqs))()
+        check(lib.qf_batch_info(h, teams, None, None), "qf_batch_info")
+        for r, w in zip(reqs, teams):
+            r.team = int(w)
         theta = np.ascontiguousarray(np.concatenate([r.theta for r in reqs]), dtype=np.float64)
         keep.append(theta)
         mb = self.mailbox[slot].value
@@ -217,7 +233,7 @@ class Server:
     def serve(self, requests, poll_s: float = 50e-6):
         """Replay `requests` (sorted by arrival, seconds from start).  Returns stats."""
         for r in requests:
-            r.footprint = r.footprint or footprint([r], self.team)
+            r.footprint = r.footprint or footprint([r], self.team, self.share)
             if r.footprint > self.arena.nbytes:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena has {self.arena.nbytes}")
         pending = []

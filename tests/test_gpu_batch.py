@@ -64,6 +64,22 @@ def test_batch_teams_match_oracle(qf, team):
         check_vs_oracle(d, e, g)
 
 
+def test_batch_shared_teams(qf):
+    """team < 0 splits the grid by work: a lone instance takes every sub-cube
+    it can use; in a mix the large instance gets the larger share."""
+    big, small = instance(qf, 8, 8, 61), instance(qf, 6, 6, 62)  # 16 and 12 qubits
+    alone = qf.Batch([big], team=[-1])
+    assert alone.info()["team"] == [16]  # 2^(16-12) sub-cubes per segment
+    mixed = qf.Batch([big, small], team=[-1, -1])
+    wb, ws = mixed.info()["team"]
+    assert wb == 16 and ws == 1
+    E, grads = mixed.run([big["theta"], small["theta"]], use_graph=False)
+    for d, e, g in zip((big, small), E, grads):
+        check_vs_oracle(d, e, g)
+    Ea, ga = alone.run([big["theta"]], use_graph=False)
+    assert Ea[0] == E[0] and np.array_equal(ga[0], grads[0])
+
+
 def test_batch_18q_instance_matches_oracle(qf):
     d = instance(qf, 9, 9, 2042)
     B = qf.Batch([d])

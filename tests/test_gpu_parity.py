@@ -198,6 +198,32 @@ def test_sigma_matches_oracle(qf):
     assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
 
 
+@pytest.mark.parametrize("real_only", [False, True])
+def test_sigma_17q_matches_oracle(qf, real_only):
+    """lambda = H psi at 17 qubits, with and without imaginary-phase strings
+    (odd number of Y): many groups, high flip bits and the diagonal group."""
+    n = 17
+    xs, zs, cs = qi.random_paulis(n, 900, 33)
+    rng = np.random.default_rng(34)
+    # strings with low flip masks only, so classes hold several groups
+    lx = rng.integers(0, 1 << 11, 300).astype(np.uint64)
+    lz = rng.integers(0, 1 << n, 300).astype(np.uint64)
+    xs, zs = np.concatenate([xs, lx, np.zeros(20, np.uint64)]), np.concatenate([zs, lz, lz[:20]])
+    cs = np.concatenate([cs, rng.normal(size=320)])
+    if real_only:
+        keep = np.array([bin(int(x) & int(z)).count("1") % 2 == 0 for x, z in zip(xs, zs)])
+        xs, zs, cs = xs[keep], zs[keep], cs[keep]
+    xs, zs, cs, off = grouped(xs, zs, cs)
+    psi0 = qi.random_state(n, 35)
+    plan = qf.Plan(n, None, qf.terms_array(xs, zs, cs), off)
+    assert plan.info()["tile_bits"] == -11
+    lam = torch.empty_like(dev(psi0))
+    e = plan.sigma(dev(psi0), lam)
+    want = core.sigma(psi0, n, xs, zs, cs)
+    assert np.max(np.abs(host(lam) - want)) < 1e-11
+    assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
+
+
 def test_plan_matches_one_shot_and_is_deterministic(qf):
     w, n, occ, (x, z, c, off), (ax, az, ac, aoff, th) = system("8q")
     H = qf.terms_array(x, z, c)

@@ -42,7 +42,7 @@ def test_serve_mix_equals_alone_oracle_and_plain(qf):
     assert st["requests"] == 24 and st["waves"] >= 4
     assert st["max_waves_in_flight"] == 2
     for r in reqs:
-        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        e, g = alone(qf, r, r.team)
         assert e == r.E and np.array_equal(g, r.grad)
     for r in reqs[:6]:
         e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
@@ -58,12 +58,12 @@ def test_serve_mix_equals_alone_oracle_and_plain(qf):
 def test_serve_small_arena_admits_one_at_a_time(qf):
     from paper_2108_04413_amd import serve
     reqs = serve.make_requests(qf, qi, trace(6, 0.0, (16,), seed=3))
-    need = max(serve.footprint([r]) for r in reqs)
+    need = max(serve.footprint([r], serve.default_team_table(), share=True) for r in reqs)
     srv = serve.Server(arena_bytes=need + 4096, slots=2, max_wave=8)
     st = srv.serve(reqs)
     assert st["mean_wave_size"] == 1.0 and st["max_waves_in_flight"] == 1
     for r in reqs:
-        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        e, g = alone(qf, r, r.team)
         assert e == r.E and np.array_equal(g, r.grad)
 
 
@@ -87,6 +87,6 @@ def test_short_requests_complete_before_long_ones_in_a_wave(qf):
     big, small = reqs[0], reqs[1:]
     assert max(r.t_done for r in small) < big.t_done
     for r in reqs:
-        e, g = alone(qf, r, srv.team.get(r.n, 0))
+        e, g = alone(qf, r, r.team)
         assert e == r.E and np.array_equal(g, r.grad)
     srv.close()
