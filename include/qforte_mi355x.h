@@ -205,11 +205,12 @@ int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, v
  *   occ_mask[i], ansatz A[i] (K[i] strings, host), grouped Hamiltonian H[i]
  *   with group_off[i] (n_groups[i] groups, host).  team (may be NULL) gives
  *   the number of workgroups that cooperate on instance i (clamped to the
- *   resident grid and to one 2^12-amplitude sub-cube per workgroup, i.e.
- *   2^(n-12)); NULL, or team[i] == 0, uses the built-in table (2^(n-14)
+ *   resident grid and to one 2^11-amplitude sub-cube per workgroup, i.e.
+ *   2^(n-11)); NULL, or team[i] == 0, uses the built-in table (2^(n-14)
  *   workgroups, 1..256); team[i] < 0 shares the resident grid among those
- *   instances in proportion to 2^n (K + Hamiltonian strings), with at least
- *   -team[i] workgroups each (for latency when few instances are in flight).
+ *   instances in proportion to 2^n (K + Hamiltonian strings), at most
+ *   2^(n-12) and at least -team[i] workgroups each (for latency when few
+ *   instances are in flight).
  *   The batch owns all device memory: tables, two states per
  *   instance, outputs.  Results of an instance depend only on the instance
  *   and its team size, so they are identical alone and in any batch.

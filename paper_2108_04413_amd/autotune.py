@@ -67,7 +67,7 @@ def tune(ns=(12, 14, 16, 18, 20, 22, 24), count: int = 43, reps: int = 2, max_te
     for n in ns:
         insts = _instances(qf, qi, n, count, 9000 + 100 * n)
         thetas = [d["theta"] for d in insts]
-        tiles = max(1, (1 << (n - 1)) // 2048)  # the library's clamp: one 2^12 sub-cube per member
+        tiles = max(1, (1 << (n - 1)) // 1024)  # the library's clamp: one 2^11 sub-cube per member
         # a single workgroup per instance is hopeless beyond 20 qubits
         w_min = 1 << max(0, n - 20)
         cands = [w for w in (1, 2, 4, 8, 16, 32, 64, 128, 256) if w_min <= w <= min(tiles, max_team)]

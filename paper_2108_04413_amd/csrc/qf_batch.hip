@@ -58,7 +58,10 @@ __device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target,
         __syncthreads();
         return;
     }
-    __threadfence();
+    // release this member's stores before arriving, acquire after leaving
+    // (an agent-scope release writes back the L2 of this XCD, so it is paid
+    // once per barrier, not twice)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     {
         if (threadIdx.x == 0) {
@@ -75,7 +78,7 @@ __device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target,
             }
         }
         __syncthreads();
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
 }
 
@@ -799,16 +802,20 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
                 total += std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
         for (int i = 0; i < count; i++)
             if (team[i] < 0) {
+                // a shared team takes at most one forward sub-cube per member:
+                // more members mostly add barrier traffic
                 const double w = std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
-                const int share = (int)std::min<double>((double)B.grid, std::floor((double)B.grid * w / total));
+                const double cap = std::ldexp(1.0, std::max(0, n_qubits[i] - 12));
+                const int share =
+                    (int)std::min<double>({(double)B.grid, cap, std::floor((double)B.grid * w / total)});
                 B.W[(size_t)i] = std::max(-team[i], share);
             }
     }
     for (int i = 0; i < count; i++) {
-        // a team never exceeds one 2048-pair tile (one 2^12 sub-cube) per
-        // member or the grid
+        // a team never exceeds one 1024-pair tile (one reverse-sweep 2^11
+        // sub-cube) per member, or the grid
         const int n = n_qubits[i];
-        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / (kBT * kItems));
+        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / 1024);
         B.W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B.W[(size_t)i], tiles, (int64_t)B.grid});
     }
     std::vector<int> order((size_t)count);

@@ -51,14 +51,15 @@ def test_batch_uneven_sizes_match_oracle(qf):
         check_vs_oracle(d, e, g)
 
 
-@pytest.mark.parametrize("team", [[1, 1], [2, 4], [4, 16], [8, 32]])
+@pytest.mark.parametrize("team", [[1, 1], [2, 4], [4, 16], [16, 64]])
 def test_batch_teams_match_oracle(qf, team):
-    """Teams split each segment's 2^12 sub-cubes, so a team is clamped to
-    2^(n - 12) members (14 qubits: 4, 16 qubits: 16)."""
+    """Teams split each segment's sub-cubes (forward 2^12, reverse 2^11), so a
+    team is clamped to 2^(n - 11) members (14 qubits: 8, 16 qubits: 32);
+    members beyond 2^(n - 12) sit out the forward segments."""
     insts = [instance(qf, 7, 7, 21), instance(qf, 8, 8, 22)]  # 14 and 16 qubits
     B = qf.Batch(insts, team=team)
     info = B.info()
-    assert info["team"] == [min(team[0], 4), min(team[1], 16)]
+    assert info["team"] == [min(team[0], 8), min(team[1], 32)]
     E, grads = B.run([d["theta"] for d in insts], use_graph=False)
     for d, e, g in zip(insts, E, grads):
         check_vs_oracle(d, e, g)
@@ -69,7 +70,7 @@ def test_batch_shared_teams(qf):
     it can use; in a mix the large instance gets the larger share."""
     big, small = instance(qf, 8, 8, 61), instance(qf, 6, 6, 62)  # 16 and 12 qubits
     alone = qf.Batch([big], team=[-1])
-    assert alone.info()["team"] == [16]  # 2^(16-12) sub-cubes per segment
+    assert alone.info()["team"] == [16]  # at most 2^(16-12): one forward sub-cube each
     mixed = qf.Batch([big, small], team=[-1, -1])
     wb, ws = mixed.info()["team"]
     assert wb == 16 and ws == 1
