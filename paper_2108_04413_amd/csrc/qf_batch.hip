@@ -312,20 +312,10 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
                 accumulate(u, q);
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            double o[kMaxRun];
-#pragma unroll
-            for (int k = 0; k < kMaxRun; k++)
-                o[k] = __shfl_xor(acc[k], off, 64);
-#pragma unroll
-            for (int k = 0; k < kMaxRun; k++)
-                acc[k] += o[k];
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < kMaxRun; k++)
-                red[wave][k] = acc[k];
+        {
+            const double h = wave_sum8(acc, lane);
+            if (lane < 8)
+                red[wave][sum8_index(lane)] = h;
         }
         __syncthreads();
         if (threadIdx.x < (uint32_t)d.m) {

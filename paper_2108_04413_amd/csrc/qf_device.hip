@@ -996,22 +996,10 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     accumulate(u, q);
                 }
             }
-            // wavefront sums of all accumulators, one shuffle step at a time
-            // so that the eight exchanges of a step are in flight together
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                double o[kMaxRun];
-#pragma unroll
-                for (int k = 0; k < kMaxRun; k++)
-                    o[k] = __shfl_xor(acc[k], off, 64);
-#pragma unroll
-                for (int k = 0; k < kMaxRun; k++)
-                    acc[k] += o[k];
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < kMaxRun; k++)
-                    red[wave][k] = acc[k];
+            {
+                const double h = wave_sum8(acc, lane);
+                if (lane < 8)
+                    red[wave][sum8_index(lane)] = h;
             }
             __syncthreads();
             if (tid < (uint32_t)d.m) {
