@@ -51,24 +51,79 @@ struct BatchEntry {
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
 
-__device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target, unsigned spin_limit,
-                                          unsigned *err)
+// Team barrier across the XCDs of the chip. Each XCD has its own L2, and an
+// agent-scope release writes back the whole L2 of the XCD that issues it, so
+// the barrier pays it once per XCD the team spans instead of once per member:
+// members on one XCD arrive on that XCD's counter after their stores have
+// reached the shared L2, the last of them releases the L2 and arrives on the
+// team counter, and everyone leaves when every spanned XCD has arrived.
+// Counter words of a team (kSyncWords apart, zeroed before each launch):
+//   [0] XCDs arrived (all epochs), [2 + x] members registered on XCD x,
+//   [10 + x] arrivals on XCD x.
+// A member's arrival on its XCD counter is not itself a release: its stores
+// are complete in the XCD's L2 before it arrives (waitcnt + workgroup
+// barrier), and the last arriver's release writes that L2 back to HBM.
+constexpr int kSyncWords = 32;
+
+__device__ __forceinline__ unsigned xcc_id()
+{
+    // hwreg(HW_REG_XCC_ID, offset 0, 4 bits): the XCD this wave runs on
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 7u;
+}
+
+struct TeamSync {
+    unsigned *ctr;
+    unsigned xcc;  // this member's XCD
+    unsigned mine; // team members on it (0 until the first barrier has read the registration)
+    unsigned nxcc; // XCDs the team spans
+};
+
+// bounded poll of a counter; on timeout or a raised error flag the caller
+// goes on with whatever it has and the launch reports the error
+__device__ __forceinline__ void spin_until(const unsigned *p, unsigned target, unsigned spin_limit, unsigned *err)
+{
+    unsigned spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        __builtin_amdgcn_s_sleep(4);
+        if (++spins >= spin_limit) {
+            atomicOr(err, 1u);
+            return;
+        }
+    }
+}
+
+// thread 0 of each member, once per team and before its first barrier
+__device__ __forceinline__ void team_register(int W, TeamSync &ts)
+{
+    if (W == 1)
+        return;
+    ts.xcc = xcc_id();
+    ts.mine = 0;
+    atomicAdd(ts.ctr + 2 + ts.xcc, 1u);
+}
+
+__device__ __forceinline__ void team_sync(int W, TeamSync &ts, unsigned epoch, unsigned spin_limit, unsigned *err)
 {
     if (W == 1) {  // one workgroup: its waves share the CU's caches
         __syncthreads();
         return;
     }
-    // release this member's stores before arriving, acquire after leaving
-    // (an agent-scope release writes back the L2 of this XCD, so it is paid
-    // once per barrier, not twice)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave's stores have reached this XCD's L2 before thread 0 arrives
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    {
-        if (threadIdx.x == 0) {
-            atomicAdd(ctr, 1u);
-            unsigned spins = 0;
-            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    if (threadIdx.x == 0) {
+        if (!ts.mine) {
+            // wait until all W members have registered, then read the census
+            unsigned reg[8], spins = 0;
+            for (;;) {
+                unsigned tot = 0;
+                for (int x = 0; x < 8; x++) {
+                    reg[x] = __hip_atomic_load(ts.ctr + 2 + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    tot += reg[x];
+                }
+                if (tot >= (unsigned)W || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                     break;
                 __builtin_amdgcn_s_sleep(4);
                 if (++spins >= spin_limit) {
@@ -76,10 +131,21 @@ __device__ __forceinline__ void team_sync(int W, unsigned *ctr, unsigned target,
                     break;
                 }
             }
+            unsigned nx = 0;
+            for (int x = 0; x < 8; x++)
+                nx += reg[x] ? 1u : 0u;
+            ts.mine = max(1u, reg[ts.xcc]);
+            ts.nxcc = max(1u, nx);
         }
-        __syncthreads();
+        const unsigned old = atomicAdd(ts.ctr + 10 + ts.xcc, 1u);
+        if (old + 1u == ts.mine * epoch) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(ts.ctr, 1u);
+        }
+        spin_until(ts.ctr, ts.nxcc * epoch, spin_limit, err);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    __syncthreads();
 }
 
 // Workgroup shape of the batched kernel: 512 threads, and LDS for one
@@ -499,7 +565,7 @@ __device__ void pass_adjoint(double2 *__restrict__ phi, double2 *__restrict__ la
 
 __global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, unsigned *err)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nentries; i += gridDim.x * blockDim.x)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nentries * kSyncWords; i += gridDim.x * blockDim.x)
         sync[i] = 0u;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *ticket = 0u;
@@ -555,13 +621,16 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         const double *th = theta + en.theta0;
         double *gpart = partials + en.part0;     // [W][K] string sums
         double *epart = gpart + (size_t)W * en.K; // [W] energy sums
-        unsigned *ctr = sync + ei;
+        TeamSync ts;
+        ts.ctr = sync + (size_t)ei * kSyncWords;
+        if (threadIdx.x == 0)
+            team_register(W, ts);
         unsigned epoch = 0;
         uint64_t b, e;
 
         member_slice(dim, W, rank, b, e);
         pass_prepare(phi, b, e, en.occ);
-        team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+        team_sync(W, ts, ++epoch, spin_limit, err);
 
         // forward: segments of runs on sub-cubes, members take sub-cubes rank, rank + W, ...
         for (int si = 0; si < en.naseg; si++) {
@@ -579,7 +648,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
                     sub_apply(phi, en.Bapp, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub);
             }
-            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+            team_sync(W, ts, ++epoch, spin_limit, err);
         }
 
         member_slice(dim, W, rank, b, e);
@@ -589,7 +658,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (threadIdx.x == 0)
                 epart[rank] = s_part[0];
         }
-        team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+        team_sync(W, ts, ++epoch, spin_limit, err);
 
         // reverse sweep: segments last first; each member leaves its string sums in gpart[rank]
         for (int si = en.ndseg - 1; si >= 0; si--) {
@@ -622,7 +691,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];
             }
-            team_sync(W, ctr, (unsigned)W * ++epoch, spin_limit, err);
+            team_sync(W, ts, ++epoch, spin_limit, err);
         }
         if (rank == 0) {
             for (int k = threadIdx.x; k < en.K; k += kBT) {
@@ -890,7 +959,7 @@ Layout batch_layout(const qf_batch &B, const BatchHost &T)
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
-        (size_t)T.parts * sizeof(double), T.ent.size() * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
+        (size_t)T.parts * sizeof(double), T.ent.size() * kSyncWords * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun)};
     Layout L;
@@ -951,7 +1020,7 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
 
 void batch_kernels(qf_batch &B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries + 255) / 256))), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
                        B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
