@@ -178,8 +178,9 @@ def serving_leg(qf, qi, n_req=200):
     t0 = time.perf_counter()
     reqs = serve.make_requests(qf, qi, trace)
     log(f"serving: built {n_req} requests in {time.perf_counter() - t0:.1f} s")
-    srv = serve.Server(arena_bytes=48 << 30, slots=2, max_wave=64)
+    srv = serve.Server(arena_bytes=48 << 30, slots=2, max_wave=64, solo_qubits=serve.SOLO_QUBITS)
     st_b = srv.serve(reqs)
+    srv.close()
     log(f"serving (continuous batching): {st_b}")
     plain = serve.make_requests(qf, qi, trace)
     st_p = serve.serve_plain(plain, max(r.n for r in plain))
@@ -189,6 +190,7 @@ def serving_leg(qf, qi, n_req=200):
     for r in reqs:
         mix[r.n] = mix.get(r.n, 0) + 1
     return {"requests": n_req, "offered_rate_req_per_s": 2000.0, "qubit_mix": dict(sorted(mix.items())),
+            "solo_qubits": serve.SOLO_QUBITS,
             "continuous_batching": st_b, "plain_serial": st_p,
             "throughput_ratio": st_b["throughput_req_per_s"] / st_p["throughput_req_per_s"],
             "max_abs_dE_batched_vs_plain": dE}

@@ -17,7 +17,17 @@ serving (hipFree would synchronize the device).  Scheduling:
   memory); the kernel publishes an instance's energy and gradient there and
   then raises its flag as soon as that instance's team is done, so a short
   request in a wave completes without waiting for the wave's long ones.  A
-  wave's arena range and slot are released when the whole launch finishes.
+  wave's arena range and slot are released when the whole launch finishes;
+* solo lane (solo_qubits): a request of at least that many qubits fills the
+  device by itself, and the single-instance kernels (a plan: blocked apply,
+  sigma, blocked adjoint, each a full-grid launch) run it faster than a team
+  of the persistent kernel, which has to meet at a barrier after every pass.
+  Such requests queue FIFO for one solo lane: a host thread that runs the
+  plan path on its own stream with its two states in the arena, while the
+  batched waves of the smaller requests go on beside it.  The plan's own
+  tables (a few MB to ~100 MB) are allocated by the library when the request
+  starts; plans are destroyed when the replay has drained, since hipFree
+  would wait for the whole device.
 
 Latency is measured from a request's arrival to the collection of its wave.
 The plain path (`serve_plain`) runs the same trace one request at a time
@@ -26,6 +36,7 @@ with per-request plans and the single-instance kernels.
 from __future__ import annotations
 
 import ctypes
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -35,6 +46,10 @@ from . import api
 from ._lib import check, lib, ptr, stream_handle
 
 ALIGN = 256
+# Requests of at least this many qubits take the solo lane.  On MI355X the
+# 200-request mixed trace (12-24 qubits) served 61 req/s with 20, 61 with
+# 22, 59 with 18 and 51 with every request batched.
+SOLO_QUBITS = 20
 
 
 @dataclass
@@ -52,7 +67,8 @@ class Request:
     t_admit: float | None = None
     t_done: float | None = None
     footprint: int = 0
-    team: int = 0  # workgroups the request's instance ran with
+    team: int = 0  # workgroups the request's instance ran with (0: solo lane)
+    solo: bool = False  # ran on the solo lane (plan kernels)
 
 
 class RangeAllocator:
@@ -146,19 +162,40 @@ class Wave:
     open: int = 0                    # requests not yet published
 
 
+class _Addr:
+    """A device address in the arena, passed where the API takes a buffer."""
+
+    def __init__(self, addr: int):
+        self.addr = addr
+
+    def data_ptr(self) -> int:
+        return self.addr
+
+
+def solo_footprint(r) -> int:
+    """Arena bytes of a solo-lane request: its two states (phi, lambda)."""
+    return 2 * (1 << r.n) * 16
+
+
 def _view(addr: int, ctype, count: int) -> np.ndarray:
     return np.ctypeslib.as_array(ctypes.cast(ctypes.c_void_p(addr), ctypes.POINTER(ctype)), shape=(count,))
 
 
 class Server:
     def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None,
-                 mailbox_bytes: int = 32 << 20, share: bool = True):
+                 mailbox_bytes: int = 32 << 20, share: bool = True, solo_qubits: int | None = SOLO_QUBITS):
         import torch
         if team_table is None:
             team_table = default_team_table()
         self.team = team_table
         self.share = share  # split the grid among a wave's requests by work
+        self.solo_qubits = solo_qubits  # None: every request goes through batched waves
         self.arena = Arena(arena_bytes)
+        self.solo_stream = torch.cuda.Stream()
+        self.solo_job = None      # (thread, request, arena range)
+        self.solo_error = None
+        self.solo_plans = []      # finished plans, destroyed when a replay drains
+        self.solo_runs = 0
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.busy = [None] * slots
         self.max_wave = max_wave
@@ -220,6 +257,46 @@ class Server:
                 r.t_done = now
                 w.open -= 1
 
+    def _solo_run(self, r, addr: int, t0: float):
+        """Solo lane body (host thread): plan, energy + gradient, publish."""
+        try:
+            plan = api.Plan(r.n, r.A, r.H, r.off)
+            self.solo_plans.append(plan)
+            r.E, r.grad = plan.energy_grad(r.occ, r.theta, _Addr(addr), self.solo_stream)
+            r.t_done = time.perf_counter() - t0
+        except BaseException as e:  # reported by the serving loop
+            self.solo_error = e
+
+    def _solo_poll(self, pending_solo, t0) -> int:
+        """Retire a finished solo request, start the next if its states fit.
+        Returns the number of requests completed."""
+        done = 0
+        if self.solo_job is not None and not self.solo_job[0].is_alive():
+            th, r, rng = self.solo_job
+            th.join()
+            self.solo_job = None
+            self.arena.release(*rng)
+            if self.solo_error is not None:
+                raise RuntimeError(f"solo lane failed on request {r.rid}") from self.solo_error
+            done += 1
+        if self.solo_job is None and pending_solo:
+            r = pending_solo[0]
+            rng = self.arena.alloc(r.footprint)
+            if rng is not None:
+                pending_solo.pop(0)
+                r.t_admit = time.perf_counter() - t0
+                r.solo, r.team = True, 0
+                th = threading.Thread(target=self._solo_run, args=(r, self.arena.base + rng[0], t0), daemon=True)
+                self.solo_job = (th, r, rng)
+                self.solo_runs += 1
+                th.start()
+        return done
+
+    def _drain_plans(self):
+        for p in self.solo_plans:
+            p.close()
+        self.solo_plans = []
+
     def _finish(self, w: Wave, now):
         E = np.zeros(len(w.reqs))
         g = np.zeros(max(1, sum(len(r.A) for r in w.reqs)))
@@ -232,19 +309,40 @@ class Server:
 
     def serve(self, requests, poll_s: float = 50e-6):
         """Replay `requests` (sorted by arrival, seconds from start).  Returns stats."""
+        def is_solo(r):
+            return self.solo_qubits is not None and r.n >= self.solo_qubits
+
         for r in requests:
-            r.footprint = r.footprint or footprint([r], self.team, self.share)
+            if not r.footprint:
+                r.footprint = solo_footprint(r) if is_solo(r) else footprint([r], self.team, self.share)
             if r.footprint > self.arena.nbytes:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena has {self.arena.nbytes}")
-        pending = []
+        pending, pending_solo = [], []
+        t0 = time.perf_counter()
+        try:
+            self._replay(requests, is_solo, pending, pending_solo, t0, poll_s)
+        finally:
+            if self.solo_job is not None:
+                self.solo_job[0].join()
+                self.arena.release(*self.solo_job[2])
+                self.solo_job = None
+            import torch
+            torch.cuda.synchronize()
+            self._drain_plans()
+        out = stats(requests, self.waves, self.wave_sizes)
+        out["max_waves_in_flight"] = self.max_busy
+        out["solo_requests"] = self.solo_runs
+        return out
+
+    def _replay(self, requests, is_solo, pending, pending_solo, t0, poll_s):
         nxt = 0
         done = 0
-        t0 = time.perf_counter()
         while done < len(requests):
             now = time.perf_counter() - t0
             while nxt < len(requests) and requests[nxt].arrival <= now:
-                pending.append(requests[nxt])
+                (pending_solo if is_solo(requests[nxt]) else pending).append(requests[nxt])
                 nxt += 1
+            done += self._solo_poll(pending_solo, t0)
             for s, w in enumerate(self.busy):
                 if w is None:
                     continue
@@ -276,13 +374,11 @@ class Server:
                 self.busy[s] = w
                 pending = pending[len(wave):]
                 self.max_busy = max(self.max_busy, sum(b is not None for b in self.busy))
-            if nxt < len(requests) and not pending and all(b is None for b in self.busy):
+            idle = not pending and not pending_solo and self.solo_job is None and all(b is None for b in self.busy)
+            if nxt < len(requests) and idle:
                 time.sleep(max(0.0, min(requests[nxt].arrival - (time.perf_counter() - t0), 1e-3)))
             else:
                 time.sleep(poll_s)
-        out = stats(requests, self.waves, self.wave_sizes)
-        out["max_waves_in_flight"] = self.max_busy
-        return out
 
 
 def serve_plain(requests, max_qubits: int):

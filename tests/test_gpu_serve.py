@@ -81,7 +81,7 @@ def test_short_requests_complete_before_long_ones_in_a_wave(qf):
     tr = [(0.0, dict(n_orb=10, n_elec=10, seed=6000, t_scale=0.1))] + \
          [(0.0, dict(n_orb=5, n_elec=5, seed=6001 + j, t_scale=0.1)) for j in range(6)]
     reqs = serve.make_requests(qf, qi, tr)
-    srv = serve.Server(arena_bytes=1 << 30, slots=1, max_wave=16)
+    srv = serve.Server(arena_bytes=1 << 30, slots=1, max_wave=16, solo_qubits=None)
     st = srv.serve(reqs)
     assert st["waves"] == 1
     big, small = reqs[0], reqs[1:]
@@ -90,3 +90,34 @@ def test_short_requests_complete_before_long_ones_in_a_wave(qf):
         e, g = alone(qf, r, r.team)
         assert e == r.E and np.array_equal(g, r.grad)
     srv.close()
+
+
+def test_solo_lane_runs_large_requests_beside_waves(qf):
+    """Requests at or above solo_qubits run on the plan kernels in the solo
+    lane (bitwise equal to a plan alone); the rest go through batched waves
+    (bitwise equal to the batched kernel alone); both match the oracle."""
+    from paper_2108_04413_amd import serve
+    tr = [(0.0, dict(n_orb=9, n_elec=9, seed=7000, t_scale=0.1)),
+          (0.0, dict(n_orb=9, n_elec=9, seed=7001, t_scale=0.1))] + \
+         [(1e-4 * j, dict(n_orb=6, n_elec=6, seed=7002 + j, t_scale=0.1)) for j in range(8)]
+    reqs = serve.make_requests(qf, qi, tr)
+    srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=8, solo_qubits=18)
+    st = srv.serve(reqs)
+    srv.close()
+    assert st["requests"] == 10 and st["solo_requests"] == 2
+    ws = torch.empty(2 << 18, dtype=torch.complex128, device="cuda")
+    for r in reqs:
+        assert r.solo == (r.n >= 18)
+        if r.solo:
+            p = qf.Plan(r.n, r.A, r.H, r.off)
+            e, g = p.energy_grad(r.occ, r.theta, ws)
+            p.close()
+        else:
+            e, g = alone(qf, r, r.team)
+        assert e == r.E and np.array_equal(g, r.grad)
+    for r in (reqs[0], reqs[2]):
+        e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
+        assert r.E == pytest.approx(e_o, abs=1e-10)
+        assert np.max(np.abs(r.grad - g_o)) < 1e-9
+    # the small requests did not wait for both large ones
+    assert min(r.t_done for r in reqs[2:]) < max(r.t_done for r in reqs[:2])
