@@ -256,28 +256,34 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
         }
         const uint32_t pz = par(base & d.z0f);
         __syncthreads();
+        // u(y) and the Z-parity are affine in y; item j = tid | j0 splits
+        // into a per-thread part and a workgroup-uniform part (disjoint bits)
         if (d.x) {
-            for (uint32_t j = threadIdx.x; j < NB / 2; j += kBT) {
-                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
-                uint32_t u = pb;
-#pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y1 & bm[q]) << q;
-                const double2 cs = tab[toff + u];
+            const uint32_t yt = insert0(threadIdx.x, d.hbit);
+            const uint32_t ut = pb ^ gf2_coords(yt, bm);
+            const uint32_t pt = par(yt & d.z0) ^ pz;
+            const uint32_t kx = 2u * par(d.x & d.z0);
+            for (uint32_t j0 = 0; j0 < NB / 2; j0 += kBT) {
+                if (threadIdx.x + j0 >= NB / 2)
+                    break;
+                const uint32_t yk = insert0(j0, d.hbit);
+                const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
+                const double2 cs = tab[toff + (ut ^ gf2_coords(yk, bm))];
                 const double c = cs.x, s = cs.y;
                 const double2 a = st[y1], b = st[y2];
-                const double2 pbv = mul_ik((d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u, b);
-                const double2 pav = mul_ik((d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u, a);
+                const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
+                const double2 pbv = mul_ik(k1 ^ kx, b);
+                const double2 pav = mul_ik(k1, a);
                 st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
                 st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
             }
         } else {
-            for (uint32_t y = threadIdx.x; y < NB; y += kBT) {
-                uint32_t u = pb;
-#pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y & bm[q]) << q;
-                const double2 cs = tab[toff + u];
+            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
+            for (uint32_t y0 = 0; y0 < NB; y0 += kBT) {
+                if (threadIdx.x + y0 >= NB)
+                    break;
+                const uint32_t y = threadIdx.x | y0;
+                const double2 cs = tab[toff + (ut ^ gf2_coords(y0, bm))];
                 const double c = cs.x, s = cs.y;
                 const double2 v = st[y];
                 st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
@@ -343,17 +349,21 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         };
         __syncthreads();  // the previous run's updates are visible
         if (d.x) {
-            for (uint32_t j = threadIdx.x; j < NB / 2; j += kBT) {
-                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
-                uint32_t u = pb;
-#pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y1 & bm[q]) << q;
+            const uint32_t yt = insert0(threadIdx.x, d.hbit);
+            const uint32_t ut = pb ^ gf2_coords(yt, bm);
+            const uint32_t pt = par(yt & d.z0) ^ pz;
+            const uint32_t kx = 2u * par(d.x & d.z0);
+            for (uint32_t j0 = 0; j0 < NB / 2; j0 += kBT) {
+                if (threadIdx.x + j0 >= NB / 2)
+                    break;
+                const uint32_t yk = insert0(j0, d.hbit);
+                const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
+                const uint32_t u = ut ^ gf2_coords(yk, bm);
                 const double2 cs = tab[toff + u];
                 const double c = cs.x, s = cs.y;
                 const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
-                const uint32_t k1 = (d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u;
-                const uint32_t k2 = (d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u;
+                const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
+                const uint32_t k2 = k1 ^ kx;
                 const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
                 const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
                 sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
@@ -364,11 +374,12 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
                 accumulate(u, q);
             }
         } else {
-            for (uint32_t y = threadIdx.x; y < NB; y += kBT) {
-                uint32_t u = pb;
-#pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y & bm[q]) << q;
+            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
+            for (uint32_t y0 = 0; y0 < NB; y0 += kBT) {
+                if (threadIdx.x + y0 >= NB)
+                    break;
+                const uint32_t y = threadIdx.x | y0;
+                const uint32_t u = ut ^ gf2_coords(y0, bm);
                 const double2 cs = tab[toff + u];
                 const double c = cs.x, s = cs.y;
                 const double2 a = sp[y], la = sl[y];

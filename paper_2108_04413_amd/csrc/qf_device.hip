@@ -209,30 +209,38 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
         }
         const uint32_t pz = par(base & d.z0f);
         __syncthreads();
+        // The table index u(y) and the Z-parity of y are affine in y.  A
+        // thread's items are y = y_t | y_k with y_t from the thread index and
+        // y_k from the item index (disjoint bits), so each splits into a
+        // per-thread part computed once per run and a part that is the same
+        // for the whole workgroup.
         if (d.x) {
-#pragma unroll 2
-            for (uint32_t j = threadIdx.x; j < NB / 2; j += NT) {
-                const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
-                uint32_t u = pb;
+            constexpr int NP = NB / 2 >= NT ? (int)(NB / 2 / NT) : 1;
+            const uint32_t yt = insert0(threadIdx.x, d.hbit);
+            const uint32_t ut = pb ^ gf2_coords(yt, bm);
+            const uint32_t pt = par(yt & d.z0) ^ pz;
+            const uint32_t kx = 2u * par(d.x & d.z0);  // y2 = y1 ^ x flips the Z-parity by par(x & z0)
+            if (NB / 2 >= NT || threadIdx.x < NB / 2) {
 #pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y1 & bm[q]) << q;
-                const double2 cs = stab[toff + u];
-                const double c = cs.x, s = sgn * cs.y;
-                const double2 a = st[y1], b = st[y2];
-                const double2 pbv = mul_ik((d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u, b);
-                const double2 pav = mul_ik((d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u, a);
-                st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
-                st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
+                for (int k = 0; k < NP; k++) {
+                    const uint32_t yk = insert0((uint32_t)k * NT, d.hbit);
+                    const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
+                    const double2 cs = stab[toff + (ut ^ gf2_coords(yk, bm))];
+                    const double c = cs.x, s = sgn * cs.y;
+                    const double2 a = st[y1], b = st[y2];
+                    const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
+                    const double2 pbv = mul_ik(k1 ^ kx, b);
+                    const double2 pav = mul_ik(k1, a);
+                    st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
+                    st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
+                }
             }
         } else {
-#pragma unroll 2
-            for (uint32_t y = threadIdx.x; y < NB; y += NT) {
-                uint32_t u = pb;
+            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
 #pragma unroll
-                for (int q = 0; q < kMaxRank; q++)
-                    u ^= par(y & bm[q]) << q;
-                const double2 cs = stab[toff + u];
+            for (int k = 0; k < PER; k++) {
+                const uint32_t y = threadIdx.x + (uint32_t)k * NT;
+                const double2 cs = stab[toff + (ut ^ gf2_coords((uint32_t)k * NT, bm))];
                 const double c = cs.x, s = sgn * cs.y;
                 const double2 v = st[y];
                 st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
@@ -958,19 +966,26 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 }
             };
             __syncthreads();  // the previous run's updates are visible
+            // u(y) and the Z-parity split into a per-thread and a
+            // workgroup-uniform part, as in the blocked apply
             if (d.x) {
+                constexpr int NP = NB / 2 >= NT ? (int)(NB / 2 / NT) : 1;
+                const uint32_t yt = insert0(tid, d.hbit);
+                const uint32_t ut = pb ^ gf2_coords(yt, bm);
+                const uint32_t pt = par(yt & d.z0) ^ pz;
+                const uint32_t kx = 2u * par(d.x & d.z0);
 #pragma unroll
-                for (uint32_t j = tid; j < NB / 2; j += NT) {
-                    const uint32_t y1 = insert0(j, d.hbit), y2 = y1 ^ d.x;
-                    uint32_t u = pb;
-#pragma unroll
-                    for (int q = 0; q < kMaxRank; q++)
-                        u ^= par(y1 & bm[q]) << q;
+                for (int kk = 0; kk < NP; kk++) {
+                    if (NB / 2 < NT && tid >= NB / 2)
+                        break;
+                    const uint32_t yk = insert0((uint32_t)kk * NT, d.hbit);
+                    const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
+                    const uint32_t u = ut ^ gf2_coords(yk, bm);
                     const double2 cs = stab[toff + u];
                     const double c = cs.x, s = cs.y;
                     const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
-                    const uint32_t k1 = (d.a0 + 2u * (par(y1 & d.z0) ^ pz)) & 3u;
-                    const uint32_t k2 = (d.a0 + 2u * (par(y2 & d.z0) ^ pz)) & 3u;
+                    const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
+                    const uint32_t k2 = k1 ^ kx;
                     const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
                     const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
                     sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
@@ -981,12 +996,11 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     accumulate(u, q);
                 }
             } else {
+                const uint32_t ut = pb ^ gf2_coords(tid, bm);
 #pragma unroll
-                for (uint32_t y = tid; y < NB; y += NT) {
-                    uint32_t u = pb;
-#pragma unroll
-                    for (int q = 0; q < kMaxRank; q++)
-                        u ^= par(y & bm[q]) << q;
+                for (int kk = 0; kk < PER; kk++) {
+                    const uint32_t y = tid + (uint32_t)kk * NT;
+                    const uint32_t u = ut ^ gf2_coords((uint32_t)kk * NT, bm);
                     const double2 cs = stab[toff + u];
                     const double c = cs.x, s = cs.y;
                     const double2 a = sp[y], la = sl[y];

@@ -159,6 +159,17 @@ __device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane)
     return h;
 }
 
+// GF(2) coordinates of y against the masks bm (zero beyond the run's
+// rank): bit q is the parity of y & bm[q].  Linear in y.
+__device__ __forceinline__ uint32_t gf2_coords(uint32_t y, const uint32_t (&bm)[kMaxRank])
+{
+    uint32_t u = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxRank; q++)
+        u ^= par(y & bm[q]) << q;
+    return u;
+}
+
 __device__ __forceinline__ uint32_t run_coords(const RunDesc &d, uint32_t y)
 {
     // Unrolled to the maximum rank so that every index is a constant: a
