@@ -236,54 +236,61 @@ __device__ __forceinline__ uint32_t subcube_base(uint32_t sc, uint32_t Q, int n)
     return base;
 }
 
-// Apply a segment's runs to one 2^B sub-cube held in st (LDS).
+// Apply a segment's runs to one 2^B sub-cube held in st (LDS).  Thread t's
+// items are t + k * kBT (kBT = kItemStride); table indices and Z-parities
+// split into the thread's part and the run's tabulated item parts, and the
+// phase of a flip run folds into signs (rot_pair).
+template <bool SW>
+__device__ __forceinline__ void sub_apply_pairs(double2 *st, const double2 *tb, const LocalRun &d, uint32_t NB,
+                                                uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31)
+{
+    for (int k = 0; (uint32_t)k * kBT < NB / 2; k++) {
+        if (threadIdx.x + (uint32_t)k * kBT >= NB / 2)
+            break;
+        const uint32_t ik = item_part(item_table(d), k);
+        const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
+        const double2 cs = tb[ut ^ (ik & 63u)];
+        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31);
+        double2 a = st[y1], b = st[y2];
+        rot_pair<SW>(cs.x, flip31(cs.y, P1), flip31(cs.y, P1 ^ px31), a, b);
+        st[y1] = a;
+        st[y2] = b;
+    }
+}
+
 __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const Segment &sg,
-                          const LocalRun *__restrict__ lr, const double2 *tab, const uint32_t *hoff, double2 *st)
+                          const LocalRun *__restrict__ lr, const double2 *tab, const uint32_t *hoff, double2 *st,
+                          uint32_t *pbzs)
 {
     const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
+    // (the previous sub-cube's runs have all read pbzs: barrier before its write-back)
+    sub_parities(lr, sg.r0, sg.r1 - sg.r0, base, pbzs, (int)threadIdx.x, kBT);
     __syncthreads();  // the previous sub-cube's LDS image is written back
     for (uint32_t l = threadIdx.x; l < NB; l += kBT)
         st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
     for (int ri = sg.r0; ri < sg.r1; ri++) {
         const LocalRun d = lr[ri];
-        const int toff = d.tab - sg.tab0;
-        uint32_t bm[kMaxRank];
-        uint32_t pb = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxRank; q++) {
-            bm[q] = q < d.r ? d.b[q] : 0u;
-            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
-        }
-        const uint32_t pz = par(base & d.z0f);
+        const double2 *tb = tab + (d.tab - sg.tab0);
+        const uint32_t pbz = pbzs[ri - sg.r0];
         __syncthreads();
-        // u(y) and the Z-parity are affine in y; item j = tid | j0 splits
-        // into a per-thread part and a workgroup-uniform part (disjoint bits)
         if (d.x) {
+            // rotation factor (-1)^p2 i^m with m = a0 + 3 (exp(-i theta P))
+            const uint32_t m = (d.a0 + 3u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = pb ^ gf2_coords(yt, bm);
-            const uint32_t pt = par(yt & d.z0) ^ pz;
-            const uint32_t kx = 2u * par(d.x & d.z0);
-            for (uint32_t j0 = 0; j0 < NB / 2; j0 += kBT) {
-                if (threadIdx.x + j0 >= NB / 2)
-                    break;
-                const uint32_t yk = insert0(j0, d.hbit);
-                const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
-                const double2 cs = tab[toff + (ut ^ gf2_coords(yk, bm))];
-                const double c = cs.x, s = cs.y;
-                const double2 a = st[y1], b = st[y2];
-                const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
-                const double2 pbv = mul_ik(k1 ^ kx, b);
-                const double2 pav = mul_ik(k1, a);
-                st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
-                st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
-            }
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
+            const uint32_t px31 = par(d.x & d.z0) << 31;
+            if (m & 1u)
+                sub_apply_pairs<true>(st, tb, d, NB, yt, ut, pt31, px31);
+            else
+                sub_apply_pairs<false>(st, tb, d, NB, yt, ut, pt31, px31);
         } else {
-            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
-            for (uint32_t y0 = 0; y0 < NB; y0 += kBT) {
-                if (threadIdx.x + y0 >= NB)
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
+            for (int k = 0; (uint32_t)k * kBT < NB; k++) {
+                if (threadIdx.x + (uint32_t)k * kBT >= NB)
                     break;
-                const uint32_t y = threadIdx.x | y0;
-                const double2 cs = tab[toff + (ut ^ gf2_coords(y0, bm))];
+                const uint32_t y = threadIdx.x | ((uint32_t)k * kBT);
+                const double2 cs = tb[ut ^ item_part(item_table(d), k)];
                 const double c = cs.x, s = cs.y;
                 const double2 v = st[y];
                 st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
@@ -295,16 +302,48 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
         psi[base | (l & lomask) | hoff[l >> sg.q0]] = st[l];
 }
 
+// Reverse-sweep pairs of one flip run (q and the undo as in the single-
+// instance blocked adjoint: rotation factor (-1)^p i^(a0 + 1), q the
+// imaginary (a0 even) or real (a0 odd) part of the pair's bracket).
+template <bool SW, class Acc>
+__device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, const double2 *tb, const LocalRun &d,
+                                                  uint32_t NB, uint32_t yt, uint32_t ut, uint32_t pt31,
+                                                  uint32_t px31, uint32_t dq31, Acc &&accumulate)
+{
+    for (int k = 0; (uint32_t)k * kBT < NB / 2; k++) {
+        if (threadIdx.x + (uint32_t)k * kBT >= NB / 2)
+            break;
+        const uint32_t ik = item_part(item_table(d), k);
+        const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
+        const uint32_t u = ut ^ (ik & 63u);
+        const double2 cs = tb[u];
+        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
+        double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+        const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+        const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+        const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
+        const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+        rot_pair<SW>(cs.x, s1, s2, a, b);
+        rot_pair<SW>(cs.x, s1, s2, la, lb);
+        sp[y1] = a;
+        sp[y2] = b;
+        sl[y1] = la;
+        sl[y2] = lb;
+        accumulate(u, q);
+    }
+}
+
 // Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and
 // lambda (sl), adding each run's 2 Im <lambda|P_k|phi> / 2 per string to
 // lacc[k - sk0] before the run is undone.
 __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, int B, uint32_t base,
                             const Segment &sg, const LocalRun *__restrict__ lr, const double2 *tab,
                             const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc, double (*red)[kMaxRun],
-                            int sk0)
+                            int sk0, uint32_t *pbzs)
 {
     const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
     const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
+    sub_parities(lr, sg.r0, sg.r1 - sg.r0, base, pbzs, (int)threadIdx.x, kBT);
     __syncthreads();  // the previous sub-cube's LDS images are written back
     for (uint32_t l = threadIdx.x; l < NB; l += kBT) {
         const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
@@ -313,15 +352,8 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
     }
     for (int ri = sg.r1 - 1; ri >= sg.r0; ri--) {
         const LocalRun d = lr[ri];
-        const int toff = d.tab - sg.tab0;
-        uint32_t bm[kMaxRank];
-        uint32_t pb = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxRank; q++) {
-            bm[q] = q < d.r ? d.b[q] : 0u;
-            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
-        }
-        const uint32_t pz = par(base & d.z0f);
+        const double2 *tb = tab + (d.tab - sg.tab0);
+        const uint32_t pbz = pbzs[ri - sg.r0];
         // string k's weight is s_k (-1)^popcount(u & e_k): for rank <= 3 the
         // pass sums the 8 Walsh terms (-1)^popcount(u & e) q and string k
         // takes s_k times term e_k; otherwise acc[k] is string k's own sum
@@ -349,38 +381,24 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         };
         __syncthreads();  // the previous run's updates are visible
         if (d.x) {
+            const uint32_t m = (d.a0 + 1u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = pb ^ gf2_coords(yt, bm);
-            const uint32_t pt = par(yt & d.z0) ^ pz;
-            const uint32_t kx = 2u * par(d.x & d.z0);
-            for (uint32_t j0 = 0; j0 < NB / 2; j0 += kBT) {
-                if (threadIdx.x + j0 >= NB / 2)
-                    break;
-                const uint32_t yk = insert0(j0, d.hbit);
-                const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
-                const uint32_t u = ut ^ gf2_coords(yk, bm);
-                const double2 cs = tab[toff + u];
-                const double c = cs.x, s = cs.y;
-                const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
-                const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
-                const uint32_t k2 = k1 ^ kx;
-                const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
-                const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
-                sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
-                sp[y2] = make_double2(c * b.x - s * wa.y, c * b.y + s * wa.x);
-                const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
-                sl[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
-                sl[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
-                accumulate(u, q);
-            }
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
+            const uint32_t px31 = par(d.x & d.z0) << 31;
+            const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
+            if (m & 1u)
+                sub_adjoint_pairs<true>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+            else
+                sub_adjoint_pairs<false>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
         } else {
-            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
-            for (uint32_t y0 = 0; y0 < NB; y0 += kBT) {
-                if (threadIdx.x + y0 >= NB)
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
+            for (int k = 0; (uint32_t)k * kBT < NB; k++) {
+                if (threadIdx.x + (uint32_t)k * kBT >= NB)
                     break;
-                const uint32_t y = threadIdx.x | y0;
-                const uint32_t u = ut ^ gf2_coords(y0, bm);
-                const double2 cs = tab[toff + u];
+                const uint32_t y = threadIdx.x | ((uint32_t)k * kBT);
+                const uint32_t u = ut ^ item_part(item_table(d), k);
+                const double2 cs = tb[u];
                 const double c = cs.x, s = cs.y;
                 const double2 a = sp[y], la = sl[y];
                 const double q = la.x * a.y - la.y * a.x;
@@ -600,6 +618,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double s_lacc[kSegStr];
     __shared__ double s_red[kBW][kMaxRun];
     __shared__ double s_part[kMaxRun];
+    __shared__ uint32_t s_pbz[kSegRuns];
     for (;;) {
         if (threadIdx.x == 0) {
             const unsigned t = atomicAdd(ticket, 1u);
@@ -620,7 +639,9 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
             s_rank = rank;
         }
         __syncthreads();
-        const int ei = s_entry, rank = s_rank;
+        // uniform across the workgroup: scalar registers, so that the entry
+        // and every descriptor reached from it are scalar loads
+        const int ei = __builtin_amdgcn_readfirstlane(s_entry), rank = __builtin_amdgcn_readfirstlane(s_rank);
         __syncthreads();
         if (ei < 0)
             break;
@@ -657,7 +678,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 seg_hoff(sg, s_hoff);
                 const uint32_t nsub = 1u << (n - en.Bapp);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
-                    sub_apply(phi, en.Bapp, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub);
+                    sub_apply(phi, en.Bapp, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub, s_pbz);
             }
             team_sync(W, ts, ++epoch, spin_limit, err);
         }
@@ -697,7 +718,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const uint32_t nsub = 1u << (n - en.Badj);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
                     sub_adjoint(phi, lam, en.Badj, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub,
-                                s_sub + (kSub / 2), s_lacc, s_red, sk0);
+                                s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
                 __syncthreads();
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];

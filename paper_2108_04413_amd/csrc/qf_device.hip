@@ -152,10 +152,36 @@ __global__ __launch_bounds__(kBlock) void k_apply_run(double2 *__restrict__ psi,
     }
 }
 
+// Pairs of one flip run on a sub-cube in LDS.  Thread t's items are pair
+// indices t + k * NT (k < NP); y1 = insert0(j, hbit) has its table index and
+// Z-parity split into the thread's part (ut, pt31) and item k's part (the
+// run's item table).  pt31 carries, in bit 31, the Z-parity of y_t plus the
+// constant signs of the rotation; px31 the parity of x & z0.
+template <bool SW, uint32_t NB, int NT>
+__device__ __forceinline__ void apply_pairs(double2 *st, const double2 *tb, const LocalRun &d, uint32_t yt,
+                                            uint32_t ut, uint32_t pt31, uint32_t px31)
+{
+    constexpr int NP = NB / 2 >= (uint32_t)NT ? (int)(NB / 2 / NT) : 1;
+    if (NB / 2 < (uint32_t)NT && threadIdx.x >= NB / 2)
+        return;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const uint32_t ik = item_part(item_table(d), k);
+        const uint32_t y1 = yt | insert0((uint32_t)k * NT, d.hbit), y2 = y1 ^ d.x;
+        const double2 cs = tb[ut ^ (ik & 63u)];
+        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31);
+        double2 a = st[y1], b = st[y2];
+        rot_pair<SW>(cs.x, flip31(cs.y, P1), flip31(cs.y, P1 ^ px31), a, b);
+        st[y1] = a;
+        st[y2] = b;
+    }
+}
+
 // Blocked apply: one workgroup per sub-cube of 2^B amplitudes.  Runs of the
 // segment are applied in order (or reversed, with sgn = -1, for U^dagger);
 // the pairs (y, y ^ x) of a run never leave the sub-cube because x is in Q.
-// The segment's (cos, sin) tables are staged in LDS with the sub-cube.
+// The segment's (cos, sin) tables are staged in LDS with the sub-cube, and
+// so are the parities of the sub-cube's fixed bits against every run.
 template <int B, int NT>
 __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, int n, Segment sg,
                                                         const LocalRun *__restrict__ lruns,
@@ -164,9 +190,11 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
     constexpr uint32_t NB = 1u << B;
     static_assert(NT <= (int)NB && NB % NT == 0, "the workgroup must tile the sub-cube");
     constexpr int PER = (int)(NB / NT);
+    static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
     __shared__ double2 st[NB];
     __shared__ uint32_t hoff[64];
     __shared__ double2 stab[kSegTab];
+    __shared__ uint32_t spbz[kSegRuns];
     // base: the block index scattered into the qubits outside Q
     uint32_t base = 0;
     {
@@ -188,59 +216,39 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
     }
     for (int t = threadIdx.x; t < sg.ntab; t += NT)
         stab[t] = tab[sg.tab0 + t];
+    const int nr = sg.r1 - sg.r0;
+    sub_parities(lruns, sg.r0, nr, base, spbz, (int)threadIdx.x, NT);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; i++) {
         const uint32_t l = threadIdx.x + (uint32_t)i * NT;
         st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
     }
-    const int nr = sg.r1 - sg.r0;
+    const uint32_t sneg = sgn < 0 ? 1u : 0u;
     for (int ri = 0; ri < nr; ri++) {
-        const LocalRun d = lruns[sgn > 0 ? sg.r0 + ri : sg.r1 - 1 - ri];
-        const int toff = d.tab - sg.tab0;
-        // Masks of ranks above d.r are zero, so the loops below run to the
-        // constant maximum and the descriptor stays in registers.
-        uint32_t bm[kMaxRank];
-        uint32_t pb = 0;
-#pragma unroll
-        for (int q = 0; q < kMaxRank; q++) {
-            bm[q] = q < d.r ? d.b[q] : 0u;
-            pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
-        }
-        const uint32_t pz = par(base & d.z0f);
+        const int rr = sgn > 0 ? ri : nr - 1 - ri;
+        const LocalRun d = lruns[sg.r0 + rr];
+        const double2 *tb = stab + (d.tab - sg.tab0);
+        const uint32_t pbz = spbz[rr];
         __syncthreads();
-        // The table index u(y) and the Z-parity of y are affine in y.  A
-        // thread's items are y = y_t | y_k with y_t from the thread index and
-        // y_k from the item index (disjoint bits), so each splits into a
-        // per-thread part computed once per run and a part that is the same
-        // for the whole workgroup.
         if (d.x) {
-            constexpr int NP = NB / 2 >= NT ? (int)(NB / 2 / NT) : 1;
+            // a' = c a - i sgn s i^k2 b with i^k2 = i^a0 (-1)^p2, so the
+            // rotation factor is sgn (-1)^p2 i^m, m = a0 + 3
+            const uint32_t m = (d.a0 + 3u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = pb ^ gf2_coords(yt, bm);
-            const uint32_t pt = par(yt & d.z0) ^ pz;
-            const uint32_t kx = 2u * par(d.x & d.z0);  // y2 = y1 ^ x flips the Z-parity by par(x & z0)
-            if (NB / 2 >= NT || threadIdx.x < NB / 2) {
-#pragma unroll
-                for (int k = 0; k < NP; k++) {
-                    const uint32_t yk = insert0((uint32_t)k * NT, d.hbit);
-                    const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
-                    const double2 cs = stab[toff + (ut ^ gf2_coords(yk, bm))];
-                    const double c = cs.x, s = sgn * cs.y;
-                    const double2 a = st[y1], b = st[y2];
-                    const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
-                    const double2 pbv = mul_ik(k1 ^ kx, b);
-                    const double2 pav = mul_ik(k1, a);
-                    st[y1] = make_double2(c * a.x + s * pbv.y, c * a.y - s * pbv.x);
-                    st[y2] = make_double2(c * b.x + s * pav.y, c * b.y - s * pav.x);
-                }
-            }
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1) ^ sneg) << 31;
+            const uint32_t px31 = par(d.x & d.z0) << 31;
+            if (m & 1u)
+                apply_pairs<true, NB, NT>(st, tb, d, yt, ut, pt31, px31);
+            else
+                apply_pairs<false, NB, NT>(st, tb, d, yt, ut, pt31, px31);
         } else {
-            const uint32_t ut = pb ^ gf2_coords(threadIdx.x, bm);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
 #pragma unroll
             for (int k = 0; k < PER; k++) {
                 const uint32_t y = threadIdx.x + (uint32_t)k * NT;
-                const double2 cs = stab[toff + (ut ^ gf2_coords((uint32_t)k * NT, bm))];
+                const double2 cs = tb[ut ^ item_part(item_table(d), k)];
                 const double c = cs.x, s = sgn * cs.y;
                 const double2 v = st[y];
                 st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
@@ -872,7 +880,44 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_run(double2 *__restrict__ ph
 // run on both states.  The grid is persistent (resident workgroups, each
 // looping over sub-cubes) and keeps per-string sums in LDS; the last
 // workgroup to finish sums the per-workgroup sums in workgroup order.
-constexpr int adj_threads(int B) { return B >= 11 ? 512 : (1 << B) / 2 >= 256 ? 256 : 64; }
+constexpr int adj_threads(int B) { return B >= 10 ? 512 : (1 << B) / 2 >= 256 ? 256 : 64; }
+
+// Pairs of one flip run in the reverse sweep (items as in apply_pairs).
+// Before the run is undone, q = 2 Im <lambda|P_0|phi> / 2 over the pair with
+// P_0's phase i^a0 (-1)^p split off: q = Im[i^a0 ((-1)^p1 conj(lb) a +
+// (-1)^p2 conj(la) b)], which is the imaginary part (a0 even) or the real
+// part (a0 odd) of the bracket, negated for a0 >= 2.  Undoing the run is
+// rot_pair with the factor (-1)^p i^(a0 + 1); SW = (a0 + 1) & 1, so SW also
+// selects Im.  dq31 is the sign of q relative to the rotation's signs.
+template <bool SW, uint32_t NB, int NT, class Acc>
+__device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const double2 *tb, const LocalRun &d,
+                                              uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31,
+                                              uint32_t dq31, Acc &&accumulate)
+{
+    constexpr int NP = NB / 2 >= (uint32_t)NT ? (int)(NB / 2 / NT) : 1;
+    if (NB / 2 < (uint32_t)NT && threadIdx.x >= NB / 2)
+        return;
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const uint32_t ik = item_part(item_table(d), k);
+        const uint32_t y1 = yt | insert0((uint32_t)k * NT, d.hbit), y2 = y1 ^ d.x;
+        const uint32_t u = ut ^ (ik & 63u);
+        const double2 cs = tb[u];
+        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
+        double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+        const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+        const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+        const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
+        const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+        rot_pair<SW>(cs.x, s1, s2, a, b);
+        rot_pair<SW>(cs.x, s1, s2, la, lb);
+        sp[y1] = a;
+        sp[y2] = b;
+        sl[y1] = la;
+        sl[y2] = lb;
+        accumulate(u, q);
+    }
+}
 
 template <int B, int NT>
 __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
@@ -889,6 +934,8 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
     __shared__ double2 stab[kSegTab];
     __shared__ double lacc[kSegStr];
     __shared__ double red[NW][kMaxRun];
+    __shared__ uint32_t spbz[kSegRuns];
+    static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
     const uint32_t tid = threadIdx.x;
     const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
     const uint32_t lomask = (1u << sg.q0) - 1u;
@@ -916,6 +963,8 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     k++;
                 }
         }
+        // (the previous sub-cube's runs have all read spbz: barrier before its write-back)
+        sub_parities(lruns, sg.r0, nr, base, spbz, (int)tid, NT);
         __syncthreads();  // tables staged; the previous sub-cube is written back
 #pragma unroll
         for (int i = 0; i < PER; i++) {
@@ -930,15 +979,8 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             const LocalRun d = dnext;
             if (ri > 0)
                 dnext = lruns[sg.r0 + ri - 1];
-            const int toff = d.tab - sg.tab0;
-            uint32_t bm[kMaxRank];
-            uint32_t pb = 0;
-#pragma unroll
-            for (int q = 0; q < kMaxRank; q++) {
-                bm[q] = q < d.r ? d.b[q] : 0u;
-                pb |= (q < d.r ? par(base & d.bf[q]) : 0u) << q;
-            }
-            const uint32_t pz = par(base & d.z0f);
+            const double2 *tb = stab + (d.tab - sg.tab0);
+            const uint32_t pbz = spbz[ri];
             // string k's weight is eps_k = s_k (-1)^popcount(u & e_k) with
             // s_k = +-1 and e_k < 2^r.  For r <= 3 the pass accumulates the 8
             // Walsh sums W[e] = sum (-1)^popcount(u & e) q (acc[e]) and string
@@ -966,42 +1008,24 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 }
             };
             __syncthreads();  // the previous run's updates are visible
-            // u(y) and the Z-parity split into a per-thread and a
-            // workgroup-uniform part, as in the blocked apply
             if (d.x) {
-                constexpr int NP = NB / 2 >= NT ? (int)(NB / 2 / NT) : 1;
+                const uint32_t m = (d.a0 + 1u) & 3u;
                 const uint32_t yt = insert0(tid, d.hbit);
-                const uint32_t ut = pb ^ gf2_coords(yt, bm);
-                const uint32_t pt = par(yt & d.z0) ^ pz;
-                const uint32_t kx = 2u * par(d.x & d.z0);
-#pragma unroll
-                for (int kk = 0; kk < NP; kk++) {
-                    if (NB / 2 < NT && tid >= NB / 2)
-                        break;
-                    const uint32_t yk = insert0((uint32_t)kk * NT, d.hbit);
-                    const uint32_t y1 = yt | yk, y2 = y1 ^ d.x;
-                    const uint32_t u = ut ^ gf2_coords(yk, bm);
-                    const double2 cs = stab[toff + u];
-                    const double c = cs.x, s = cs.y;
-                    const double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
-                    const uint32_t k1 = (d.a0 + 2u * (pt ^ par(yk & d.z0))) & 3u;
-                    const uint32_t k2 = k1 ^ kx;
-                    const double2 wa = mul_ik(k1, a), wb = mul_ik(k2, b);
-                    const double q = (lb.x * wa.y - lb.y * wa.x) + (la.x * wb.y - la.y * wb.x);
-                    sp[y1] = make_double2(c * a.x - s * wb.y, c * a.y + s * wb.x);
-                    sp[y2] = make_double2(c * b.x - s * wa.y, c * b.y + s * wa.x);
-                    const double2 wla = mul_ik(k1, la), wlb = mul_ik(k2, lb);
-                    sl[y1] = make_double2(c * la.x - s * wlb.y, c * la.y + s * wlb.x);
-                    sl[y2] = make_double2(c * lb.x - s * wla.y, c * lb.y + s * wla.x);
-                    accumulate(u, q);
-                }
+                const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+                const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
+                const uint32_t px31 = par(d.x & d.z0) << 31;
+                const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
+                if (m & 1u)
+                    adjoint_pairs<true, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
+                else
+                    adjoint_pairs<false, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
             } else {
-                const uint32_t ut = pb ^ gf2_coords(tid, bm);
+                const uint32_t ut = (pbz & 63u) ^ gf2_coords(tid, d.b);
 #pragma unroll
                 for (int kk = 0; kk < PER; kk++) {
                     const uint32_t y = tid + (uint32_t)kk * NT;
-                    const uint32_t u = ut ^ gf2_coords((uint32_t)kk * NT, bm);
-                    const double2 cs = stab[toff + u];
+                    const uint32_t u = ut ^ item_part(item_table(d), kk);
+                    const double2 cs = tb[u];
                     const double c = cs.x, s = cs.y;
                     const double2 a = sp[y], la = sl[y];
                     const double q = la.x * a.y - la.y * a.x;
@@ -1284,6 +1308,25 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
             for (int k = 0; k < kMaxRun; k++) {
                 L.e[k] = d.e[k];
                 L.s[k] = d.s[k];
+            }
+            // per-item parts of the table index and the Z-parity
+            auto coords = [&](uint32_t y) {
+                uint32_t u = 0;
+                for (int q = 0; q < d.r; q++)
+                    u |= (uint32_t)(__builtin_popcount(y & L.b[q]) & 1) << q;
+                return u;
+            };
+            if (L.x) {
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t j = (uint32_t)k * kItemStride;
+                    const uint32_t lo = j & ((1u << L.hbit) - 1u);
+                    const uint32_t yk = ((j ^ lo) << 1) | lo;
+                    const uint32_t v = coords(yk) | (uint32_t)(__builtin_popcount(yk & L.z0) & 1) << 6;
+                    L.itm[0] |= v << (8 * k);
+                }
+            } else {
+                for (int k = 0; k < 8; k++)
+                    L.itm[k >> 2] |= coords((uint32_t)k * kItemStride) << (8 * (k & 3));
             }
             lr.push_back(L);
         }

@@ -46,15 +46,28 @@ struct Segment {
     int32_t pad;
 };
 
+// Sub-cube kernels give thread t the items t + k * kItemStride (k = 0, 1,
+// ...) of a run: pair index j for a flip run, amplitude index y for a
+// diagonal one.  Both the table index u(y) and the Z-parity par(y & z0) are
+// affine in y and the item offsets are the same for every thread, so their
+// parts from item k's offset are tabulated per run (LocalRun::itm, byte k):
+//   flip run:     y_k = insert0(k * kItemStride, hbit),
+//                 byte k = u(y_k) | par(y_k & z0) << 6,  k < 4;
+//   diagonal run: byte k = u(k * kItemStride),            k < 8.
+// Every kernel that has more than one item per thread runs kItemStride threads.
+constexpr int kItemStride = 512;
+constexpr int kSegRuns = kSegStr;  // runs of one segment (each has >= 1 string)
+
 struct LocalRun {
     uint32_t x, hbit, z0, a0;       // local flip mask, its highest bit, local z0, i^a0
-    uint32_t b[kMaxRank];           // local GF(2) basis masks
+    uint32_t b[kMaxRank];           // local GF(2) basis masks (zero beyond the rank)
     uint32_t z0f;                   // full-space z0
     uint32_t bf[kMaxRank];          // full-space basis masks
     int32_t r, tab;
     int32_t k0, m;                  // the run's strings (as in RunDesc)
     uint8_t e[kMaxRun];
     int8_t s[kMaxRun];
+    uint32_t itm[2];                // per-item table-index and parity parts
 };
 
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
@@ -119,6 +132,59 @@ __device__ __forceinline__ double flip(double v, uint32_t p)
 {
     // multiply by (-1)^p on the sign bit
     return __hiloint2double(__double2hiint(v) ^ (int)(p << 31), __double2loint(v));
+}
+
+// v with its sign bit xor-ed with bit 31 of m
+__device__ __forceinline__ double flip31(double v, uint32_t m)
+{
+    return __hiloint2double(__double2hiint(v) ^ (int)m, __double2loint(v));
+}
+
+// A run's item table as one 64-bit word, and its byte k.  (Shifts, not an
+// index: a run-time index into a register copy of the descriptor would put
+// the copy in scratch memory.)
+__device__ __forceinline__ uint64_t item_table(const LocalRun &d)
+{
+    return (uint64_t)d.itm[0] | ((uint64_t)d.itm[1] << 32);
+}
+
+__device__ __forceinline__ uint32_t item_part(uint64_t it, int k)
+{
+    return (uint32_t)(it >> (8 * k)) & 0xffu;
+}
+
+// Rotation of a pair by the exponential of a run.  Writing the phase of the
+// partner amplitude as i^a0 (-1)^p, with a0 fixed by the run and p the
+// Z-parity of the partner, both exp(-i theta P) and exp(+i theta P) take
+// (a, b) = (psi[y1], psi[y1 ^ x]) to
+//   a' = c a + s2 i^w b,    b' = c b + s1 i^w a
+// with w = 0 or 1 (SWAP) and s1, s2 = +-s: the rest of the phase, the
+// direction and the two parities are all signs.  i v = (-v.y, v.x).
+template <bool SWAP> __device__ __forceinline__ void rot_pair(double c, double s1, double s2, double2 &a, double2 &b)
+{
+    const double2 a0 = a, b0 = b;
+    if (SWAP) {
+        a = make_double2(c * a0.x - s2 * b0.y, c * a0.y + s2 * b0.x);
+        b = make_double2(c * b0.x - s1 * a0.y, c * b0.y + s1 * a0.x);
+    } else {
+        a = make_double2(c * a0.x + s2 * b0.x, c * a0.y + s2 * b0.y);
+        b = make_double2(c * b0.x + s1 * a0.x, c * b0.y + s1 * a0.y);
+    }
+}
+
+// Fixed-bit parities of every run of a segment for one sub-cube:
+// pbz[r] = sum_q par(base & bf_q) << q | par(base & z0f) << 6.
+__device__ __forceinline__ void sub_parities(const LocalRun *__restrict__ lr, int r0, int nr, uint32_t base,
+                                             uint32_t *pbz, int tid, int nt)
+{
+    for (int r = tid; r < nr; r += nt) {
+        const LocalRun &d = lr[r0 + r];
+        uint32_t v = par(base & d.z0f) << 6;
+#pragma unroll
+        for (int q = 0; q < kMaxRank; q++)
+            v |= par(base & d.bf[q]) << q;
+        pbz[r] = v;
+    }
 }
 
 // Wavefront sums of 8 values per lane with 10 exchanges instead of 48: three
