@@ -409,7 +409,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         }
         {
             const double h = wave_sum8(acc, lane);
-            if (lane < 8)
+            if (sum8_writer(lane))
                 red[wave][sum8_index(lane)] = h;
         }
         __syncthreads();
@@ -530,7 +530,8 @@ __device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restric
                 bv[i] = psi[y2[i]];
             }
             double dre[kItems], dim[kItems];
-            group_d(g, zs, cs, y2, dre, dim);
+            static_assert(kItems == 4 && kBT == 512, "items are y0 + 512 i, i < 4");
+            group_d4<9>(g, zs, cs, (uint32_t)(j0 + threadIdx.x) ^ g.x, dre, dim);
 #pragma unroll
             for (int i = 0; i < kItems; i++) {
                 l[i].x += dre[i] * bv[i].x - dim[i] * bv[i].y;

@@ -786,22 +786,35 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
             y[i] = (uint32_t)(ok[i] ? j : 0);
             l[i] = make_double2(0.0, 0.0);
         }
-        for (int gi = 0; gi < G; gi++) {
-            const GroupDesc g = groups[gi];
-            double2 b[kItems];
-            uint32_t y2[kItems];
+        // Two groups at a time: both groups' gathers are issued first, so
+        // the second group's loads are in flight while the first group's
+        // coefficients are evaluated (the pass is bound by gathers from
+        // L2 / Infinity Cache).
+        static_assert(kItems == 4 && kBlock == 256, "items are y0 + 256 i, i < 4");
+        const uint32_t yt = (uint32_t)(j0 + threadIdx.x);
+        auto gather = [&](const GroupDesc &g, double2 (&b)[kItems]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int i = 0; i < kItems; i++) {
-                y2[i] = y[i] ^ g.x;
-                b[i] = psi[y2[i]];
-            }
+            for (int i = 0; i < kItems; i++)
+                b[i] = psi[y[i] ^ g.x];
+        };
+        auto add_group = [&](const GroupDesc &g, const double2 (&b)[kItems]) __attribute__((always_inline)) {
             double dre[kItems], dimg[kItems];
-            group_d(g, zs, cs, y2, dre, dimg);
+            group_d4<8>(g, zs, cs, yt ^ g.x, dre, dimg);
 #pragma unroll
             for (int i = 0; i < kItems; i++) {
                 l[i].x += dre[i] * b[i].x - dimg[i] * b[i].y;
                 l[i].y += dre[i] * b[i].y + dimg[i] * b[i].x;
             }
+        };
+        for (int gi = 0; gi < G; gi += 2) {
+            const bool two = gi + 1 < G;
+            const GroupDesc ga = groups[gi], gb = groups[two ? gi + 1 : gi];
+            double2 ba[kItems], bb[kItems];
+            gather(ga, ba);
+            gather(gb, bb);
+            add_group(ga, ba);
+            if (two)
+                add_group(gb, bb);
         }
 #pragma unroll
         for (int i = 0; i < kItems; i++) {
@@ -1036,7 +1049,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             }
             {
                 const double h = wave_sum8(acc, lane);
-                if (lane < 8)
+                if (sum8_writer(lane))
                     red[wave][sum8_index(lane)] = h;
             }
             __syncthreads();

@@ -187,42 +187,81 @@ __device__ __forceinline__ void sub_parities(const LocalRun *__restrict__ lr, in
     }
 }
 
-// Wavefront sums of 8 values per lane with 10 exchanges instead of 48: three
-// halving steps (each lane keeps half of its values and sends the other half
-// to its partner) leave lane l with value 4 b0 + 2 b1 + b2 (its lane bits)
-// summed over its 8-lane group, and three more steps add the 8 groups.  The
-// order of additions is fixed.
+// Wavefront sums of 8 values per lane with 10 exchanges instead of 48, all
+// of them register moves (DPP and the gfx950 lane swaps), none through the
+// LDS crossbar.  Three halving steps over lane bits 0, 1 and 4 (each lane
+// keeps half of its values and receives the other half from its partner)
+// leave lane l with value sum8_index(l) = 4 b0 + 2 b1 + b4 summed over the 8
+// lanes that share bits 2, 3 and 5; two rotations within each 16-lane row
+// add the lanes that differ in bits 2 and 3 (the rotation's direction does
+// not matter: ror 4 then ror 8 visits all four), and a swap of the two
+// 32-lane halves adds bit 5.  Lanes with bits 2, 3 and 5 clear
+// (sum8_writer) hold the 8 totals.  The order of additions is fixed.
 __device__ __forceinline__ int sum8_index(int lane)
 {
-    return 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1);
+    return 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 4) & 1);
+}
+
+__device__ __forceinline__ bool sum8_writer(int lane) { return (lane & 0x2c) == 0; }
+
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+constexpr int kDppXor1 = 0xb1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4e;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRor4 = 0x124; // row_ror:4
+constexpr int kDppRor8 = 0x128; // row_ror:8
+
+// the value of lane l ^ 16 (lanes exchange 16-lane rows 0 <-> 1, 2 <-> 3)
+__device__ __forceinline__ double xor16_f64(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    // one result of each swap is this lane's own word, the other the
+    // partner's; where both are equal either is right
+    const bool first_is_own = (int)pl[0] == lo && (int)ph[0] == hi;
+    return __hiloint2double(first_is_own ? (int)ph[1] : (int)ph[0], first_is_own ? (int)pl[1] : (int)pl[0]);
+}
+
+// v(l) + v(l ^ 32): the swap leaves each lane one word of each half
+__device__ __forceinline__ double sum_xor32_f64(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
 }
 
 __device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane)
 {
-    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1;
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b4 = (lane >> 4) & 1;
     double h4[4], h2[2];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const double send = b0 ? v[k] : v[k + 4];
         const double keep = b0 ? v[k + 4] : v[k];
-        h4[k] = keep + __shfl_xor(send, 1, 64);
+        h4[k] = keep + dpp_f64<kDppXor1>(send);
     }
 #pragma unroll
     for (int k = 0; k < 2; k++) {
         const double send = b1 ? h4[k] : h4[k + 2];
         const double keep = b1 ? h4[k + 2] : h4[k];
-        h2[k] = keep + __shfl_xor(send, 2, 64);
+        h2[k] = keep + dpp_f64<kDppXor2>(send);
     }
     double h;
     {
-        const double send = b2 ? h2[0] : h2[1];
-        const double keep = b2 ? h2[1] : h2[0];
-        h = keep + __shfl_xor(send, 4, 64);
+        const double send = b4 ? h2[0] : h2[1];
+        const double keep = b4 ? h2[1] : h2[0];
+        h = keep + xor16_f64(send);
     }
-    h += __shfl_xor(h, 8, 64);
-    h += __shfl_xor(h, 16, 64);
-    h += __shfl_xor(h, 32, 64);
-    return h;
+    h += dpp_f64<kDppRor4>(h);
+    h += dpp_f64<kDppRor8>(h);
+    return sum_xor32_f64(h);
 }
 
 // GF(2) coordinates of y against the masks bm (zero beyond the run's
@@ -274,6 +313,49 @@ __device__ __forceinline__ void group_d(const GroupDesc &g, const uint32_t *__re
         for (int i = 0; i < kItems; i++)
             dim[i] += flip(c, par(y[i] & z));
     }
+}
+
+// D_g at the four indices Y ^ (i << LS), i = 0..3, for the sigma passes,
+// whose items are 2^LS apart with bits LS and LS + 1 of the first item
+// clear.  String k's sign at item i is (-1)^popcount(Y & z_k) times
+// (-1)^(i0 z_k[LS] + i1 z_k[LS + 1]); the first factor is computed once per
+// thread, the second is the same for the whole wavefront and enters as an
+// FMA by +-1.0 (exact, so equal to the signed add).  (A host table of the
+// item signs, 32 B per string, was slower in the batched kernel: many
+// instances' tables thrash the scalar cache.)
+__device__ __forceinline__ double pm_one(uint32_t m31)
+{
+    return __hiloint2double((int)(0x3ff00000u ^ m31), 0);
+}
+
+template <int LS>
+__device__ __forceinline__ void group_d4_part(int k0, int k1, const uint32_t *__restrict__ zs,
+                                              const double *__restrict__ cs, uint32_t Y, double (&d)[4])
+{
+#pragma unroll 2
+    for (int k = k0; k < k1; k++) {
+        const uint32_t z = zs[k];
+        const uint32_t m1 = (z >> LS) << 31, m2 = (z >> (LS + 1)) << 31;
+        const double t = flip31(cs[k], (uint32_t)__popc(Y & z) << 31);
+        d[0] += t;
+        d[1] = fma(pm_one(m1), t, d[1]);
+        d[2] = fma(pm_one(m2), t, d[2]);
+        d[3] = fma(pm_one(m1 ^ m2), t, d[3]);
+    }
+}
+
+template <int LS>
+__device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__restrict__ zs,
+                                         const double *__restrict__ cs, uint32_t Y, double (&dre)[4],
+                                         double (&dim)[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        dre[i] = 0.0;
+        dim[i] = 0.0;
+    }
+    group_d4_part<LS>(g.k0, g.kre, zs, cs, Y, dre);
+    group_d4_part<LS>(g.kre, g.k1, zs, cs, Y, dim);
 }
 
 } // namespace qf
