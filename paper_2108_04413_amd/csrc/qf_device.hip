@@ -36,11 +36,11 @@ namespace qf {
 
 // Block-wide deterministic sum of M values per thread, then the last block
 // to arrive sums the per-block partials in block order into out[0..M).
-template <int M>
+template <int M, int NTH = kBlock>
 __device__ void reduce_finish(double (&v)[M], double *partials, unsigned *counter, double *out,
                               double scale, int nout)
 {
-    __shared__ double lds[kBlock / 64][M];
+    __shared__ double lds[NTH / 64][M];
     __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -54,7 +54,7 @@ __device__ void reduce_finish(double (&v)[M], double *partials, unsigned *counte
     __syncthreads();
     if (threadIdx.x < M) {
         double s = 0.0;
-        for (int w = 0; w < kBlock / 64; w++)
+        for (int w = 0; w < NTH / 64; w++)
             s += lds[w][threadIdx.x];
         __hip_atomic_store(&partials[(size_t)blockIdx.x * M + threadIdx.x], s, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -69,16 +69,16 @@ __device__ void reduce_finish(double (&v)[M], double *partials, unsigned *counte
     if (!last)
         return;
     __threadfence();
-    // fixed-shape tree: thread t sums blocks t, t+256, ... for each k
+    // fixed-shape tree: thread t sums blocks t, t + NTH, ... for each k
     const int nb = gridDim.x;
-    __shared__ double red[kBlock];
+    __shared__ double red[NTH];
     for (int k = 0; k < M; k++) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kBlock)
+        for (int b = threadIdx.x; b < nb; b += NTH)
             s += __hip_atomic_load(&partials[(size_t)b * M + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         red[threadIdx.x] = s;
         __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
+        for (int w = NTH / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w)
                 red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
@@ -829,6 +829,152 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
+// Sigma over tiles of 2^11 outputs: groups whose flip masks agree above bit
+// 11 form a class, and for output tile t every group of class c reads its
+// partner amplitudes psi[y ^ x] from the one tile t ^ xh_c.  That tile is
+// staged in LDS once per class (double-buffered, the next class's tile is in
+// flight in registers while this class is evaluated), so the state crosses
+// HBM once per class instead of being gathered once per group.  A thread
+// owns outputs tb | tid | 512 i (i < 4); D_g is evaluated at the partner
+// index as in k_sigma.
+constexpr int kSigL = 11;
+constexpr int kSigNT = 512;
+
+__global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                        int n, const ClassDesc *__restrict__ classes, int ncls,
+                                                        const GroupDesc *__restrict__ groups, int G,
+                                                        const uint32_t *__restrict__ zs,
+                                                        const double *__restrict__ cs, int KH, double *partials,
+                                                        unsigned *counter, double *result)
+{
+    constexpr uint32_t T = 1u << kSigL;
+    constexpr int IT = (int)(T / kSigNT);
+    static_assert(IT == 4, "four outputs 512 apart per thread");
+    __shared__ double2 sp[2][T];
+    const uint32_t ntiles = 1u << (n - kSigL);
+    const uint32_t tid = threadIdx.x;
+    const int lane = (int)(tid & 63u);
+    double acc = 0.0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t tb = t << kSigL;
+        double2 l[IT];
+#pragma unroll
+        for (int i = 0; i < IT; i++)
+            l[i] = make_double2(0.0, 0.0);
+        // the next partner tile, in flight in registers (four named values:
+        // an array carried around the class loop was put in scratch memory)
+        const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
+        double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
+                p3 = psi[pb0 | (tid + 3 * kSigNT)];
+        // Group descriptors and strings reach the wave 64 at a time, one per
+        // lane (coalesced vector loads), and are broadcast by readlane: a
+        // scalar load per group or string from tables larger than the scalar
+        // cache left the pass latency-bound (~2500 clocks per group).
+        int gc = 0, kc = 0;
+        uint32_t gxv = 0;
+        int gk0v = 0, gkrev = 0, gk1v = 0;
+        uint32_t zv = 0;
+        double cv = 0.0;
+        auto load_groups = [&](int g) __attribute__((always_inline)) {
+            gc = g;
+            const GroupDesc d = groups[min(g + lane, G - 1)];
+            gxv = d.x;
+            gk0v = d.k0;
+            gkrev = d.kre;
+            gk1v = d.k1;
+        };
+        auto load_strings = [&](int k) __attribute__((always_inline)) {
+            kc = k;
+            zv = zs[min(k + lane, KH - 1)];
+            cv = cs[min(k + lane, KH - 1)];
+        };
+        load_groups(0);
+        load_strings(0);
+        for (int c = 0; c < ncls; c++) {
+            double2 *buf = sp[c & 1];
+            buf[tid] = p0;
+            buf[tid + kSigNT] = p1;
+            buf[tid + 2 * kSigNT] = p2;
+            buf[tid + 3 * kSigNT] = p3;
+            const ClassDesc cd = classes[c];
+            {
+                // unconditional: the last class fetches its own tile again
+                const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
+                p0 = psi[pb | tid];
+                p1 = psi[pb | (tid + kSigNT)];
+                p2 = psi[pb | (tid + 2 * kSigNT)];
+                p3 = psi[pb | (tid + 3 * kSigNT)];
+            }
+            // buf is complete; its previous readers (class c - 2) passed the
+            // barrier of class c - 1 before anyone writes it again
+            __syncthreads();
+            for (int g = cd.g0; g < cd.g1; g++) {
+                if (g - gc >= 64)
+                    load_groups(g);
+                const int jg = g - gc;
+                const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
+                const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
+                const int kre = __builtin_amdgcn_readlane(gkrev, jg);
+                const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
+                const uint32_t xl = gx & (T - 1u);
+                const uint32_t Y = (tb | tid) ^ gx;
+                double dre[IT], dimg[IT];
+#pragma unroll
+                for (int i = 0; i < IT; i++) {
+                    dre[i] = 0.0;
+                    dimg[i] = 0.0;
+                }
+                auto part = [&](int ka, int kb, double(&d)[IT]) __attribute__((always_inline)) {
+#pragma unroll 2
+                    for (int k = ka; k < kb; k++) {
+                        if ((unsigned)(k - kc) >= 64u)  // (groups re-sorted by class may jump back)
+                            load_strings(k);
+                        const int j = k - kc;
+                        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)zv, j);
+                        const double cc = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(cv), j),
+                                                           __builtin_amdgcn_readlane(__double2loint(cv), j));
+                        // sign at item i: (-1)^popcount(Y & z) times the
+                        // uniform sign of bits 9 and 10 of z (items 512 apart)
+                        const uint32_t m1 = (z >> 9) << 31, m2 = (z >> 10) << 31;
+                        const double tt = flip31(cc, (uint32_t)__popc(Y & z) << 31);
+                        d[0] += tt;
+                        d[1] = fma(pm_one(m1), tt, d[1]);
+                        d[2] = fma(pm_one(m2), tt, d[2]);
+                        d[3] = fma(pm_one(m1 ^ m2), tt, d[3]);
+                    }
+                };
+                part(k0, kre, dre);
+                if (k1 > kre) {
+                    part(kre, k1, dimg);
+#pragma unroll
+                    for (int i = 0; i < IT; i++) {
+                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                        l[i].x += dre[i] * b.x - dimg[i] * b.y;
+                        l[i].y += dre[i] * b.y + dimg[i] * b.x;
+                    }
+                } else {  // real phases only (every string of a real Hamiltonian)
+#pragma unroll
+                    for (int i = 0; i < IT; i++) {
+                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                        l[i].x += dre[i] * b.x;
+                        l[i].y += dre[i] * b.y;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < IT; i++) {
+            const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
+            lam[y] = l[i];
+            const double2 p = psi[y];
+            acc += p.x * l[i].x + p.y * l[i].y;
+        }
+        __syncthreads();  // the last class's buffer is read before the next tile stages into it
+    }
+    double vals[1] = {acc};
+    reduce_finish<1, kSigNT>(vals, partials, counter, result, 1.0, 1);
+}
+
 // One reverse-sweep step over a run: grad[k0+k] = 2 Im <lam|P_k|phi>, then
 // phi, lam <- U_run^dagger (phi, lam).
 __global__ __launch_bounds__(kBlock) void k_adjoint_run(double2 *__restrict__ phi, double2 *__restrict__ lam,
@@ -1390,6 +1536,9 @@ struct qf_plan {
     qf::GroupDesc *d_groups = nullptr;
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
+    qf::ClassDesc *d_sclasses = nullptr;  // sigma classes over 2^11 tiles (n >= 12)
+    qf::GroupDesc *d_sgroups = nullptr;   // groups in class order (ranges into d_z / d_c)
+    int n_sclasses = 0;
     double *d_partials = nullptr;
     unsigned *d_counter = nullptr;
     double *d_result = nullptr;
@@ -1401,7 +1550,7 @@ struct qf_plan {
         if (h_theta)
             (void)hipHostFree(h_theta);
         void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
-                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls};
+                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_sclasses, d_sgroups};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -1647,6 +1796,30 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         P.groups = gd;
         P.hz = zs;
         P.hc = cs;
+        if (n > kSigL) {
+            // sigma classes: groups sorted by their flip bits above the tile
+            std::vector<GroupDesc> sg(gd);
+            std::stable_sort(sg.begin(), sg.end(), [](const GroupDesc &a, const GroupDesc &b) {
+                return (a.x >> kSigL) < (b.x >> kSigL);
+            });
+            std::vector<ClassDesc> sc;
+            for (size_t g = 0; g < sg.size(); g++) {
+                const uint32_t xh = sg[g].x >> kSigL;
+                if (sc.empty() || sc.back().xh != xh) {
+                    ClassDesc c;
+                    c.xh = xh;
+                    c.hb = hibit(xh);
+                    c.g0 = c.g1 = (int32_t)g;
+                    sc.push_back(c);
+                }
+                sc.back().g1 = (int32_t)g + 1;
+            }
+            P.d_sclasses = dev_alloc<ClassDesc>(sc.size());
+            P.d_sgroups = dev_alloc<GroupDesc>(sg.size());
+            QF_HIP(hipMemcpy(P.d_sclasses, sc.data(), sc.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
+            QF_HIP(hipMemcpy(P.d_sgroups, sg.data(), sg.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+            P.n_sclasses = (int)sc.size();
+        }
         for (const GroupDesc &g : gd)
             if (g.k1 > g.kre)
                 P.has_imag = true;
@@ -1843,6 +2016,15 @@ void launch_energy(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t 
 
 void launch_sigma(qf_plan &P, const double2 *psi, double2 *lam, double *dev_out, hipStream_t s)
 {
+    if (P.n_sclasses) {
+        const unsigned ntiles = 1u << (P.n - kSigL);
+        const unsigned nb = std::min<unsigned>(ntiles, (unsigned)kMaxBlocks);
+        hipLaunchKernelGGL(k_sigma_tiled, dim3(nb), dim3(kSigNT), 0, s, psi, lam, P.n, P.d_sclasses,
+                           P.n_sclasses, P.d_sgroups, P.G, P.d_z, P.d_c, (int)P.hz.size(), P.d_partials,
+                           P.d_counter, dev_out);
+        QF_HIP(hipGetLastError());
+        return;
+    }
     const uint64_t dim = 1ull << P.n;
     const unsigned nb = grid_for(dim, (uint64_t)kBlock * kItems, kMaxBlocks);
     hipLaunchKernelGGL(k_sigma, dim3(nb), dim3(kBlock), 0, s, psi, lam, P.n, P.d_groups, P.G, P.d_z, P.d_c,
