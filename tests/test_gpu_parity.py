@@ -224,6 +224,35 @@ def test_sigma_17q_matches_oracle(qf, real_only):
     assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
 
 
+@pytest.mark.parametrize("n", [12, 13])
+def test_sigma_tiled_edge_cases_match_oracle(qf, n):
+    """The class-tiled sigma at its smallest sizes (2 and 4 tiles of 2^11),
+    with groups given out of flip-mask order (strings of a class are then
+    not contiguous) and a diagonal group of 150 strings (longer than the
+    64 strings a wave holds at a time)."""
+    rng = np.random.default_rng([n, 41])
+    xs, zs, cs = qi.random_paulis(n, 400, 40 + n)
+    dz = rng.integers(0, 1 << n, 150).astype(np.uint64)
+    xs = np.concatenate([xs, np.zeros(150, np.uint64)])
+    zs = np.concatenate([zs, dz])
+    cs = np.concatenate([cs, rng.normal(size=150)])
+    xs, zs, cs, off = grouped(xs, zs, cs)
+    # shuffle whole groups
+    G = len(off) - 1
+    perm = rng.permutation(G)
+    parts = [np.arange(off[g], off[g + 1]) for g in perm]
+    idx = np.concatenate(parts)
+    xs, zs, cs = xs[idx], zs[idx], cs[idx]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    psi0 = qi.random_state(n, 50 + n)
+    plan = qf.Plan(n, None, qf.terms_array(xs, zs, cs), off)
+    lam = torch.empty_like(dev(psi0))
+    e = plan.sigma(dev(psi0), lam)
+    want = core.sigma(psi0, n, xs, zs, cs)
+    assert np.max(np.abs(host(lam) - want)) < 1e-11
+    assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
+
+
 def test_plan_matches_one_shot_and_is_deterministic(qf):
     w, n, occ, (x, z, c, off), (ax, az, ac, aoff, th) = system("8q")
     H = qf.terms_array(x, z, c)
