@@ -532,10 +532,18 @@ __device__ double pass_sigma(const double2 *__restrict__ psi, double2 *__restric
             double dre[kItems], dim[kItems];
             static_assert(kItems == 4 && kBT == 512, "items are y0 + 512 i, i < 4");
             group_d4<9>(g, zs, cs, (uint32_t)(j0 + threadIdx.x) ^ g.x, dre, dim);
+            if (g.k1 > g.kre) {
 #pragma unroll
-            for (int i = 0; i < kItems; i++) {
-                l[i].x += dre[i] * bv[i].x - dim[i] * bv[i].y;
-                l[i].y += dre[i] * bv[i].y + dim[i] * bv[i].x;
+                for (int i = 0; i < kItems; i++) {
+                    l[i].x += dre[i] * bv[i].x - dim[i] * bv[i].y;
+                    l[i].y += dre[i] * bv[i].y + dim[i] * bv[i].x;
+                }
+            } else {  // real phases only
+#pragma unroll
+                for (int i = 0; i < kItems; i++) {
+                    l[i].x += dre[i] * bv[i].x;
+                    l[i].y += dre[i] * bv[i].y;
+                }
             }
         }
 #pragma unroll
