@@ -137,3 +137,25 @@ def test_batch_recipe_instances(qf):
     E, grads = B.run([d["theta"] for d in insts])
     for d, e, g in zip(insts, E, grads):
         check_vs_oracle(d, e, g)
+
+
+def test_batch_full_recipe_sampled(qf):
+    """The whole batched workload (256 instances of 12-22 qubits, tuned
+    teams, one graph launch, as the benchmark runs it): sampled instances
+    the oracle finishes quickly against the oracle, every instance against
+    the single-instance plan path."""
+    recs = qi.batched_instances(256)
+    insts = [instance(qf, r["n_orb"], r["n_elec"], r["seed"], r["t_scale"]) for r in recs]
+    B = qf.Batch(insts)
+    E, grads = B.run([d["theta"] for d in insts], use_graph=True)
+    B.close()
+    small = [i for i, d in enumerate(insts) if d["n"] <= 14]
+    for i in small[:4] + small[-2:]:
+        check_vs_oracle(insts[i], E[i], grads[i])
+    ws = torch.empty(2 << max(d["n"] for d in insts), dtype=torch.complex128, device="cuda")
+    for i, d in enumerate(insts):
+        p = qf.Plan(d["n"], d["A"], d["H"], d["off"])
+        e, g = p.energy_grad(d["occ"], d["theta"], ws)
+        p.close()
+        assert E[i] == pytest.approx(e, abs=E_TOL)
+        assert np.max(np.abs(grads[i] - g)) < G_TOL
