@@ -223,3 +223,41 @@ class Batch:
         check(lib.qf_batch_run(self._h, ptr(theta), ptr(E), ptr(g), int(use_graph), stream_handle(stream)),
               "qf_batch_run")
         return E, [g[self.koff[i]:self.koff[i + 1]].copy() for i in range(self.count)]
+
+    def run_completion(self, thetas, stream=None, poll_s: float = 20e-6):
+        """One launch in which the kernel publishes each instance to a host
+        mailbox as soon as its team finishes (qf_batch_launch_mailbox).
+        Returns (E, grads, t_done): t_done[i] is the time in seconds from the
+        launch call to the host seeing instance i's flag."""
+        import time
+        theta = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in thetas])
+                                     if self.count else np.zeros(0), dtype=np.float64)
+        if len(theta) != self.koff[-1]:
+            raise ValueError("theta lengths do not match the batch's ansatz sizes")
+        need = ctypes.c_int64()
+        check(lib.qf_batch_mailbox_bytes(self._h, ctypes.byref(need)), "qf_batch_mailbox_bytes")
+        mb = ctypes.c_void_p()
+        check(lib.qf_mailbox_alloc(need.value, ctypes.byref(mb)), "qf_mailbox_alloc")
+        try:
+            kt = int(self.koff[-1])
+            flags = np.ctypeslib.as_array(
+                ctypes.cast(ctypes.c_void_p(mb.value + 8 * self.count + 8 * kt), ctypes.POINTER(ctypes.c_uint32)),
+                shape=(self.count,))
+            t_done = np.full(self.count, np.nan)
+            t0 = time.perf_counter()
+            check(lib.qf_batch_launch_mailbox(self._h, ptr(theta), mb, need.value, stream_handle(stream)),
+                  "qf_batch_launch_mailbox")
+            while True:
+                now = time.perf_counter() - t0
+                up = (flags == 1) & np.isnan(t_done)
+                t_done[up] = now
+                if not np.isnan(t_done).any() or lib.qf_batch_poll(self._h) == 0:
+                    break
+                time.sleep(poll_s)
+            E = np.zeros(self.count)
+            g = np.zeros(max(kt, 1))
+            check(lib.qf_batch_collect(self._h, ptr(E), ptr(g)), "qf_batch_collect")
+            t_done[np.isnan(t_done)] = time.perf_counter() - t0
+        finally:
+            lib.qf_mailbox_free(mb)
+        return E, [g[self.koff[i]:self.koff[i + 1]].copy() for i in range(self.count)], t_done

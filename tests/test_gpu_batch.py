@@ -159,3 +159,18 @@ def test_batch_full_recipe_sampled(qf):
         p.close()
         assert E[i] == pytest.approx(e, abs=E_TOL)
         assert np.max(np.abs(grads[i] - g)) < G_TOL
+
+
+def test_batch_run_completion_matches_run(qf):
+    """Mailbox launch: every instance is published with its completion time,
+    and the results are bitwise those of an ordinary launch."""
+    insts = [instance(qf, 8, 8, 71), instance(qf, 5, 5, 72), instance(qf, 6, 6, 73), instance(qf, 4, 4, 74)]
+    B = qf.Batch(insts, team=[4, 1, 2, 1])
+    thetas = [d["theta"] for d in insts]
+    E, g = B.run(thetas, use_graph=False)
+    Ec, gc, t_done = B.run_completion(thetas)
+    B.close()
+    assert np.array_equal(E, Ec)
+    assert all(np.array_equal(a, b) for a, b in zip(g, gc))
+    assert np.all(np.isfinite(t_done)) and np.all(t_done > 0)
+    check_vs_oracle(insts[1], Ec[1], gc[1])
