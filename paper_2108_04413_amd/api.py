@@ -88,11 +88,22 @@ def energy_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarra
     return e.value, g
 
 
+_PLAN_TILES = None
+
+
+def _plan_tiles() -> dict:
+    global _PLAN_TILES
+    if _PLAN_TILES is None:
+        from .autotune import device_arch, load_plan_table
+        _PLAN_TILES = load_plan_table(device_arch())
+    return _PLAN_TILES
+
+
 class Plan:
     """qf_plan_*: device-resident ansatz and Hamiltonian tables for repeated calls."""
 
     def __init__(self, n_qubits: int, A: np.ndarray | None = None, H: np.ndarray | None = None,
-                 group_off: np.ndarray | None = None):
+                 group_off: np.ndarray | None = None, tuned: bool = True):
         self.n = n_qubits
         self.K = 0 if A is None else len(A)
         self._A = A
@@ -103,6 +114,15 @@ class Plan:
         check(lib.qf_plan_create(n_qubits, ptr(A), self.K, ptr(H), ptr(self._goff), G, ctypes.byref(h)),
               "qf_plan_create")
         self._h = h
+        if tuned:
+            # the autotuned tiles for this qubit count, when the committed
+            # table matches this device (else the library's defaults)
+            t = _plan_tiles().get(int(n_qubits))
+            if t:
+                if self.K and t.get("block_bits"):
+                    self.set_block_bits(int(t["block_bits"]))
+                if G and t.get("energy_tile") and n_qubits > int(t["energy_tile"]):
+                    self.set_energy_tile(int(t["energy_tile"]), True)
 
     def close(self, _destroy=lib.qf_plan_destroy):
         if getattr(self, "_h", None):

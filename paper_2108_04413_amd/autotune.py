@@ -1,5 +1,14 @@
 """Autotuner for the persistent batched kernel.
 
+Two kinds of knobs are tuned per qubit count.
+
+Plan tiles (`plan` in the table): the sub-cube size B of the blocked apply
+(and of the reverse sweep, min(B, 11)) and the tile of the energy passes
+(2^L amplitudes, merged lo-terms).  For each n the tuner builds one seeded
+instance and times energy + gradient for B in {10, 11, 12} and the energy
+for L in {10, 11, 12}; api.Plan applies the winners when the table matches
+the device.
+
 The schedule knob of qf_batch is the team size W(n): how many workgroups
 cooperate on one instance of n qubits.  Small W runs many instances side by
 side (each pass is short and stays in one CU's cache); large W spreads one
@@ -93,24 +102,99 @@ def tune(ns=(12, 14, 16, 18, 20, 22, 24), count: int = 43, reps: int = 2, max_te
     return result
 
 
+def load_plan_table(arch: str | None = None) -> dict:
+    """Tuned plan tiles {n: {"block_bits": B, "energy_tile": L}} for this
+    architecture ({} if none)."""
+    if not os.path.exists(TABLE):
+        return {}
+    with open(TABLE) as f:
+        tab = json.load(f)
+    if arch is not None and tab.get("arch") != arch:
+        return {}
+    return {int(k): v for k, v in tab.get("plan", {}).items()}
+
+
+def tune_plan(ns=(12, 14, 16, 18, 20, 22, 24), reps: int = 3, log=print) -> dict:
+    """Per n: the blocked-apply sub-cube bits (timed on energy + gradient,
+    which also runs the reverse sweep) and the energy tile bits (timed on
+    the energy of the prepared state)."""
+    import torch
+
+    import paper_2108_04413_amd as qf
+    sys.path.insert(0, os.path.dirname(HERE))
+    import qf_inputs as qi
+
+    def best_of(fn):
+        fn()
+        t = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+        return t * 1e3
+
+    out, ms = {}, {}
+    for n in ns:
+        d = _instances(qf, qi, n, 1, 8000 + n)[0]
+        plan = qf.Plan(n, d["A"], d["H"], d["off"], tuned=False)
+        ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+        psi = ws[:1 << n]
+        tb = {}
+        for B in (10, 11, 12):
+            if B > n:
+                continue
+            plan.set_block_bits(B)
+            tb[B] = best_of(lambda: plan.energy_grad(d["occ"], d["theta"], ws))
+            log(f"autotune plan n={n} block bits {B}: energy + gradient {tb[B]:.3f} ms")
+        bbest = min(tb, key=tb.get)
+        plan.set_block_bits(bbest)
+        qf.prepare_state(psi, n, d["occ"])
+        plan.apply(psi, d["theta"])
+        te = {}
+        for L in (10, 11, 12):
+            if L >= n:
+                continue
+            plan.set_energy_tile(L, True)
+            te[L] = best_of(lambda: plan.energy(psi))
+            log(f"autotune plan n={n} energy tile {L}: energy {te[L]:.3f} ms")
+        lbest = min(te, key=te.get) if te else 0
+        out[str(n)] = {"block_bits": int(bbest), "energy_tile": int(lbest)}
+        ms[str(n)] = {"energy_grad": {str(k): v for k, v in tb.items()},
+                      "energy": {str(k): v for k, v in te.items()}}
+        log(f"autotune plan n={n}: block bits {bbest}, energy tile {lbest}")
+        del ws, psi
+        plan.close()
+        torch.cuda.empty_cache()
+    return {"plan": out, "plan_ms": ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--count", type=int, default=43)
     ap.add_argument("--ns", default="12,14,16,18,20,22,24")
     ap.add_argument("--merge", action="store_true", help="update the existing table instead of replacing it")
+    ap.add_argument("--what", default="all", choices=["all", "team", "plan"])
     args = ap.parse_args()
-    res = tune(tuple(int(v) for v in args.ns.split(",")), count=args.count,
-               log=lambda m: print(m, flush=True))
+    ns = tuple(int(v) for v in args.ns.split(","))
+    say = lambda m: print(m, flush=True)  # noqa: E731
+    res = {"arch": device_arch(), "count": args.count, "team": {}, "ms": {}}
+    if args.what in ("all", "team"):
+        res.update(tune(ns, count=args.count, log=say))
+    if args.what in ("all", "plan"):
+        res.update(tune_plan(ns, log=say))
     if args.merge and os.path.exists(args.out):
         with open(args.out) as f:
             old = json.load(f)
-        old["team"].update(res["team"])
-        old["ms"].update(res["ms"])
+        for key in ("team", "ms", "plan", "plan_ms"):
+            if key in res:
+                old.setdefault(key, {}).update(res[key])
         res = old
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps(res["team"]))
+    print(json.dumps({"team": res.get("team"), "plan": res.get("plan")}))
 
 
 if __name__ == "__main__":
