@@ -100,7 +100,12 @@ def _plan_tiles() -> dict:
 
 
 class Plan:
-    """qf_plan_*: device-resident ansatz and Hamiltonian tables for repeated calls."""
+    """qf_plan_*: device-resident ansatz and Hamiltonian tables for repeated calls.
+
+    tuned: apply the autotuned tiles for this qubit count (blocked-apply
+    sub-cube bits, energy tile bits) from the committed table when it was
+    measured on this device architecture; False keeps the library defaults.
+    """
 
     def __init__(self, n_qubits: int, A: np.ndarray | None = None, H: np.ndarray | None = None,
                  group_off: np.ndarray | None = None, tuned: bool = True):
