@@ -844,7 +844,7 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
                                                         int n, const ClassDesc *__restrict__ classes, int ncls,
                                                         const GroupDesc *__restrict__ groups, int G,
                                                         const uint32_t *__restrict__ zs,
-                                                        const double *__restrict__ cs, int KH, double *partials,
+                                                        const double *__restrict__ cs, double *partials,
                                                         unsigned *counter, double *result)
 {
     constexpr uint32_t T = 1u << kSigL;
@@ -866,15 +866,15 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
         const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
         double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
                 p3 = psi[pb0 | (tid + 3 * kSigNT)];
-        // Group descriptors and strings reach the wave 64 at a time, one per
-        // lane (coalesced vector loads), and are broadcast by readlane: a
-        // scalar load per group or string from tables larger than the scalar
-        // cache left the pass latency-bound (~2500 clocks per group).
-        int gc = 0, kc = 0;
+        // Group descriptors reach the wave 64 at a time, one per lane
+        // (coalesced vector loads), and are broadcast by readlane: a scalar
+        // load per group from a table larger than the scalar cache left the
+        // pass latency-bound (~2500 clocks per group).  Strings are scalar
+        // loads (a readlane broadcast of them costs three VALU per string,
+        // which measured slower).
+        int gc = 0;
         uint32_t gxv = 0;
         int gk0v = 0, gkrev = 0, gk1v = 0;
-        uint32_t zv = 0;
-        double cv = 0.0;
         auto load_groups = [&](int g) __attribute__((always_inline)) {
             gc = g;
             const GroupDesc d = groups[min(g + lane, G - 1)];
@@ -883,13 +883,7 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
             gkrev = d.kre;
             gk1v = d.k1;
         };
-        auto load_strings = [&](int k) __attribute__((always_inline)) {
-            kc = k;
-            zv = zs[min(k + lane, KH - 1)];
-            cv = cs[min(k + lane, KH - 1)];
-        };
         load_groups(0);
-        load_strings(0);
         for (int c = 0; c < ncls; c++) {
             double2 *buf = sp[c & 1];
             buf[tid] = p0;
@@ -927,12 +921,8 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
                 auto part = [&](int ka, int kb, double(&d)[IT]) __attribute__((always_inline)) {
 #pragma unroll 2
                     for (int k = ka; k < kb; k++) {
-                        if ((unsigned)(k - kc) >= 64u)  // (groups re-sorted by class may jump back)
-                            load_strings(k);
-                        const int j = k - kc;
-                        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)zv, j);
-                        const double cc = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(cv), j),
-                                                           __builtin_amdgcn_readlane(__double2loint(cv), j));
+                        const uint32_t z = zs[k];
+                        const double cc = cs[k];
                         // sign at item i: (-1)^popcount(Y & z) times the
                         // uniform sign of bits 9 and 10 of z (items 512 apart)
                         const uint32_t m1 = (z >> 9) << 31, m2 = (z >> 10) << 31;
@@ -2020,8 +2010,7 @@ void launch_sigma(qf_plan &P, const double2 *psi, double2 *lam, double *dev_out,
         const unsigned ntiles = 1u << (P.n - kSigL);
         const unsigned nb = std::min<unsigned>(ntiles, (unsigned)kMaxBlocks);
         hipLaunchKernelGGL(k_sigma_tiled, dim3(nb), dim3(kSigNT), 0, s, psi, lam, P.n, P.d_sclasses,
-                           P.n_sclasses, P.d_sgroups, P.G, P.d_z, P.d_c, (int)P.hz.size(), P.d_partials,
-                           P.d_counter, dev_out);
+                           P.n_sclasses, P.d_sgroups, P.G, P.d_z, P.d_c, P.d_partials, P.d_counter, dev_out);
         QF_HIP(hipGetLastError());
         return;
     }
