@@ -187,12 +187,19 @@ int qf_plan_info(const qf_plan *plan, int *tile_bits, int64_t *classes, int64_t 
  * a set of B qubits form a segment; each segment is one pass in which every
  * sub-cube of 2^B amplitudes is loaded into LDS, updated by all the
  * segment's runs in order, and stored.  Default: B = min(12, n_qubits) for
- * n_qubits >= 6.  The adjoint sweep of qf_plan_energy_grad is not affected.
+ * n_qubits >= 6.  The reverse sweep of qf_plan_energy_grad follows: for
+ * B >= 10 it undoes segments on sub-cubes of min(B, 11) qubits of phi and
+ * lambda (Sec. 3.1 gradient, one pass per segment), otherwise one pass per
+ * fused run.  The Python binding applies autotuned values of B and of the
+ * energy tile per qubit count when its table matches the device.
  */
 int qf_plan_set_block_bits(qf_plan *plan, int block_bits);
 /* block bits, number of fused runs, passes over the state per application */
 int qf_plan_apply_info(const qf_plan *plan, int *block_bits, int64_t *runs, int64_t *passes);
-/* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out) */
+/* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out).
+ * For n_qubits >= 12 the groups are taken in classes by their flip bits
+ * above bit 11 and each class's partner tile of 2^11 amplitudes is read once
+ * per output tile; below, psi[y ^ x] is gathered per group. */
 int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
 
 /*
