@@ -48,6 +48,7 @@ struct BatchEntry {
     int32_t aseg0, naseg, alr0;  // forward segments (Segment, LocalRun offsets)
     int32_t dseg0, ndseg, dlr0;  // reverse-sweep segments
     int32_t Bapp, Badj;          // their sub-cube sizes (qubits)
+    int32_t cls0, ncls;          // sigma classes (ClassDesc; groups in class order), 0: untiled sigma
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
 
@@ -149,11 +150,13 @@ __device__ __forceinline__ void team_sync(int W, TeamSync &ts, unsigned epoch, u
 }
 
 // Workgroup shape of the batched kernel: 512 threads, and LDS for one
-// 2^12-amplitude sub-cube (blocked apply) or one 2^11 sub-cube of each of
-// phi and lambda (blocked adjoint), two workgroups per CU.
+// 2^12-amplitude sub-cube (blocked apply), one 2^11 sub-cube of each of phi
+// and lambda (blocked adjoint) or the two partner-tile buffers of the
+// class-tiled sigma, two workgroups per CU.
 constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 constexpr int kSub = 4096;
+static_assert(kSub >= (2 << kSigL) && kBT == kSigNT, "the sigma tile buffers fit the sub-cube image");
 
 // member's slice [b, e) of `units`, in whole tiles of kBT * kItems
 __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
@@ -614,7 +617,8 @@ __global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, un
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
                                                unsigned total_tickets, const RunDesc *__restrict__ runs,
                                                const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
-                                               const GroupDesc *__restrict__ groups, const uint32_t *__restrict__ zs,
+                                               const GroupDesc *__restrict__ groups,
+                                               const ClassDesc *__restrict__ classes, const uint32_t *__restrict__ zs,
                                                const double *__restrict__ cs, const double *__restrict__ theta,
                                                double2 *states, double *partials, unsigned *sync, unsigned *ticket,
                                                unsigned *err, double *E_out, double *grad_out, unsigned spin_limit,
@@ -692,9 +696,19 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
             team_sync(W, ts, ++epoch, spin_limit, err);
         }
 
-        member_slice(dim, W, rank, b, e);
         {
-            double v[1] = {pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e)};
+            double v[1] = {0.0};
+            if (en.ncls) {
+                // class tiles rank, rank + W, ... (a team has at most one member per tile);
+                // the two tile buffers are the sub-cube image
+                double2(*sp)[1u << kSigL] = reinterpret_cast<double2(*)[1u << kSigL]>(s_sub);
+                for (uint32_t t = (uint32_t)rank; t < (1u << (n - kSigL)); t += (uint32_t)W)
+                    sigma_tile(phi, lam, t, classes + en.cls0, en.ncls, groups + en.group0, en.G, zs + en.term0,
+                               cs + en.term0, sp, v[0]);
+            } else {
+                member_slice(dim, W, rank, b, e);
+                v[0] = pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e);
+            }
             block_sum<1>(v, s_part);
             if (threadIdx.x == 0)
                 epart[rank] = s_part[0];
@@ -786,6 +800,7 @@ struct qf_batch {
     qf::Segment *d_segs = nullptr;
     qf::LocalRun *d_lruns = nullptr;
     qf::GroupDesc *d_groups = nullptr;
+    qf::ClassDesc *d_classes = nullptr;
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
     double *d_theta = nullptr;
@@ -860,6 +875,7 @@ struct BatchHost {
     std::vector<Segment> segs;
     std::vector<LocalRun> lruns;
     std::vector<GroupDesc> groups;
+    std::vector<ClassDesc> cls;
     std::vector<uint32_t> zs;
     std::vector<double> cs;
     uint64_t state_amps = 0;
@@ -933,6 +949,9 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::vector<uint32_t> z;
         std::vector<double> c;
         build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
+        std::vector<ClassDesc> sc;
+        if (n > kSigL && !gd.empty())
+            sigma_classes(gd, sc);
         // forward segments on 2^min(n,12) sub-cubes, reverse on 2^min(n,11)
         // (phi and lambda share the LDS image)
         const int Bapp = std::min(n, 12), Badj = std::min(n, 11);
@@ -964,6 +983,8 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         e.run0 = (int32_t)T.runs.size();
         e.group0 = (int32_t)T.groups.size();
         e.term0 = (int32_t)T.zs.size();
+        e.cls0 = (int32_t)T.cls.size();
+        e.ncls = (int32_t)sc.size();
         e.theta0 = (int32_t)B.koff[(size_t)i];
         e.ticket0 = (int32_t)T.tickets;
         e.part0 = (int32_t)T.parts;
@@ -973,6 +994,7 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.ent.push_back(e);
         T.runs.insert(T.runs.end(), r.begin(), r.end());
         T.groups.insert(T.groups.end(), gd.begin(), gd.end());
+        T.cls.insert(T.cls.end(), sc.begin(), sc.end());
         T.zs.insert(T.zs.end(), z.begin(), z.end());
         T.cs.insert(T.cs.end(), c.begin(), c.end());
         T.state_amps += 2ull << n;
@@ -990,22 +1012,23 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[15];
+    size_t off[16];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[15] = {
+    const size_t sizes[16] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
         (size_t)T.parts * sizeof(double), T.ent.size() * kSyncWords * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
-        std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun)};
+        std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
+        std::max<size_t>(T.cls.size(), 1) * sizeof(ClassDesc)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 15; i++) {
+    for (int i = 0; i < 16; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -1030,6 +1053,7 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_grad = (double *)(base + L.off[12]);
     B.d_segs = (Segment *)(base + L.off[13]);
     B.d_lruns = (LocalRun *)(base + L.off[14]);
+    B.d_classes = (ClassDesc *)(base + L.off[15]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -1050,6 +1074,9 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
                               s));
     QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
                           s));
+    if (!T.cls.empty())
+        QF_HIP(hipMemcpyAsync(B.d_classes, T.cls.data(), T.cls.size() * sizeof(ClassDesc), hipMemcpyHostToDevice,
+                              s));
     QF_HIP(hipMemcpyAsync(B.d_z, T.zs.data(), T.zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     QF_HIP(hipMemcpyAsync(B.d_c, T.cs.data(), T.cs.size() * sizeof(double), hipMemcpyHostToDevice, s));
     const int64_t ng = std::max<int64_t>(B.K_total, 1);
@@ -1064,7 +1091,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_classes, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }

@@ -829,17 +829,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
-// Sigma over tiles of 2^11 outputs: groups whose flip masks agree above bit
-// 11 form a class, and for output tile t every group of class c reads its
-// partner amplitudes psi[y ^ x] from the one tile t ^ xh_c.  That tile is
-// staged in LDS once per class (double-buffered, the next class's tile is in
-// flight in registers while this class is evaluated), so the state crosses
-// HBM once per class instead of being gathered once per group.  A thread
-// owns outputs tb | tid | 512 i (i < 4); D_g is evaluated at the partner
-// index as in k_sigma.
-constexpr int kSigL = 11;
-constexpr int kSigNT = 512;
-
+// Class-tiled sigma (sigma_tile): one workgroup per output tile at a time.
 __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restrict__ psi, double2 *__restrict__ lam,
                                                         int n, const ClassDesc *__restrict__ classes, int ncls,
                                                         const GroupDesc *__restrict__ groups, int G,
@@ -847,120 +837,11 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
                                                         const double *__restrict__ cs, double *partials,
                                                         unsigned *counter, double *result)
 {
-    constexpr uint32_t T = 1u << kSigL;
-    constexpr int IT = (int)(T / kSigNT);
-    static_assert(IT == 4, "four outputs 512 apart per thread");
-    __shared__ double2 sp[2][T];
+    __shared__ double2 sp[2][1u << kSigL];
     const uint32_t ntiles = 1u << (n - kSigL);
-    const uint32_t tid = threadIdx.x;
-    const int lane = (int)(tid & 63u);
     double acc = 0.0;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t tb = t << kSigL;
-        double2 l[IT];
-#pragma unroll
-        for (int i = 0; i < IT; i++)
-            l[i] = make_double2(0.0, 0.0);
-        // the next partner tile, in flight in registers (four named values:
-        // an array carried around the class loop was put in scratch memory)
-        const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
-        double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
-                p3 = psi[pb0 | (tid + 3 * kSigNT)];
-        // Group descriptors reach the wave 64 at a time, one per lane
-        // (coalesced vector loads), and are broadcast by readlane: a scalar
-        // load per group from a table larger than the scalar cache left the
-        // pass latency-bound (~2500 clocks per group).  Strings are scalar
-        // loads (a readlane broadcast of them costs three VALU per string,
-        // which measured slower).
-        int gc = 0;
-        uint32_t gxv = 0;
-        int gk0v = 0, gkrev = 0, gk1v = 0;
-        auto load_groups = [&](int g) __attribute__((always_inline)) {
-            gc = g;
-            const GroupDesc d = groups[min(g + lane, G - 1)];
-            gxv = d.x;
-            gk0v = d.k0;
-            gkrev = d.kre;
-            gk1v = d.k1;
-        };
-        load_groups(0);
-        for (int c = 0; c < ncls; c++) {
-            double2 *buf = sp[c & 1];
-            buf[tid] = p0;
-            buf[tid + kSigNT] = p1;
-            buf[tid + 2 * kSigNT] = p2;
-            buf[tid + 3 * kSigNT] = p3;
-            const ClassDesc cd = classes[c];
-            {
-                // unconditional: the last class fetches its own tile again
-                const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
-                p0 = psi[pb | tid];
-                p1 = psi[pb | (tid + kSigNT)];
-                p2 = psi[pb | (tid + 2 * kSigNT)];
-                p3 = psi[pb | (tid + 3 * kSigNT)];
-            }
-            // buf is complete; its previous readers (class c - 2) passed the
-            // barrier of class c - 1 before anyone writes it again
-            __syncthreads();
-            for (int g = cd.g0; g < cd.g1; g++) {
-                if (g - gc >= 64)
-                    load_groups(g);
-                const int jg = g - gc;
-                const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
-                const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
-                const int kre = __builtin_amdgcn_readlane(gkrev, jg);
-                const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
-                const uint32_t xl = gx & (T - 1u);
-                const uint32_t Y = (tb | tid) ^ gx;
-                double dre[IT], dimg[IT];
-#pragma unroll
-                for (int i = 0; i < IT; i++) {
-                    dre[i] = 0.0;
-                    dimg[i] = 0.0;
-                }
-                auto part = [&](int ka, int kb, double(&d)[IT]) __attribute__((always_inline)) {
-#pragma unroll 2
-                    for (int k = ka; k < kb; k++) {
-                        const uint32_t z = zs[k];
-                        const double cc = cs[k];
-                        // sign at item i: (-1)^popcount(Y & z) times the
-                        // uniform sign of bits 9 and 10 of z (items 512 apart)
-                        const uint32_t m1 = (z >> 9) << 31, m2 = (z >> 10) << 31;
-                        const double tt = flip31(cc, (uint32_t)__popc(Y & z) << 31);
-                        d[0] += tt;
-                        d[1] = fma(pm_one(m1), tt, d[1]);
-                        d[2] = fma(pm_one(m2), tt, d[2]);
-                        d[3] = fma(pm_one(m1 ^ m2), tt, d[3]);
-                    }
-                };
-                part(k0, kre, dre);
-                if (k1 > kre) {
-                    part(kre, k1, dimg);
-#pragma unroll
-                    for (int i = 0; i < IT; i++) {
-                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                        l[i].x += dre[i] * b.x - dimg[i] * b.y;
-                        l[i].y += dre[i] * b.y + dimg[i] * b.x;
-                    }
-                } else {  // real phases only (every string of a real Hamiltonian)
-#pragma unroll
-                    for (int i = 0; i < IT; i++) {
-                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                        l[i].x += dre[i] * b.x;
-                        l[i].y += dre[i] * b.y;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < IT; i++) {
-            const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
-            lam[y] = l[i];
-            const double2 p = psi[y];
-            acc += p.x * l[i].x + p.y * l[i].y;
-        }
-        __syncthreads();  // the last class's buffer is read before the next tile stages into it
-    }
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        sigma_tile(psi, lam, t, classes, ncls, groups, G, zs, cs, sp, acc);
     double vals[1] = {acc};
     reduce_finish<1, kSigNT>(vals, partials, counter, result, 1.0, 1);
 }
@@ -1389,6 +1270,24 @@ uint32_t pext32(uint32_t v, uint32_t mask)
 
 } // namespace
 
+void sigma_classes(std::vector<GroupDesc> &gd, std::vector<ClassDesc> &cls)
+{
+    std::stable_sort(gd.begin(), gd.end(),
+                     [](const GroupDesc &a, const GroupDesc &b) { return (a.x >> kSigL) < (b.x >> kSigL); });
+    cls.clear();
+    for (size_t g = 0; g < gd.size(); g++) {
+        const uint32_t xh = gd[g].x >> kSigL;
+        if (cls.empty() || cls.back().xh != xh) {
+            ClassDesc c;
+            c.xh = xh;
+            c.hb = hibit(xh);
+            c.g0 = c.g1 = (int32_t)g;
+            cls.push_back(c);
+        }
+        cls.back().g1 = (int32_t)g + 1;
+    }
+}
+
 // Greedy segmentation of the run sequence for blocked application: extend a
 // segment while the union of its flip masks and the lowest q0 qubits has at
 // most B qubits; pad Q with the lowest free qubits to exactly B.  A run whose
@@ -1787,23 +1686,9 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         P.hz = zs;
         P.hc = cs;
         if (n > kSigL) {
-            // sigma classes: groups sorted by their flip bits above the tile
             std::vector<GroupDesc> sg(gd);
-            std::stable_sort(sg.begin(), sg.end(), [](const GroupDesc &a, const GroupDesc &b) {
-                return (a.x >> kSigL) < (b.x >> kSigL);
-            });
             std::vector<ClassDesc> sc;
-            for (size_t g = 0; g < sg.size(); g++) {
-                const uint32_t xh = sg[g].x >> kSigL;
-                if (sc.empty() || sc.back().xh != xh) {
-                    ClassDesc c;
-                    c.xh = xh;
-                    c.hb = hibit(xh);
-                    c.g0 = c.g1 = (int32_t)g;
-                    sc.push_back(c);
-                }
-                sc.back().g1 = (int32_t)g + 1;
-            }
+            sigma_classes(sg, sc);
             P.d_sclasses = dev_alloc<ClassDesc>(sc.size());
             P.d_sgroups = dev_alloc<GroupDesc>(sg.size());
             QF_HIP(hipMemcpy(P.d_sclasses, sc.data(), sc.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));

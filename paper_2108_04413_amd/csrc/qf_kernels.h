@@ -358,4 +358,119 @@ __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__r
     group_d4_part<LS>(g.kre, g.k1, zs, cs, Y, dim);
 }
 
+// Sigma over tiles of 2^kSigL outputs: groups whose flip masks agree above
+// bit kSigL form a class (ClassDesc, groups in class order), and for output
+// tile t every group of class c reads its partner amplitudes psi[y ^ x] from
+// the one tile t ^ xh_c.  That tile is staged in LDS once per class
+// (double-buffered: the next class's tile is in flight in registers while
+// this class is evaluated), so the state crosses HBM once per class instead
+// of being gathered once per group.  A thread of the kSigNT-thread workgroup
+// owns outputs tb | tid | 512 i (i < 4); D_g is evaluated at the partner
+// index.  Writes lam over the tile and adds the thread's share of
+// <psi|lam> on it to acc.  sp: two LDS buffers of 2^kSigL amplitudes; the function
+// ends with a workgroup barrier, after which sp may be reused.
+constexpr int kSigL = 11;
+constexpr int kSigNT = 512;
+
+__device__ __forceinline__ void sigma_tile(const double2 *__restrict__ psi, double2 *__restrict__ lam, uint32_t t,
+                                           const ClassDesc *__restrict__ classes, int ncls,
+                                           const GroupDesc *__restrict__ groups, int G,
+                                           const uint32_t *__restrict__ zs, const double *__restrict__ cs,
+                                           double2 (*__restrict__ sp)[1u << kSigL], double &acc)
+{
+    constexpr uint32_t T = 1u << kSigL;
+    constexpr int IT = (int)(T / kSigNT);
+    static_assert(IT == 4 && kSigNT == kItemStride, "four outputs 512 apart per thread");
+    const uint32_t tid = threadIdx.x;
+    const int lane = (int)(tid & 63u);
+    const uint32_t tb = t << kSigL;
+    double2 l[IT];
+#pragma unroll
+    for (int i = 0; i < IT; i++)
+        l[i] = make_double2(0.0, 0.0);
+    // the next partner tile, in flight in registers (four named values: an
+    // array carried around the class loop was put in scratch memory)
+    const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
+    double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
+            p3 = psi[pb0 | (tid + 3 * kSigNT)];
+    // Group descriptors reach the wave 64 at a time, one per lane (coalesced
+    // vector loads), and are broadcast by readlane: a scalar load per group
+    // from a table larger than the scalar cache left the pass latency-bound
+    // (~2500 clocks per group).  Strings are scalar loads (a readlane
+    // broadcast of them costs three VALU per string, which measured slower).
+    int gc = 0;
+    uint32_t gxv = 0;
+    int gk0v = 0, gkrev = 0, gk1v = 0;
+    auto load_groups = [&](int g) __attribute__((always_inline)) {
+        gc = g;
+        const GroupDesc d = groups[min(g + lane, G - 1)];
+        gxv = d.x;
+        gk0v = d.k0;
+        gkrev = d.kre;
+        gk1v = d.k1;
+    };
+    load_groups(0);
+    for (int c = 0; c < ncls; c++) {
+        double2 *buf = sp[c & 1];
+        buf[tid] = p0;
+        buf[tid + kSigNT] = p1;
+        buf[tid + 2 * kSigNT] = p2;
+        buf[tid + 3 * kSigNT] = p3;
+        const ClassDesc cd = classes[c];
+        {
+            // unconditional: the last class fetches its own tile again
+            const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
+            p0 = psi[pb | tid];
+            p1 = psi[pb | (tid + kSigNT)];
+            p2 = psi[pb | (tid + 2 * kSigNT)];
+            p3 = psi[pb | (tid + 3 * kSigNT)];
+        }
+        // buf is complete; its previous readers (class c - 2) passed the
+        // barrier of class c - 1 before anyone writes it again
+        __syncthreads();
+        for (int g = cd.g0; g < cd.g1; g++) {
+            if (g - gc >= 64)
+                load_groups(g);
+            const int jg = g - gc;
+            const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
+            const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
+            const int kre = __builtin_amdgcn_readlane(gkrev, jg);
+            const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
+            const uint32_t xl = gx & (T - 1u);
+            const uint32_t Y = (tb | tid) ^ gx;
+            double dre[IT], dimg[IT];
+#pragma unroll
+            for (int i = 0; i < IT; i++) {
+                dre[i] = 0.0;
+                dimg[i] = 0.0;
+            }
+            group_d4_part<kSigL - 2>(k0, kre, zs, cs, Y, dre);
+            if (k1 > kre) {
+                group_d4_part<kSigL - 2>(kre, k1, zs, cs, Y, dimg);
+#pragma unroll
+                for (int i = 0; i < IT; i++) {
+                    const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                    l[i].x += dre[i] * b.x - dimg[i] * b.y;
+                    l[i].y += dre[i] * b.y + dimg[i] * b.x;
+                }
+            } else {  // real phases only (every string of a real Hamiltonian)
+#pragma unroll
+                for (int i = 0; i < IT; i++) {
+                    const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                    l[i].x += dre[i] * b.x;
+                    l[i].y += dre[i] * b.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; i++) {
+        const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
+        lam[y] = l[i];
+        const double2 p = psi[y];
+        acc += p.x * l[i].x + p.y * l[i].y;
+    }
+    __syncthreads();  // the last class's buffer is read before sp is written again
+}
+
 } // namespace qf
