@@ -174,3 +174,46 @@ def test_batch_run_completion_matches_run(qf):
     assert all(np.array_equal(a, b) for a, b in zip(g, gc))
     assert np.all(np.isfinite(t_done)) and np.all(t_done > 0)
     check_vs_oracle(insts[1], Ec[1], gc[1])
+
+
+def random_instance(qf, n, seed, n_h=300, n_a=60):
+    """Random same-mask runs for the ansatz and a random Pauli sum with
+    odd-Y (imaginary-phase) strings and a 150-string diagonal group for H,
+    its groups handed over in shuffled order."""
+    rng = np.random.default_rng([n, seed, 5])
+    xs, zs = [], []
+    while len(xs) < n_a:
+        x = 0 if rng.random() < 0.2 else int(rng.integers(1, 1 << n))
+        for _ in range(int(rng.integers(1, 9))):
+            xs.append(x)
+            zs.append(int(rng.integers(0, 1 << n)))
+    ax, az = np.array(xs[:n_a], dtype=np.uint64), np.array(zs[:n_a], dtype=np.uint64)
+    hx, hz, hc = qi.random_paulis(n, n_h, seed + 1)
+    hx = np.concatenate([hx, np.zeros(150, np.uint64)])
+    hz = np.concatenate([hz, rng.integers(0, 1 << n, 150).astype(np.uint64)])
+    hc = np.concatenate([hc, rng.normal(size=150)])
+    order = np.lexsort((hz, hx))
+    hx, hz, hc = hx[order], hz[order], hc[order]
+    cut = [0] + [i for i in range(1, len(hx)) if hx[i] != hx[i - 1]] + [len(hx)]
+    parts = [np.arange(cut[g], cut[g + 1]) for g in rng.permutation(len(cut) - 1)]
+    idx = np.concatenate(parts)
+    hx, hz, hc = hx[idx], hz[idx], hc[idx]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    th = qi.random_angles(n_a, seed + 2, 1.0)
+    return dict(n=n, occ=(1 << (n // 2)) - 1, A=qf.terms_array(ax, az, np.ones(n_a)), theta=th,
+                H=qf.terms_array(hx, hz, hc), off=off, raw=(ax, az, hx, hz, hc))
+
+
+def test_batch_random_paulis_match_oracle(qf):
+    """General terms through the batched kernel: the class-tiled sigma (12
+    and 13 qubits: 2 and 4 tiles, imaginary phases, groups out of order)
+    beside the gather form (10 qubits), teams of 1, 2 and 4."""
+    insts = [random_instance(qf, 12, 81), random_instance(qf, 10, 82), random_instance(qf, 13, 83)]
+    B = qf.Batch(insts, team=[2, 1, 4])
+    E, grads = B.run([d["theta"] for d in insts], use_graph=False)
+    B.close()
+    for d, e, g in zip(insts, E, grads):
+        ax, az, hx, hz, hc = d["raw"]
+        e_o, g_o = core.energy_grad(d["n"], d["occ"], ax, az, d["theta"], hx, hz, hc)
+        assert e == pytest.approx(e_o, abs=E_TOL)
+        assert np.max(np.abs(g - g_o)) < G_TOL
