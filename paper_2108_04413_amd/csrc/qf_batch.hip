@@ -367,7 +367,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         for (int k = 0; k < kMaxRun; k++) {
             em[k] = d.e[k];
             sneg[k] = d.s[k] < 0 ? 1u : 0u;
-            acc[k] = 0.0;
+            acc[k] = -0.0;  // -0.0 + x is x, so the first term needs no add
         }
         auto accumulate = [&](uint32_t u, double q) __attribute__((always_inline)) {
             if (walsh) {
@@ -702,9 +702,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 // class tiles rank, rank + W, ... (a team has at most one member per tile);
                 // the two tile buffers are the sub-cube image
                 double2(*sp)[1u << kSigL] = reinterpret_cast<double2(*)[1u << kSigL]>(s_sub);
-                for (uint32_t t = (uint32_t)rank; t < (1u << (n - kSigL)); t += (uint32_t)W)
-                    sigma_tile(phi, lam, t, classes + en.cls0, en.ncls, groups + en.group0, en.G, zs + en.term0,
-                               cs + en.term0, sp, v[0]);
+                v[0] = sigma_tiles(phi, lam, (uint32_t)rank, (uint32_t)W, 1u << (n - kSigL), classes + en.cls0,
+                                   en.ncls, groups + en.group0, en.G, zs + en.term0, cs + en.term0, sp);
             } else {
                 member_slice(dim, W, rank, b, e);
                 v[0] = pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e);

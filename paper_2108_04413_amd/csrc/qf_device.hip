@@ -829,7 +829,7 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
-// Class-tiled sigma (sigma_tile): one workgroup per output tile at a time.
+// Class-tiled sigma (sigma_tiles): one workgroup per output tile at a time.
 __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restrict__ psi, double2 *__restrict__ lam,
                                                         int n, const ClassDesc *__restrict__ classes, int ncls,
                                                         const GroupDesc *__restrict__ groups, int G,
@@ -838,11 +838,8 @@ __global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restric
                                                         unsigned *counter, double *result)
 {
     __shared__ double2 sp[2][1u << kSigL];
-    const uint32_t ntiles = 1u << (n - kSigL);
-    double acc = 0.0;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        sigma_tile(psi, lam, t, classes, ncls, groups, G, zs, cs, sp, acc);
-    double vals[1] = {acc};
+    double vals[1] = {
+        sigma_tiles(psi, lam, blockIdx.x, gridDim.x, 1u << (n - kSigL), classes, ncls, groups, G, zs, cs, sp)};
     reduce_finish<1, kSigNT>(vals, partials, counter, result, 1.0, 1);
 }
 
@@ -918,7 +915,9 @@ constexpr int adj_threads(int B) { return B >= 10 ? 512 : (1 << B) / 2 >= 256 ? 
 // (-1)^p2 conj(la) b)], which is the imaginary part (a0 even) or the real
 // part (a0 odd) of the bracket, negated for a0 >= 2.  Undoing the run is
 // rot_pair with the factor (-1)^p i^(a0 + 1); SW = (a0 + 1) & 1, so SW also
-// selects Im.  dq31 is the sign of q relative to the rotation's signs.
+// selects Im.  dq31 is the sign of q relative to the rotation's signs.  The
+// items' q go to accumulate(u_0, du, q) together (du[k] = u_0 ^ u_k, the
+// same for every thread).
 template <bool SW, uint32_t NB, int NT, class Acc>
 __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const double2 *tb, const LocalRun &d,
                                               uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31,
@@ -927,11 +926,15 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
     constexpr int NP = NB / 2 >= (uint32_t)NT ? (int)(NB / 2 / NT) : 1;
     if (NB / 2 < (uint32_t)NT && threadIdx.x >= NB / 2)
         return;
+    const uint32_t i0 = item_part(item_table(d), 0) & 63u;
+    uint32_t du[NP];
+    double qs[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         const uint32_t ik = item_part(item_table(d), k);
         const uint32_t y1 = yt | insert0((uint32_t)k * NT, d.hbit), y2 = y1 ^ d.x;
         const uint32_t u = ut ^ (ik & 63u);
+        du[k] = i0 ^ (ik & 63u);
         const double2 cs = tb[u];
         const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
         double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
@@ -945,8 +948,9 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
         sp[y2] = b;
         sl[y1] = la;
         sl[y2] = lb;
-        accumulate(u, q);
+        qs[k] = q;
     }
+    accumulate(ut ^ i0, du, qs);
 }
 
 template <int B, int NT>
@@ -1022,19 +1026,19 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             for (int k = 0; k < kMaxRun; k++) {
                 em[k] = d.e[k];
                 sneg[k] = d.s[k] < 0 ? 1u : 0u;
-                acc[k] = 0.0;
+                acc[k] = -0.0;  // -0.0 + x is x, so the first term needs no add
             }
-            auto accumulate = [&](uint32_t u, double q) __attribute__((always_inline)) {
+            // items k of the thread have table indices u0 ^ du[k] (du uniform)
+            auto accumulate = [&](uint32_t u0, const auto &du, const auto &q) __attribute__((always_inline)) {
+                constexpr int N = (int)(sizeof(q) / sizeof(double));
                 if (walsh) {
-                    const uint32_t b1 = u << 31, b2 = (u >> 1) << 31, b4 = (u >> 2) << 31;
-                    const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
-#pragma unroll
-                    for (int e = 0; e < kMaxRun; e++)
-                        acc[e] += __hiloint2double(__double2hiint(q) ^ (int)sb[e], __double2loint(q));
+                    walsh_add<N>(acc, u0, du, q);
                 } else {
 #pragma unroll
-                    for (int k = 0; k < kMaxRun; k++)
-                        acc[k] += flip(q, (__popc(u & em[k]) ^ sneg[k]) & 1u);
+                    for (int i = 0; i < N; i++)
+#pragma unroll
+                        for (int k = 0; k < kMaxRun; k++)
+                            acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & em[k]) ^ sneg[k]) & 1u);
                 }
             };
             __syncthreads();  // the previous run's updates are visible
@@ -1051,18 +1055,22 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     adjoint_pairs<false, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
             } else {
                 const uint32_t ut = (pbz & 63u) ^ gf2_coords(tid, d.b);
+                const uint32_t i0 = item_part(item_table(d), 0);
+                uint32_t du[PER];
+                double qs[PER];
 #pragma unroll
                 for (int kk = 0; kk < PER; kk++) {
                     const uint32_t y = tid + (uint32_t)kk * NT;
                     const uint32_t u = ut ^ item_part(item_table(d), kk);
+                    du[kk] = i0 ^ item_part(item_table(d), kk);
                     const double2 cs = tb[u];
                     const double c = cs.x, s = cs.y;
                     const double2 a = sp[y], la = sl[y];
-                    const double q = la.x * a.y - la.y * a.x;
+                    qs[kk] = la.x * a.y - la.y * a.x;
                     sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
                     sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
-                    accumulate(u, q);
                 }
+                accumulate(ut ^ i0, du, qs);
             }
             {
                 const double h = wave_sum8(acc, lane);

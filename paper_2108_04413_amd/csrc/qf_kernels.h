@@ -204,10 +204,13 @@ __device__ __forceinline__ int sum8_index(int lane)
 
 __device__ __forceinline__ bool sum8_writer(int lane) { return (lane & 0x2c) == 0; }
 
+// Every control used here (quad_perm, row_ror with all rows and banks
+// enabled) reads a lane inside the same row, so no lane falls back to the
+// old value and none needs to be supplied (bound_ctrl).
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -262,6 +265,30 @@ __device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane)
     h += dpp_f64<kDppRor4>(h);
     h += dpp_f64<kDppRor8>(h);
     return sum_xor32_f64(h);
+}
+
+// One thread's share of one run in the 8 Walsh sums
+// W[e] += sum_k (-1)^popcount(u_k & e) q_k over its items k, whose table
+// indices are u_k = u0 ^ du[k] with du[k] the same for every thread:
+// W[e] += (-1)^popcount(u0 & e) sum_k (-1)^popcount(du[k] & e) q_k, the
+// inner signs uniform (FMAs by +-1.0) and the outer one a sign flip.  Equal
+// bit for bit to adding the signed terms one at a time (negation commutes
+// with rounding; an FMA by +-1.0 rounds as the add it stands for).
+__device__ __forceinline__ double pm_one(uint32_t m31);
+template <int N>
+__device__ __forceinline__ void walsh_add(double (&acc)[kMaxRun], uint32_t u0, const uint32_t (&du)[N],
+                                          const double (&q)[N])
+{
+    const uint32_t b1 = u0 << 31, b2 = (u0 >> 1) << 31, b4 = (u0 >> 2) << 31;
+    const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
+#pragma unroll
+    for (int e = 0; e < kMaxRun; e++) {
+        double r = q[0];
+#pragma unroll
+        for (int k = 1; k < N; k++)
+            r = fma(pm_one(par(du[k] & (uint32_t)e) << 31), q[k], r);
+        acc[e] += flip31(r, sb[e]);
+    }
 }
 
 // GF(2) coordinates of y against the masks bm (zero beyond the run's
@@ -334,9 +361,12 @@ __device__ __forceinline__ void group_d4_part(int k0, int k1, const uint32_t *__
 {
 #pragma unroll 2
     for (int k = k0; k < k1; k++) {
+        // both loads first: they then share one wait (loading c after the
+        // sign arithmetic on z had the compiler wait for each separately)
         const uint32_t z = zs[k];
+        const double c = cs[k];
         const uint32_t m1 = (z >> LS) << 31, m2 = (z >> (LS + 1)) << 31;
-        const double t = flip31(cs[k], (uint32_t)__popc(Y & z) << 31);
+        const double t = flip31(c, (uint32_t)__popc(Y & z) << 31);
         d[0] += t;
         d[1] = fma(pm_one(m1), t, d[1]);
         d[2] = fma(pm_one(m2), t, d[2]);
@@ -366,111 +396,117 @@ __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__r
 // this class is evaluated), so the state crosses HBM once per class instead
 // of being gathered once per group.  A thread of the kSigNT-thread workgroup
 // owns outputs tb | tid | 512 i (i < 4); D_g is evaluated at the partner
-// index.  Writes lam over the tile and adds the thread's share of
-// <psi|lam> on it to acc.  sp: two LDS buffers of 2^kSigL amplitudes; the function
-// ends with a workgroup barrier, after which sp may be reused.
+// index.  The workgroup takes tiles t0, t0 + dt, ... below ntiles, writes
+// lam over them and returns the thread's share of <psi|lam> on them.  sp:
+// two LDS buffers of 2^kSigL amplitudes; each tile ends with a workgroup
+// barrier, after which sp may be reused.
 constexpr int kSigL = 11;
 constexpr int kSigNT = 512;
 
-__device__ __forceinline__ void sigma_tile(const double2 *__restrict__ psi, double2 *__restrict__ lam, uint32_t t,
-                                           const ClassDesc *__restrict__ classes, int ncls,
-                                           const GroupDesc *__restrict__ groups, int G,
-                                           const uint32_t *__restrict__ zs, const double *__restrict__ cs,
-                                           double2 (*__restrict__ sp)[1u << kSigL], double &acc)
+__device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                              uint32_t t0, uint32_t dt, uint32_t ntiles,
+                                              const ClassDesc *__restrict__ classes, int ncls,
+                                              const GroupDesc *__restrict__ groups, int G,
+                                              const uint32_t *__restrict__ zs, const double *__restrict__ cs,
+                                              double2 (*__restrict__ sp)[1u << kSigL])
 {
     constexpr uint32_t T = 1u << kSigL;
     constexpr int IT = (int)(T / kSigNT);
     static_assert(IT == 4 && kSigNT == kItemStride, "four outputs 512 apart per thread");
     const uint32_t tid = threadIdx.x;
     const int lane = (int)(tid & 63u);
-    const uint32_t tb = t << kSigL;
-    double2 l[IT];
+    double acc = 0.0;
+    for (uint32_t t = t0; t < ntiles; t += dt) {
+        const uint32_t tb = t << kSigL;
+        double2 l[IT];
 #pragma unroll
-    for (int i = 0; i < IT; i++)
-        l[i] = make_double2(0.0, 0.0);
-    // the next partner tile, in flight in registers (four named values: an
-    // array carried around the class loop was put in scratch memory)
-    const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
-    double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
-            p3 = psi[pb0 | (tid + 3 * kSigNT)];
-    // Group descriptors reach the wave 64 at a time, one per lane (coalesced
-    // vector loads), and are broadcast by readlane: a scalar load per group
-    // from a table larger than the scalar cache left the pass latency-bound
-    // (~2500 clocks per group).  Strings are scalar loads (a readlane
-    // broadcast of them costs three VALU per string, which measured slower).
-    int gc = 0;
-    uint32_t gxv = 0;
-    int gk0v = 0, gkrev = 0, gk1v = 0;
-    auto load_groups = [&](int g) __attribute__((always_inline)) {
-        gc = g;
-        const GroupDesc d = groups[min(g + lane, G - 1)];
-        gxv = d.x;
-        gk0v = d.k0;
-        gkrev = d.kre;
-        gk1v = d.k1;
-    };
-    load_groups(0);
-    for (int c = 0; c < ncls; c++) {
-        double2 *buf = sp[c & 1];
-        buf[tid] = p0;
-        buf[tid + kSigNT] = p1;
-        buf[tid + 2 * kSigNT] = p2;
-        buf[tid + 3 * kSigNT] = p3;
-        const ClassDesc cd = classes[c];
-        {
-            // unconditional: the last class fetches its own tile again
-            const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
-            p0 = psi[pb | tid];
-            p1 = psi[pb | (tid + kSigNT)];
-            p2 = psi[pb | (tid + 2 * kSigNT)];
-            p3 = psi[pb | (tid + 3 * kSigNT)];
-        }
-        // buf is complete; its previous readers (class c - 2) passed the
-        // barrier of class c - 1 before anyone writes it again
-        __syncthreads();
-        for (int g = cd.g0; g < cd.g1; g++) {
-            if (g - gc >= 64)
-                load_groups(g);
-            const int jg = g - gc;
-            const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
-            const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
-            const int kre = __builtin_amdgcn_readlane(gkrev, jg);
-            const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
-            const uint32_t xl = gx & (T - 1u);
-            const uint32_t Y = (tb | tid) ^ gx;
-            double dre[IT], dimg[IT];
-#pragma unroll
-            for (int i = 0; i < IT; i++) {
-                dre[i] = 0.0;
-                dimg[i] = 0.0;
+        for (int i = 0; i < IT; i++)
+            l[i] = make_double2(0.0, 0.0);
+        // the next partner tile, in flight in registers (four named values: an
+        // array carried around the class loop was put in scratch memory)
+        const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
+        double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
+                p3 = psi[pb0 | (tid + 3 * kSigNT)];
+        // Group descriptors reach the wave 64 at a time, one per lane (coalesced
+        // vector loads), and are broadcast by readlane: a scalar load per group
+        // from a table larger than the scalar cache left the pass latency-bound
+        // (~2500 clocks per group).  Strings are scalar loads (a readlane
+        // broadcast of them costs three VALU per string, which measured slower).
+        int gc = 0;
+        uint32_t gxv = 0;
+        int gk0v = 0, gkrev = 0, gk1v = 0;
+        auto load_groups = [&](int g) __attribute__((always_inline)) {
+            gc = g;
+            const GroupDesc d = groups[min(g + lane, G - 1)];
+            gxv = d.x;
+            gk0v = d.k0;
+            gkrev = d.kre;
+            gk1v = d.k1;
+        };
+        load_groups(0);
+        for (int c = 0; c < ncls; c++) {
+            double2 *buf = sp[c & 1];
+            buf[tid] = p0;
+            buf[tid + kSigNT] = p1;
+            buf[tid + 2 * kSigNT] = p2;
+            buf[tid + 3 * kSigNT] = p3;
+            const ClassDesc cd = classes[c];
+            {
+                // unconditional: the last class fetches its own tile again
+                const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
+                p0 = psi[pb | tid];
+                p1 = psi[pb | (tid + kSigNT)];
+                p2 = psi[pb | (tid + 2 * kSigNT)];
+                p3 = psi[pb | (tid + 3 * kSigNT)];
             }
-            group_d4_part<kSigL - 2>(k0, kre, zs, cs, Y, dre);
-            if (k1 > kre) {
-                group_d4_part<kSigL - 2>(kre, k1, zs, cs, Y, dimg);
+            // buf is complete; its previous readers (class c - 2) passed the
+            // barrier of class c - 1 before anyone writes it again
+            __syncthreads();
+            for (int g = cd.g0; g < cd.g1; g++) {
+                if (g - gc >= 64)
+                    load_groups(g);
+                const int jg = g - gc;
+                const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
+                const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
+                const int kre = __builtin_amdgcn_readlane(gkrev, jg);
+                const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
+                const uint32_t xl = gx & (T - 1u);
+                const uint32_t Y = (tb | tid) ^ gx;
+                double dre[IT], dimg[IT];
 #pragma unroll
                 for (int i = 0; i < IT; i++) {
-                    const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                    l[i].x += dre[i] * b.x - dimg[i] * b.y;
-                    l[i].y += dre[i] * b.y + dimg[i] * b.x;
+                    dre[i] = 0.0;
+                    dimg[i] = 0.0;
                 }
-            } else {  // real phases only (every string of a real Hamiltonian)
+                group_d4_part<kSigL - 2>(k0, kre, zs, cs, Y, dre);
+                if (k1 > kre) {
+                    group_d4_part<kSigL - 2>(kre, k1, zs, cs, Y, dimg);
 #pragma unroll
-                for (int i = 0; i < IT; i++) {
-                    const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                    l[i].x += dre[i] * b.x;
-                    l[i].y += dre[i] * b.y;
+                    for (int i = 0; i < IT; i++) {
+                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                        l[i].x += dre[i] * b.x - dimg[i] * b.y;
+                        l[i].y += dre[i] * b.y + dimg[i] * b.x;
+                    }
+                } else {  // real phases only (every string of a real Hamiltonian)
+#pragma unroll
+                    for (int i = 0; i < IT; i++) {
+                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
+                        l[i].x += dre[i] * b.x;
+                        l[i].y += dre[i] * b.y;
+                    }
                 }
             }
         }
-    }
 #pragma unroll
-    for (int i = 0; i < IT; i++) {
-        const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
-        lam[y] = l[i];
-        const double2 p = psi[y];
-        acc += p.x * l[i].x + p.y * l[i].y;
+        for (int i = 0; i < IT; i++) {
+            const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
+            lam[y] = l[i];
+            const double2 p = psi[y];
+            acc += p.x * l[i].x + p.y * l[i].y;
+        }
+        __syncthreads();  // the last class's buffer is read before sp is written again
     }
-    __syncthreads();  // the last class's buffer is read before sp is written again
+    return acc;
 }
 
 } // namespace qf
