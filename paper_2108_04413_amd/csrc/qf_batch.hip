@@ -280,7 +280,7 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
             // rotation factor (-1)^p2 i^m with m = a0 + 3 (exp(-i theta P))
             const uint32_t m = (d.a0 + 3u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b, d.r);
             const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
             const uint32_t px31 = par(d.x & d.z0) << 31;
             if (m & 1u)
@@ -288,7 +288,7 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
             else
                 sub_apply_pairs<false>(st, tb, d, NB, yt, ut, pt31, px31);
         } else {
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
             for (int k = 0; (uint32_t)k * kBT < NB; k++) {
                 if (threadIdx.x + (uint32_t)k * kBT >= NB)
                     break;
@@ -386,7 +386,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         if (d.x) {
             const uint32_t m = (d.a0 + 1u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b, d.r);
             const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
             const uint32_t px31 = par(d.x & d.z0) << 31;
             const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
@@ -395,7 +395,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
             else
                 sub_adjoint_pairs<false>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
         } else {
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
             for (int k = 0; (uint32_t)k * kBT < NB; k++) {
                 if (threadIdx.x + (uint32_t)k * kBT >= NB)
                     break;

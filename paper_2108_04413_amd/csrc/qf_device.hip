@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
             // rotation factor is sgn (-1)^p2 i^m, m = a0 + 3
             const uint32_t m = (d.a0 + 3u) & 3u;
             const uint32_t yt = insert0(threadIdx.x, d.hbit);
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b, d.r);
             const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1) ^ sneg) << 31;
             const uint32_t px31 = par(d.x & d.z0) << 31;
             if (m & 1u)
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
             else
                 apply_pairs<false, NB, NT>(st, tb, d, yt, ut, pt31, px31);
         } else {
-            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b);
+            const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
 #pragma unroll
             for (int k = 0; k < PER; k++) {
                 const uint32_t y = threadIdx.x + (uint32_t)k * NT;
@@ -1045,7 +1045,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             if (d.x) {
                 const uint32_t m = (d.a0 + 1u) & 3u;
                 const uint32_t yt = insert0(tid, d.hbit);
-                const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b);
+                const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b, d.r);
                 const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
                 const uint32_t px31 = par(d.x & d.z0) << 31;
                 const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
@@ -1054,7 +1054,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 else
                     adjoint_pairs<false, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
             } else {
-                const uint32_t ut = (pbz & 63u) ^ gf2_coords(tid, d.b);
+                const uint32_t ut = (pbz & 63u) ^ gf2_coords(tid, d.b, d.r);
                 const uint32_t i0 = item_part(item_table(d), 0);
                 uint32_t du[PER];
                 double qs[PER];

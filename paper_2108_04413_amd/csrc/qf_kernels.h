@@ -292,13 +292,17 @@ __device__ __forceinline__ void walsh_add(double (&acc)[kMaxRun], uint32_t u0, c
 }
 
 // GF(2) coordinates of y against the masks bm (zero beyond the run's
-// rank): bit q is the parity of y & bm[q].  Linear in y.
-__device__ __forceinline__ uint32_t gf2_coords(uint32_t y, const uint32_t (&bm)[kMaxRank])
+// rank r): bit q is the parity of y & bm[q].  Linear in y.  Runs of rank
+// <= 3 (every single and double excitation) skip the upper three masks on a
+// uniform branch.
+__device__ __forceinline__ uint32_t gf2_coords(uint32_t y, const uint32_t (&bm)[kMaxRank], int r)
 {
-    uint32_t u = 0;
+    uint32_t u = par(y & bm[0]) | (par(y & bm[1]) << 1) | (par(y & bm[2]) << 2);
+    if (r > 3) {
 #pragma unroll
-    for (int q = 0; q < kMaxRank; q++)
-        u ^= par(y & bm[q]) << q;
+        for (int q = 3; q < kMaxRank; q++)
+            u ^= par(y & bm[q]) << q;
+    }
     return u;
 }
 
