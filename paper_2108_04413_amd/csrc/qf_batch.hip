@@ -157,6 +157,8 @@ constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 constexpr int kSub = 4096;
 static_assert(kSub >= (2 << kSigL) && kBT == kSigNT, "the sigma tile buffers fit the sub-cube image");
+// pairs per thread in the common sub-cubes (2^12 forward, 2^11 reverse), which get unrolled variants
+constexpr int kApplyPairs = kSub / 2 / kBT, kAdjPairs = kSub / 4 / kBT;
 
 // member's slice [b, e) of `units`, in whole tiles of kBT * kItems
 __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
@@ -243,12 +245,15 @@ __device__ __forceinline__ uint32_t subcube_base(uint32_t sc, uint32_t Q, int n)
 // items are t + k * kBT (kBT = kItemStride); table indices and Z-parities
 // split into the thread's part and the run's tabulated item parts, and the
 // phase of a flip run folds into signs (rot_pair).
-template <bool SW>
+// NP > 0: exactly NP pairs per thread (NB = 2 NP kBT), unrolled so that
+// their LDS reads are in flight together; NP = 0: as many as NB holds.
+template <bool SW, int NP>
 __device__ __forceinline__ void sub_apply_pairs(double2 *st, const double2 *tb, const LocalRun &d, uint32_t NB,
                                                 uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31)
 {
-    for (int k = 0; (uint32_t)k * kBT < NB / 2; k++) {
-        if (threadIdx.x + (uint32_t)k * kBT >= NB / 2)
+#pragma unroll
+    for (int k = 0; NP ? k < NP : (uint32_t)k * kBT < NB / 2; k++) {
+        if (!NP && threadIdx.x + (uint32_t)k * kBT >= NB / 2)
             break;
         const uint32_t ik = item_part(item_table(d), k);
         const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
@@ -283,10 +288,16 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
             const uint32_t ut = (pbz & 63u) ^ gf2_coords(yt, d.b, d.r);
             const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
             const uint32_t px31 = par(d.x & d.z0) << 31;
-            if (m & 1u)
-                sub_apply_pairs<true>(st, tb, d, NB, yt, ut, pt31, px31);
-            else
-                sub_apply_pairs<false>(st, tb, d, NB, yt, ut, pt31, px31);
+            if (NB == 2u * kApplyPairs * kBT) {
+                if (m & 1u)
+                    sub_apply_pairs<true, kApplyPairs>(st, tb, d, NB, yt, ut, pt31, px31);
+                else
+                    sub_apply_pairs<false, kApplyPairs>(st, tb, d, NB, yt, ut, pt31, px31);
+            } else if (m & 1u) {
+                sub_apply_pairs<true, 0>(st, tb, d, NB, yt, ut, pt31, px31);
+            } else {
+                sub_apply_pairs<false, 0>(st, tb, d, NB, yt, ut, pt31, px31);
+            }
         } else {
             const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
             for (int k = 0; (uint32_t)k * kBT < NB; k++) {
@@ -308,13 +319,19 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
 // Reverse-sweep pairs of one flip run (q and the undo as in the single-
 // instance blocked adjoint: rotation factor (-1)^p i^(a0 + 1), q the
 // imaginary (a0 even) or real (a0 odd) part of the pair's bracket).
-template <bool SW, class Acc>
+// NP as in sub_apply_pairs; the items' q reach accumulate(u_0, du, q)
+// together when NP > 0 (du[k] = u_0 ^ u_k, uniform), one at a time otherwise.
+template <bool SW, int NP, class Acc>
 __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, const double2 *tb, const LocalRun &d,
                                                   uint32_t NB, uint32_t yt, uint32_t ut, uint32_t pt31,
                                                   uint32_t px31, uint32_t dq31, Acc &&accumulate)
 {
-    for (int k = 0; (uint32_t)k * kBT < NB / 2; k++) {
-        if (threadIdx.x + (uint32_t)k * kBT >= NB / 2)
+    const uint32_t i0 = item_part(item_table(d), 0) & 63u;
+    uint32_t du[NP ? NP : 1];
+    double qs[NP ? NP : 1];
+#pragma unroll
+    for (int k = 0; NP ? k < NP : (uint32_t)k * kBT < NB / 2; k++) {
+        if (!NP && threadIdx.x + (uint32_t)k * kBT >= NB / 2)
             break;
         const uint32_t ik = item_part(item_table(d), k);
         const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
@@ -332,8 +349,17 @@ __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, cons
         sp[y2] = b;
         sl[y1] = la;
         sl[y2] = lb;
-        accumulate(u, q);
+        if constexpr (NP > 0) {
+            du[k] = i0 ^ (ik & 63u);
+            qs[k] = q;
+        } else {
+            const uint32_t d1[1] = {0u};
+            const double q1[1] = {q};
+            accumulate(u, d1, q1);
+        }
     }
+    if constexpr (NP > 0)
+        accumulate(ut ^ i0, du, qs);
 }
 
 // Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and
@@ -369,17 +395,17 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
             sneg[k] = d.s[k] < 0 ? 1u : 0u;
             acc[k] = -0.0;  // -0.0 + x is x, so the first term needs no add
         }
-        auto accumulate = [&](uint32_t u, double q) __attribute__((always_inline)) {
+        // items i of the thread have table indices u0 ^ du[i] (du uniform)
+        auto accumulate = [&](uint32_t u0, const auto &du, const auto &q) __attribute__((always_inline)) {
+            constexpr int N = (int)(sizeof(q) / sizeof(double));
             if (walsh) {
-                const uint32_t b1 = u << 31, b2 = (u >> 1) << 31, b4 = (u >> 2) << 31;
-                const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
-#pragma unroll
-                for (int e = 0; e < kMaxRun; e++)
-                    acc[e] += __hiloint2double(__double2hiint(q) ^ (int)sb[e], __double2loint(q));
+                walsh_add<N>(acc, u0, du, q);
             } else {
 #pragma unroll
-                for (int k = 0; k < kMaxRun; k++)
-                    acc[k] += flip(q, (__popc(u & em[k]) ^ sneg[k]) & 1u);
+                for (int i = 0; i < N; i++)
+#pragma unroll
+                    for (int k = 0; k < kMaxRun; k++)
+                        acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & em[k]) ^ sneg[k]) & 1u);
             }
         };
         __syncthreads();  // the previous run's updates are visible
@@ -390,10 +416,16 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
             const uint32_t pt31 = (par(yt & d.z0) ^ (pbz >> 6) ^ (m >> 1)) << 31;
             const uint32_t px31 = par(d.x & d.z0) << 31;
             const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
-            if (m & 1u)
-                sub_adjoint_pairs<true>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
-            else
-                sub_adjoint_pairs<false>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+            if (NB == 2u * kAdjPairs * kBT) {
+                if (m & 1u)
+                    sub_adjoint_pairs<true, kAdjPairs>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+                else
+                    sub_adjoint_pairs<false, kAdjPairs>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+            } else if (m & 1u) {
+                sub_adjoint_pairs<true, 0>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+            } else {
+                sub_adjoint_pairs<false, 0>(sp, sl, tb, d, NB, yt, ut, pt31, px31, dq31, accumulate);
+            }
         } else {
             const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
             for (int k = 0; (uint32_t)k * kBT < NB; k++) {
@@ -407,7 +439,9 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
                 const double q = la.x * a.y - la.y * a.x;
                 sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
                 sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
-                accumulate(u, q);
+                const uint32_t d1[1] = {0u};
+                const double q1[1] = {q};
+                accumulate(u, d1, q1);
             }
         }
         {
