@@ -451,12 +451,11 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         }
         __syncthreads();
         if (threadIdx.x < (uint32_t)d.m) {
-            uint64_t epk = 0, spk = 0;
-#pragma unroll
-            for (int k = 0; k < kMaxRun; k++) {
-                epk |= (uint64_t)d.e[k] << (8 * k);
-                spk |= (uint64_t)(d.s[k] < 0 ? 1u : 0u) << (8 * k);
-            }
+            // (byte k of e and s is string k's; the sign bit of s_k moves to bit 0)
+            uint64_t epk, spk;
+            __builtin_memcpy(&epk, d.e, sizeof epk);
+            __builtin_memcpy(&spk, d.s, sizeof spk);
+            spk = (spk >> 7) & 0x0101010101010101ull;
             const int col = walsh ? (int)((epk >> (8 * threadIdx.x)) & 0xffu) : (int)threadIdx.x;
             double v = 0.0;
 #pragma unroll

@@ -1007,12 +1007,10 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             sp[l] = phi[y];
             sl[l] = lam[y];
         }
-        // descriptors are read one run ahead, so their load overlaps a run
-        LocalRun dnext = lruns[sg.r1 - 1];
         for (int ri = nr - 1; ri >= 0; ri--) {
-            const LocalRun d = dnext;
-            if (ri > 0)
-                dnext = lruns[sg.r0 + ri - 1];
+            // (the descriptors stay in the scalar cache over the sub-cubes of
+            // a segment; reading them a run ahead cost ~60 register copies per run)
+            const LocalRun d = lruns[sg.r0 + ri];
             const double2 *tb = stab + (d.tab - sg.tab0);
             const uint32_t pbz = spbz[ri];
             // string k's weight is eps_k = s_k (-1)^popcount(u & e_k) with
@@ -1082,12 +1080,11 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 // lane k's string fields from the uniform descriptor, packed
                 // into 64-bit words (indexing its register copy by lane would
                 // go through scratch memory)
-                uint64_t epk = 0, spk = 0;
-#pragma unroll
-                for (int k = 0; k < kMaxRun; k++) {
-                    epk |= (uint64_t)d.e[k] << (8 * k);
-                    spk |= (uint64_t)(d.s[k] < 0 ? 1u : 0u) << (8 * k);
-                }
+                // (byte k of e and s is string k's; the sign bit of s_k moves to bit 0)
+                uint64_t epk, spk;
+                __builtin_memcpy(&epk, d.e, sizeof epk);
+                __builtin_memcpy(&spk, d.s, sizeof spk);
+                spk = (spk >> 7) & 0x0101010101010101ull;
                 const int col = walsh ? (int)((epk >> (8 * tid)) & 0xffu) : (int)tid;
                 double v = 0.0;
 #pragma unroll

@@ -69,6 +69,7 @@ struct LocalRun {
     int8_t s[kMaxRun];
     uint32_t itm[2];                // per-item table-index and parity parts
 };
+static_assert(kMaxRun == 8, "e and s of a LocalRun fill one 64-bit word each");
 
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
 // are fixed, so the factor (-1)^popcount(y_hi & z_hi) of every string is a
