@@ -387,14 +387,10 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         // pass sums the 8 Walsh terms (-1)^popcount(u & e) q and string k
         // takes s_k times term e_k; otherwise acc[k] is string k's own sum
         const bool walsh = d.r <= 3;
-        uint32_t em[kMaxRun], sneg[kMaxRun];
         double acc[kMaxRun];
 #pragma unroll
-        for (int k = 0; k < kMaxRun; k++) {
-            em[k] = d.e[k];
-            sneg[k] = d.s[k] < 0 ? 1u : 0u;
+        for (int k = 0; k < kMaxRun; k++)
             acc[k] = -0.0;  // -0.0 + x is x, so the first term needs no add
-        }
         // items i of the thread have table indices u0 ^ du[i] (du uniform)
         auto accumulate = [&](uint32_t u0, const auto &du, const auto &q) __attribute__((always_inline)) {
             constexpr int N = (int)(sizeof(q) / sizeof(double));
@@ -405,7 +401,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
                 for (int i = 0; i < N; i++)
 #pragma unroll
                     for (int k = 0; k < kMaxRun; k++)
-                        acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & em[k]) ^ sneg[k]) & 1u);
+                        acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & d.e[k]) ^ (d.s[k] < 0 ? 1u : 0u)) & 1u);
             }
         };
         __syncthreads();  // the previous run's updates are visible

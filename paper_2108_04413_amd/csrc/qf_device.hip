@@ -1018,14 +1018,10 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             // Walsh sums W[e] = sum (-1)^popcount(u & e) q (acc[e]) and string
             // k takes s_k W[e_k] afterwards; for r > 3, acc[k] is string k's sum.
             const bool walsh = d.r <= 3;
-            uint32_t em[kMaxRun], sneg[kMaxRun];
             double acc[kMaxRun];
 #pragma unroll
-            for (int k = 0; k < kMaxRun; k++) {
-                em[k] = d.e[k];
-                sneg[k] = d.s[k] < 0 ? 1u : 0u;
+            for (int k = 0; k < kMaxRun; k++)
                 acc[k] = -0.0;  // -0.0 + x is x, so the first term needs no add
-            }
             // items k of the thread have table indices u0 ^ du[k] (du uniform)
             auto accumulate = [&](uint32_t u0, const auto &du, const auto &q) __attribute__((always_inline)) {
                 constexpr int N = (int)(sizeof(q) / sizeof(double));
@@ -1036,7 +1032,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     for (int i = 0; i < N; i++)
 #pragma unroll
                         for (int k = 0; k < kMaxRun; k++)
-                            acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & em[k]) ^ sneg[k]) & 1u);
+                            acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & d.e[k]) ^ (d.s[k] < 0 ? 1u : 0u)) & 1u);
                 }
             };
             __syncthreads();  // the previous run's updates are visible

@@ -282,12 +282,22 @@ __device__ __forceinline__ void walsh_add(double (&acc)[kMaxRun], uint32_t u0, c
 {
     const uint32_t b1 = u0 << 31, b2 = (u0 >> 1) << 31, b4 = (u0 >> 2) << 31;
     const uint32_t sb[kMaxRun] = {0u, b1, b2, b1 ^ b2, b4, b1 ^ b4, b2 ^ b4, b1 ^ b2 ^ b4};
+    // the uniform signs (-1)^popcount(du[k] & e) by the same XOR table
+    uint32_t sd[N][kMaxRun];
+#pragma unroll
+    for (int k = 1; k < N; k++) {
+        const uint32_t c1 = du[k] << 31, c2 = (du[k] >> 1) << 31, c4 = (du[k] >> 2) << 31;
+        const uint32_t t[kMaxRun] = {0u, c1, c2, c1 ^ c2, c4, c1 ^ c4, c2 ^ c4, c1 ^ c2 ^ c4};
+#pragma unroll
+        for (int e = 0; e < kMaxRun; e++)
+            sd[k][e] = t[e];
+    }
 #pragma unroll
     for (int e = 0; e < kMaxRun; e++) {
         double r = q[0];
 #pragma unroll
         for (int k = 1; k < N; k++)
-            r = fma(pm_one(par(du[k] & (uint32_t)e) << 31), q[k], r);
+            r = fma(pm_one(sd[k][e]), q[k], r);
         acc[e] += flip31(r, sb[e]);
     }
 }
