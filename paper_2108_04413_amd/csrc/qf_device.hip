@@ -1252,7 +1252,18 @@ void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::
         gd[(size_t)g].hbit = hibit((uint32_t)x);
         gd[(size_t)g].k0 = (int32_t)a;
         gd[(size_t)g].k1 = (int32_t)b;
-        gd[(size_t)g].pad = 0;
+        // the item-sign pattern of each phase part (0xF: the strings differ)
+        auto pattern = [&](int64_t k0, int64_t k1) {
+            int p = -1;
+            for (int64_t k = k0; k < k1; k++) {
+                const int q = (int)((zs[(size_t)k] >> kPatBit) & 3u);
+                if (p >= 0 && q != p)
+                    return 15;
+                p = q;
+            }
+            return p < 0 ? 0 : p;
+        };
+        gd[(size_t)g].pat = pattern(a, gd[(size_t)g].kre) | (pattern(gd[(size_t)g].kre, b) << 4);
     }
 }
 

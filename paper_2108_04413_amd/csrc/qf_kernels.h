@@ -24,8 +24,13 @@ struct RunDesc {
 
 struct GroupDesc {
     uint32_t x, hbit;
-    int32_t k0, kre, k1, pad;  // [k0,kre): real phase, [kre,k1): imaginary phase
+    int32_t k0, kre, k1;  // [k0,kre): real phase, [kre,k1): imaginary phase
+    // item-sign pattern of the sigma passes (items 512 apart): bits 0-3 the
+    // value of (z >> kPatBit) & 3 shared by all real-phase strings, bits 4-7
+    // that of the imaginary-phase strings, 0xF where the strings differ
+    int32_t pat;
 };
+constexpr int kPatBit = 9;
 
 // Blocked application of consecutive runs.  A segment is a range of runs
 // whose flip masks all lie inside a set Q of B qubits that contains the
@@ -389,6 +394,31 @@ __device__ __forceinline__ void group_d4_part(int k0, int k1, const uint32_t *__
     }
 }
 
+// As group_d4_part for LS = kPatBit, with the strings' common item-sign
+// pattern p (0..3) when they share one: then the signed sum runs once and
+// item i takes (-1)^popcount(i & p) times it (bit for bit the per-item sums:
+// the item signs are exact); p > 3 falls back to per-string signs.
+__device__ __forceinline__ void group_d4_part_pat(int k0, int k1, int p, const uint32_t *__restrict__ zs,
+                                                  const double *__restrict__ cs, uint32_t Y, double (&d)[4])
+{
+    if (p > 3) {
+        group_d4_part<kPatBit>(k0, k1, zs, cs, Y, d);
+        return;
+    }
+    double a = -0.0;
+#pragma unroll 2
+    for (int k = k0; k < k1; k++) {
+        const uint32_t z = zs[k];
+        const double c = cs[k];
+        a += flip31(c, (uint32_t)__popc(Y & z) << 31);
+    }
+    const uint32_t m1 = (uint32_t)p << 31, m2 = ((uint32_t)p >> 1) << 31;
+    d[0] += a;
+    d[1] += flip31(a, m1);
+    d[2] += flip31(a, m2);
+    d[3] += flip31(a, m1 ^ m2);
+}
+
 template <int LS>
 __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__restrict__ zs,
                                          const double *__restrict__ cs, uint32_t Y, double (&dre)[4],
@@ -399,8 +429,13 @@ __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__r
         dre[i] = 0.0;
         dim[i] = 0.0;
     }
-    group_d4_part<LS>(g.k0, g.kre, zs, cs, Y, dre);
-    group_d4_part<LS>(g.kre, g.k1, zs, cs, Y, dim);
+    if constexpr (LS == kPatBit) {
+        group_d4_part_pat(g.k0, g.kre, g.pat & 15, zs, cs, Y, dre);
+        group_d4_part_pat(g.kre, g.k1, (g.pat >> 4) & 15, zs, cs, Y, dim);
+    } else {
+        group_d4_part<LS>(g.k0, g.kre, zs, cs, Y, dre);
+        group_d4_part<LS>(g.kre, g.k1, zs, cs, Y, dim);
+    }
 }
 
 // Sigma over tiles of 2^kSigL outputs: groups whose flip masks agree above
@@ -449,7 +484,7 @@ __device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, d
         // broadcast of them costs three VALU per string, which measured slower).
         int gc = 0;
         uint32_t gxv = 0;
-        int gk0v = 0, gkrev = 0, gk1v = 0;
+        int gk0v = 0, gkrev = 0, gk1v = 0, gpatv = 0;
         auto load_groups = [&](int g) __attribute__((always_inline)) {
             gc = g;
             const GroupDesc d = groups[min(g + lane, G - 1)];
@@ -457,6 +492,7 @@ __device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, d
             gk0v = d.k0;
             gkrev = d.kre;
             gk1v = d.k1;
+            gpatv = d.pat;
         };
         load_groups(0);
         for (int c = 0; c < ncls; c++) {
@@ -485,6 +521,7 @@ __device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, d
                 const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
                 const int kre = __builtin_amdgcn_readlane(gkrev, jg);
                 const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
+                const int pat = __builtin_amdgcn_readlane(gpatv, jg);
                 const uint32_t xl = gx & (T - 1u);
                 const uint32_t Y = (tb | tid) ^ gx;
                 double dre[IT], dimg[IT];
@@ -493,9 +530,10 @@ __device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, d
                     dre[i] = 0.0;
                     dimg[i] = 0.0;
                 }
-                group_d4_part<kSigL - 2>(k0, kre, zs, cs, Y, dre);
+                static_assert(kSigL - 2 == kPatBit, "items 2^(kSigL - 2) apart");
+                group_d4_part_pat(k0, kre, pat & 15, zs, cs, Y, dre);
                 if (k1 > kre) {
-                    group_d4_part<kSigL - 2>(kre, k1, zs, cs, Y, dimg);
+                    group_d4_part_pat(kre, k1, (pat >> 4) & 15, zs, cs, Y, dimg);
 #pragma unroll
                     for (int i = 0; i < IT; i++) {
                         const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
