@@ -49,6 +49,7 @@ struct BatchEntry {
     int32_t dseg0, ndseg, dlr0;  // reverse-sweep segments
     int32_t Bapp, Badj;          // their sub-cube sizes (qubits)
     int32_t cls0, ncls;          // sigma classes (ClassDesc; groups in class order), 0: untiled sigma
+    int32_t tabs0;               // the runs' (cos, sin) tables in the launch's table array
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
 
@@ -192,27 +193,22 @@ __device__ void load_table(const RunDesc &d, const double *__restrict__ theta, d
     __syncthreads();
 }
 
-// (cos, sin) entries of a segment's runs from theta: run d's entry u goes to
-// tab[d.tab - tab0 + u] (the same values as load_table for that run)
-__device__ void seg_tables(const LocalRun *__restrict__ lr, int r0, int r1, int tab0,
-                           const double *__restrict__ theta, double2 *tab)
+// (cos, sin) entries of one run from theta: entry u of run d goes to
+// tab[d.tab + u] (the values load_table computes for that run)
+__device__ void run_table(const RunDesc &d, const double *__restrict__ theta, double2 *tab)
 {
-    for (int ri = r0; ri < r1; ri++) {
-        const LocalRun &d = lr[ri];
-        const uint32_t u = threadIdx.x;
-        if (u < (1u << d.r)) {
-            double th = 0.0;
+    for (int u = threadIdx.x; u < (1 << d.r); u += kBT) {
+        double th = 0.0;
 #pragma unroll
-            for (int k = 0; k < kMaxRun; k++) {
-                if (k < d.m) {
-                    const double v = (double)d.s[k] * theta[d.k0 + k];
-                    th += (__popc(u & d.e[k]) & 1) ? -v : v;
-                }
+        for (int k = 0; k < kMaxRun; k++) {
+            if (k < d.m) {
+                const double v = (double)d.s[k] * theta[d.k0 + k];
+                th += (__popc((uint32_t)u & d.e[k]) & 1) ? -v : v;
             }
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            tab[d.tab - tab0 + (int)u] = make_double2(cs, sn);
         }
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        tab[d.tab + u] = make_double2(cs, sn);
     }
 }
 
@@ -647,7 +643,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                unsigned total_tickets, const RunDesc *__restrict__ runs,
                                                const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
                                                const GroupDesc *__restrict__ groups,
-                                               const ClassDesc *__restrict__ classes, const uint32_t *__restrict__ zs,
+                                               const ClassDesc *__restrict__ classes, double2 *__restrict__ tabs,
+                                               const uint32_t *__restrict__ zs,
                                                const double *__restrict__ cs, const double *__restrict__ theta,
                                                double2 *states, double *partials, unsigned *sync, unsigned *ticket,
                                                unsigned *err, double *E_out, double *grad_out, unsigned spin_limit,
@@ -704,6 +701,9 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
 
         member_slice(dim, W, rank, b, e);
         pass_prepare(phi, b, e, en.occ);
+        // the runs' (cos, sin) tables, once per launch (runs rank, rank + W, ...)
+        for (int r = rank; r < en.nruns; r += W)
+            run_table(runs[en.run0 + r], th, tabs + en.tabs0);
         team_sync(W, ts, ++epoch, spin_limit, err);
 
         // forward: segments of runs on sub-cubes, members take sub-cubes rank, rank + W, ...
@@ -716,7 +716,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 pass_apply(phi, d, s_tab, b, e);
             } else {
                 const LocalRun *lr = lruns + en.alr0;
-                seg_tables(lr, sg.r0, sg.r1, sg.tab0, th, s_tab);
+                for (int t = (int)threadIdx.x; t < sg.ntab; t += kBT)
+                    s_tab[t] = tabs[en.tabs0 + sg.tab0 + t];
                 seg_hoff(sg, s_hoff);
                 const uint32_t nsub = 1u << (n - en.Bapp);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
@@ -762,7 +763,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const LocalRun *lr = lruns + en.dlr0;
                 const int sk0 = lr[sg.r0].k0;
                 const int nstr = lr[sg.r1 - 1].k0 + lr[sg.r1 - 1].m - sk0;
-                seg_tables(lr, sg.r0, sg.r1, sg.tab0, th, s_tab);
+                for (int t = (int)threadIdx.x; t < sg.ntab; t += kBT)
+                    s_tab[t] = tabs[en.tabs0 + sg.tab0 + t];
                 seg_hoff(sg, s_hoff);
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     s_lacc[t] = 0.0;
@@ -829,6 +831,7 @@ struct qf_batch {
     qf::LocalRun *d_lruns = nullptr;
     qf::GroupDesc *d_groups = nullptr;
     qf::ClassDesc *d_classes = nullptr;
+    double2 *d_tabs = nullptr;  // (cos, sin) tables of every instance's runs, filled in the launch
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
     double *d_theta = nullptr;
@@ -907,7 +910,7 @@ struct BatchHost {
     std::vector<uint32_t> zs;
     std::vector<double> cs;
     uint64_t state_amps = 0;
-    int64_t tickets = 0, parts = 0;
+    int64_t tickets = 0, parts = 0, tabs = 0;
 };
 
 // Validate the instances, pick team sizes and assemble the host tables.
@@ -1013,6 +1016,7 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         e.term0 = (int32_t)T.zs.size();
         e.cls0 = (int32_t)T.cls.size();
         e.ncls = (int32_t)sc.size();
+        e.tabs0 = (int32_t)T.tabs;
         e.theta0 = (int32_t)B.koff[(size_t)i];
         e.ticket0 = (int32_t)T.tickets;
         e.part0 = (int32_t)T.parts;
@@ -1026,10 +1030,11 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.zs.insert(T.zs.end(), z.begin(), z.end());
         T.cs.insert(T.cs.end(), c.begin(), c.end());
         T.state_amps += 2ull << n;
+        T.tabs += tab;
         T.tickets += e.W;
         T.parts += (int64_t)e.W * e.K + e.W;
         if (T.zs.size() > (size_t)INT32_MAX || T.tickets > INT32_MAX || T.parts > INT32_MAX ||
-            T.lruns.size() > (size_t)INT32_MAX)
+            T.lruns.size() > (size_t)INT32_MAX || T.tabs > INT32_MAX)
             raise(QF_E_ARG, "batch too large");
     }
     B.nentries = (int)T.ent.size();
@@ -1040,23 +1045,23 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[16];
+    size_t off[17];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[16] = {
+    const size_t sizes[17] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
         (size_t)T.parts * sizeof(double), T.ent.size() * kSyncWords * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
-        std::max<size_t>(T.cls.size(), 1) * sizeof(ClassDesc)};
+        std::max<size_t>(T.cls.size(), 1) * sizeof(ClassDesc), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 16; i++) {
+    for (int i = 0; i < 17; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -1082,6 +1087,7 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_segs = (Segment *)(base + L.off[13]);
     B.d_lruns = (LocalRun *)(base + L.off[14]);
     B.d_classes = (ClassDesc *)(base + L.off[15]);
+    B.d_tabs = (double2 *)(base + L.off[16]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -1119,7 +1125,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_classes, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_classes, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }
