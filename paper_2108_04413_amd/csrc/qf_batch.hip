@@ -262,11 +262,14 @@ __device__ __forceinline__ void sub_apply_pairs(double2 *st, const double2 *tb, 
     }
 }
 
+// FIXNB: the sub-cube size when it is the common 2^12 (compile-time loops),
+// 0 for 2^B
+template <uint32_t FIXNB>
 __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const Segment &sg,
                           const LocalRun *__restrict__ lr, const double2 *tab, const uint32_t *hoff, double2 *st,
                           uint32_t *pbzs)
 {
-    const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
+    const uint32_t NB = FIXNB ? FIXNB : 1u << B, lomask = (1u << sg.q0) - 1u;
     // (the previous sub-cube's runs have all read pbzs: barrier before its write-back)
     sub_parities(lr, sg.r0, sg.r1 - sg.r0, base, pbzs, (int)threadIdx.x, kBT);
     __syncthreads();  // the previous sub-cube's LDS image is written back
@@ -361,12 +364,14 @@ __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, cons
 // Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and
 // lambda (sl), adding each run's 2 Im <lambda|P_k|phi> / 2 per string to
 // lacc[k - sk0] before the run is undone.
+// FIXNB: the sub-cube size when it is the common 2^11, 0 for 2^B
+template <uint32_t FIXNB>
 __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, int B, uint32_t base,
                             const Segment &sg, const LocalRun *__restrict__ lr, const double2 *tab,
                             const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc, double (*red)[kMaxRun],
                             int sk0, uint32_t *pbzs)
 {
-    const uint32_t NB = 1u << B, lomask = (1u << sg.q0) - 1u;
+    const uint32_t NB = FIXNB ? FIXNB : 1u << B, lomask = (1u << sg.q0) - 1u;
     const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
     sub_parities(lr, sg.r0, sg.r1 - sg.r0, base, pbzs, (int)threadIdx.x, kBT);
     __syncthreads();  // the previous sub-cube's LDS images are written back
@@ -720,8 +725,13 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                     s_tab[t] = tabs[en.tabs0 + sg.tab0 + t];
                 seg_hoff(sg, s_hoff);
                 const uint32_t nsub = 1u << (n - en.Bapp);
-                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
-                    sub_apply(phi, en.Bapp, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub, s_pbz);
+                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
+                    const uint32_t base = subcube_base(sc, sg.Q, n);
+                    if (en.Bapp == 12)
+                        sub_apply<(uint32_t)kSub>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
+                    else
+                        sub_apply<0>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
+                }
             }
             team_sync(W, ts, ++epoch, spin_limit, err);
         }
@@ -769,9 +779,15 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     s_lacc[t] = 0.0;
                 const uint32_t nsub = 1u << (n - en.Badj);
-                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W)
-                    sub_adjoint(phi, lam, en.Badj, subcube_base(sc, sg.Q, n), sg, lr, s_tab, s_hoff, s_sub,
-                                s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
+                for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
+                    const uint32_t base = subcube_base(sc, sg.Q, n);
+                    if (en.Badj == 11)
+                        sub_adjoint<(uint32_t)kSub / 2>(phi, lam, en.Badj, base, sg, lr, s_tab, s_hoff, s_sub,
+                                                        s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
+                    else
+                        sub_adjoint<0>(phi, lam, en.Badj, base, sg, lr, s_tab, s_hoff, s_sub, s_sub + (kSub / 2),
+                                       s_lacc, s_red, sk0, s_pbz);
+                }
                 __syncthreads();
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];
