@@ -225,18 +225,6 @@ __device__ void seg_hoff(const Segment &sg, uint32_t *hoff)
     }
 }
 
-// sub-cube sc: its index bits scattered into the qubits outside Q
-__device__ __forceinline__ uint32_t subcube_base(uint32_t sc, uint32_t Q, int n)
-{
-    uint32_t base = 0, k = 0;
-    for (int p = 0; p < n; p++)
-        if (!((Q >> p) & 1u)) {
-            base |= ((sc >> k) & 1u) << p;
-            k++;
-        }
-    return base;
-}
-
 // Apply a segment's runs to one 2^B sub-cube held in st (LDS).  Thread t's
 // items are t + k * kBT (kBT = kItemStride); table indices and Z-parities
 // split into the thread's part and the run's tabulated item parts, and the
@@ -726,7 +714,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 seg_hoff(sg, s_hoff);
                 const uint32_t nsub = 1u << (n - en.Bapp);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
-                    const uint32_t base = subcube_base(sc, sg.Q, n);
+                    const uint32_t base = subcube_base(sc, sg);
                     if (en.Bapp == 12)
                         sub_apply<(uint32_t)kSub>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
                     else
@@ -780,7 +768,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                     s_lacc[t] = 0.0;
                 const uint32_t nsub = 1u << (n - en.Badj);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
-                    const uint32_t base = subcube_base(sc, sg.Q, n);
+                    const uint32_t base = subcube_base(sc, sg);
                     if (en.Badj == 11)
                         sub_adjoint<(uint32_t)kSub / 2>(phi, lam, en.Badj, base, sg, lr, s_tab, s_hoff, s_sub,
                                                         s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);

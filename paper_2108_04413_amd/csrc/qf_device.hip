@@ -196,15 +196,7 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, i
     __shared__ double2 stab[kSegTab];
     __shared__ uint32_t spbz[kSegRuns];
     // base: the block index scattered into the qubits outside Q
-    uint32_t base = 0;
-    {
-        uint32_t k = 0;
-        for (int p = 0; p < n; p++)
-            if (!((sg.Q >> p) & 1u)) {
-                base |= ((blockIdx.x >> k) & 1u) << p;
-                k++;
-            }
-    }
+    const uint32_t base = subcube_base(blockIdx.x, sg);
     const uint32_t lomask = (1u << sg.q0) - 1u;
     if (threadIdx.x < (1u << sg.nhi)) {
         uint32_t o = 0;
@@ -988,15 +980,7 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
     const uint32_t nsub = 1u << (n - B);
     const int nr = sg.r1 - sg.r0;
     for (uint32_t sc = blockIdx.x; sc < nsub; sc += gridDim.x) {
-        uint32_t base = 0;
-        {
-            uint32_t k = 0;
-            for (int p = 0; p < n; p++)
-                if (!((sg.Q >> p) & 1u)) {
-                    base |= ((sc >> k) & 1u) << p;
-                    k++;
-                }
-        }
+        const uint32_t base = subcube_base(sc, sg);
         // (the previous sub-cube's runs have all read spbz: barrier before its write-back)
         sub_parities(lruns, sg.r0, nr, base, spbz, (int)tid, NT);
         __syncthreads();  // tables staged; the previous sub-cube is written back

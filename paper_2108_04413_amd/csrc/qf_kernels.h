@@ -120,6 +120,19 @@ __device__ __forceinline__ uint32_t insert0(uint32_t j, uint32_t bit)
     return ((j ^ lo) << 1) | lo;
 }
 
+// Sub-cube sc of a segment: its index bits, in order, at the qubits outside
+// Q (Q = qubits 0..q0-1 and hi[0] < ... < hi[nhi-1]): shift past the low
+// run, then open a zero at each of Q's higher qubits, lowest first.
+__device__ __forceinline__ uint32_t subcube_base(uint32_t sc, const Segment &sg)
+{
+    uint32_t v = sc << sg.q0;
+#pragma unroll
+    for (int j = 0; j < 8; j++)
+        if (j < sg.nhi)
+            v = insert0(v, sg.hi[j]);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t par(uint32_t v) { return __popc(v) & 1u; }
 
 // v * i^k
