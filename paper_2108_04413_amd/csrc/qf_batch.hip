@@ -7,8 +7,9 @@
 // [ticket0_e, ticket0_e + W_e).  Every workgroup of the persistent grid takes
 // tickets from one device counter; ticket t makes it member t - ticket0_e of
 // the team of the instance that owns t.  A team runs the instance's passes
-// (prepare, each fused run forward, sigma = H psi, each run backward) on
-// disjoint slices of the state and meets at a team barrier after every pass:
+// (prepare and the run tables, each forward segment of runs on sub-cubes,
+// sigma = H psi over class tiles, each reverse segment) on disjoint parts of
+// the state and meets at a team barrier after every pass:
 // W = 1 teams only need the workgroup barrier, so small states stay in the
 // CU's L2; larger teams use an agent-scope counter barrier with a bounded
 // spin (timeout -> error flag, every wave still exits).  The grid never

@@ -4,20 +4,31 @@
 // A Pauli string P(x, z) = i^popcount(x&z) X^x Z^z maps |y> to
 // omega(y) |y ^ x>, omega(y) = i^(popcount(x&z) + 2 popcount(y&z)).
 //
-// Kernels (all HBM-bound streaming passes; FP64 throughout):
-//   k_prepare      one write pass: psi = |occ>.
-//   k_run_tables   per fused run, cos/sin of the combined angle for each
-//                  sign pattern (tiny).
-//   k_apply_run    one pass per run of consecutive commuting strings that
-//                  share the flip mask x: every amplitude pair (y, y^x) gets
-//                  one 2x2 rotation (Sec. 2.1.4 exponentials, fused).
-//   k_energy       all flip-mask groups in one launch: per pair,
-//                  2 Re conj(psi[y^x]) D_g(y) psi[y] with D_g(y) = sum of
-//                  c_k omega_k(y) over the group (Sec. 3.1, Eq. (17)).
-//   k_sigma        lambda = H psi by gathering psi[y ^ x_g] for every group,
-//                  fused with E = Re <psi|lambda>.
-//   k_adjoint_run  reverse sweep step for one run: 2 Im <lambda|P_k|phi> for
-//                  each string of the run, then phi, lambda <- U_run^dagger.
+// Kernels (FP64 throughout):
+//   k_prepare        one write pass: psi = |occ>.
+//   k_run_tables     per fused run, cos/sin of the combined angle for each
+//                    sign pattern (tiny).
+//   k_apply_block    a segment of runs (flip masks inside one set Q of B
+//                    qubits) applied to LDS sub-cubes of 2^B amplitudes:
+//                    one HBM read and write of the state per segment (the
+//                    ordered product of Sec. 2.1.4 exponentials, fused).
+//   k_apply_run /    one pass per run too wide for a sub-cube: every pair
+//   k_apply_diag     (y, y^x) gets one 2x2 rotation (a phase if x = 0).
+//   k_energy_stream  <psi|H|psi> over tiles of 2^11 amplitudes: groups whose
+//                    flip masks agree above bit 11 form a class, one state
+//                    read per class, strings merged per tile (Sec. 3.1,
+//                    Eq. (17)), work items interleaved over the classes;
+//                    k_energy_tiled / k_energy_merged walk the same items
+//                    class by class (per string / merged), k_energy makes
+//                    one pass per group.
+//   k_sigma_tiled    lambda = H psi over the same classes (the partner tile
+//                    staged in LDS), fused with E = Re <psi|lambda>; k_sigma
+//                    gathers psi[y ^ x_g] per group below 12 qubits.
+//   k_adjoint_block  reverse sweep over a segment on LDS sub-cubes of phi and
+//                    lambda: 2 Im <lambda|P_k|phi> for each string of a run,
+//                    then phi, lambda <- U_run^dagger; k_grad_reduce adds
+//                    the per-workgroup string sums; k_adjoint_run is the
+//                    one-run form.
 // Reductions are deterministic: per-block partials in a fixed shape, then
 // the last block to finish (ticket counter) sums them in index order.
 #include <hip/hip_runtime.h>
@@ -183,7 +194,7 @@ __device__ __forceinline__ void apply_pairs(double2 *st, const double2 *tb, cons
 // The segment's (cos, sin) tables are staged in LDS with the sub-cube, and
 // so are the parities of the sub-cube's fixed bits against every run.
 template <int B, int NT>
-__global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, int n, Segment sg,
+__global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, Segment sg,
                                                         const LocalRun *__restrict__ lruns,
                                                         const double2 *__restrict__ tab, double sgn)
 {
@@ -1743,7 +1754,7 @@ template <int B> void launch_block(qf_plan &P, double2 *psi, const Segment &sg, 
     // 512 threads (8 waves) per sub-cube: enough loads in flight per CU at
     // 2^11..2^12 elements while the LDS image still admits two workgroups.
     constexpr int NT = (1 << B) < 512 ? (1 << B) : 512;
-    hipLaunchKernelGGL((k_apply_block<B, NT>), dim3((unsigned)(1ull << (P.n - B))), dim3(NT), 0, s, psi, P.n, sg,
+    hipLaunchKernelGGL((k_apply_block<B, NT>), dim3((unsigned)(1ull << (P.n - B))), dim3(NT), 0, s, psi, sg,
                        P.d_lruns, P.d_tab, sgn);
 }
 
