@@ -538,6 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(const double2 *__restr
     constexpr uint32_t T = 1u << LT;
     constexpr int W = kBlock;  // staged groups / records per window
     static_assert(T == (uint32_t)kBlock * NI, "one tile per block pass");
+    static_assert(NI == 8, "slot i of a thread is bits 8..10 of y_lo");
     __shared__ double2 tile[T];
     __shared__ uint4 sgrp[W];  // x & (T-1), kre, k1
     __shared__ uint4 srec[W];  // z_lo | emit << 31, z_hi, c (lo, hi word)
@@ -691,23 +692,15 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(const double2 *__restr
                     next_lo(z, ce);
                     const uint32_t zl = z & (T - 1u);
                     const double s0 = __hiloint2double((int)(0x3FF00000u | (__popc(tid & zl) << 31)), 0);
-#define QF_LO_CASE(K)                                                                               \
-    case K:                                                                                         \
-        _Pragma("unroll") for (int i = 0; i < NI; i++) d[i] =                                       \
-            fma(s0, (__builtin_popcount((unsigned)(i & K)) & 1) ? -ce : ce, d[i]);                  \
-        break;
-                    switch (zl >> 8) {
-                        QF_LO_CASE(0)
-                        QF_LO_CASE(1)
-                        QF_LO_CASE(2)
-                        QF_LO_CASE(3)
-                        QF_LO_CASE(4)
-                        QF_LO_CASE(5)
-                        QF_LO_CASE(6)
-                    default:
-                        QF_LO_CASE(7)
-                    }
-#undef QF_LO_CASE
+                    // slot i's sign (-1)^popcount(i & K), K = bits 8..10 of
+                    // z_lo, from an XOR table of K's bits: uniform sign words
+                    // on the coefficient, no branch on K
+                    const uint32_t K = zl >> 8;
+                    const uint32_t c1 = K << 31, c2 = (K >> 1) << 31, c4 = (K >> 2) << 31;
+                    const uint32_t sk[NI] = {0u, c1, c2, c1 ^ c2, c4, c1 ^ c4, c2 ^ c4, c1 ^ c2 ^ c4};
+#pragma unroll
+                    for (int i = 0; i < NI; i++)
+                        d[i] = fma(s0, flip31(ce, sk[i]), d[i]);
                 }
             };
 
