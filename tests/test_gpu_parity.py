@@ -453,3 +453,39 @@ def test_blocked_adjoint_20q_matches_golden(qf, B):
     assert np.max(np.abs(g - np.array(gold["grad_theta"]))) < G_TOL
     e2, g2 = plan.energy_grad(occ, th, ws)
     assert e2 == e_g and np.array_equal(g2, g)
+
+
+@pytest.mark.parametrize("n", [12, 14])
+def test_sigma_shared_pattern_groups_match_oracle(qf, n):
+    """Groups of several strings whose z bits 9 and 10 agree within each
+    phase part (the summed form of the class-tiled sigma), with real- and
+    imaginary-phase parts of different patterns, beside groups whose parts
+    mix patterns (per-string signs)."""
+    rng = np.random.default_rng([n, 97])
+    xs, zs = [], []
+    for g in range(60):
+        x = int(rng.integers(1, 1 << n))
+        shared = g % 2 == 0
+        pat = {0: int(rng.integers(0, 4)), 1: int(rng.integers(0, 4))}  # per phase parity
+        for _ in range(int(rng.integers(3, 9))):
+            z = int(rng.integers(0, 1 << n))
+            if shared:
+                ph = bin(x & z).count("1") & 1
+                z = (z & ~(3 << 9)) | (pat[ph] << 9)
+                if bin(x & z).count("1") & 1 != ph:  # bits 9, 10 of x changed the phase: flip a free z bit
+                    free = [q for q in range(n) if q not in (9, 10) and (x >> q) & 1]
+                    if not free:
+                        continue
+                    z ^= 1 << free[0]
+            xs.append(x)
+            zs.append(z)
+    xs, zs = np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64)
+    cs = rng.normal(size=len(xs))
+    xs, zs, cs, off = grouped(xs, zs, cs)
+    psi0 = qi.random_state(n, 98 + n)
+    plan = qf.Plan(n, None, qf.terms_array(xs, zs, cs), off)
+    lam = torch.empty_like(dev(psi0))
+    e = plan.sigma(dev(psi0), lam)
+    want = core.sigma(psi0, n, xs, zs, cs)
+    assert np.max(np.abs(host(lam) - want)) < 1e-11
+    assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
