@@ -1,12 +1,15 @@
-"""Write oracle reference values for the 20- and 28-qubit workloads.
+"""Write oracle reference values for the 20- and 28-qubit workloads and for
+the largest instances of the batched and served mixes.
 
 Calls only the CPU oracle (oracle/) and the seeded input module.  Usage:
 
-    python tests/golden/make_golden.py 20q     # ~1 min on 8 cores
-    python tests/golden/make_golden.py 28q     # hours on 8 cores
+    python tests/golden/make_golden.py 20q       # ~1 min on 8 cores
+    python tests/golden/make_golden.py 28q       # hours on 8 cores
+    python tests/golden/make_golden.py batch22q  # ~5 min: first 22-qubit instance of the batched mix
+    python tests/golden/make_golden.py serve24q  # ~30 min: first 24-qubit request of the serving trace
 
 Each output JSON holds the recipe, the energy, sampled final-state
-amplitudes, and (20q) the full gradient dE/dtheta and dE/dt.
+amplitudes, and (all but 28q) the full gradient dE/dtheta and dE/dt.
 """
 import json
 import os
@@ -29,8 +32,22 @@ def sample_indices(n, psi, seed, count=256):
     return np.unique(np.concatenate([rand, top]))
 
 
+def mix_recipe(name):
+    """Recipe of the first instance of the named size in the batched mix
+    (256 instances) or the serving trace (10 000 requests)."""
+    if name.startswith("batch"):
+        nq = int(name[5:-1])
+        idx, rcp = next((i, r) for i, r in enumerate(qi.batched_instances(256)) if 2 * r["n_orb"] == nq)
+    else:
+        nq = int(name[5:-1])
+        idx, (_, rcp) = next((j, tr) for j, tr in enumerate(qi.serving_trace(10000)) if 2 * tr[1]["n_orb"] == nq)
+    w = dict(rcp)
+    w["mix_index"] = idx
+    return w, *qi.integrals(w["n_orb"], w["n_elec"], w["seed"])
+
+
 def system(name):
-    w, h, g = qi.workload(name)
+    w, h, g = mix_recipe(name) if name.startswith(("batch", "serve")) else qi.workload(name)
     n = 2 * w["n_orb"]
     hx, hz, hc, goff = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
     if w["ansatz"] == "uccd_top":

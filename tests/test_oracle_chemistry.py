@@ -361,3 +361,92 @@ def test_c_core_hf_energy_20q():
     x, z, c, off = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
     psi = core.prepare(20, an.reference_mask(10))
     assert core.energy(psi, 20, x, z, c, off) == pytest.approx(hf_closed_shell(h, g, 5), abs=1e-11)
+
+
+# ---------------------------------------------- diagonal strings, <N>
+
+def _diag_mix(n, count, seed):
+    """Random strings with every third one diagonal (x = 0, Z-only, with the
+    identity among them): the x = 0 branch of the C core's exponential."""
+    xs, zs, cs = qi.random_paulis(n, count, seed)
+    rng = np.random.default_rng([seed, 5])
+    for k in range(0, count, 3):
+        xs[k] = 0
+        zs[k] = 0 if k == 0 else int(rng.integers(1, 1 << n))
+    return xs, zs, cs
+
+
+def test_c_core_exp_matches_matrix_exponential():
+    # exp(-i theta P) by scipy's matrix exponential of the dense Kronecker
+    # matrix: neither the cos/sin identity nor the pair loop is involved.
+    from scipy.linalg import expm
+    n = 6
+    psi0 = qi.random_state(n, 31)
+    xs, zs, _ = _diag_mix(n, 18, 32)
+    th = qi.random_angles(18, 33)
+    assert sum(1 for x in xs if int(x) == 0) >= 5
+    for x, z, t in zip(xs, zs, th):
+        want = expm(-1j * float(t) * dense.pauli_matrix(int(x), int(z), n)) @ psi0
+        got = core.apply_product(psi0.copy(), n, [x], [z], [t])
+        assert np.allclose(got, want, atol=1e-13), (int(x), int(z))
+
+
+def test_c_core_diagonal_runs_energy_sigma_dense():
+    n = 8
+    psi0 = qi.random_state(n, 41)
+    xs, zs, cs = _diag_mix(n, 45, 42)
+    th = qi.random_angles(45, 43)
+    a = core.apply_product(psi0.copy(), n, xs, zs, th)
+    u = np.eye(1 << n, dtype=np.complex128)
+    for x, z, t in zip(xs, zs, th):
+        u = (math.cos(t) * np.eye(1 << n) - 1j * math.sin(t) * dense.pauli_matrix(int(x), int(z), n)) @ u
+    assert np.allclose(a, u @ psi0, atol=1e-13)
+    order = np.lexsort((zs, xs))
+    hx, hz, hc = xs[order], zs[order], cs[order]
+    goff = [0] + [i for i in range(1, len(hx)) if hx[i] != hx[i - 1]] + [len(hx)]
+    assert hx[0] == 0 and goff[1] >= 5  # a diagonal group of several strings
+    hm = dense.pauli_sum_matrix(hx, hz, hc, n)
+    assert core.energy(a, n, hx, hz, hc, goff) == pytest.approx(np.vdot(a, hm @ a).real, abs=1e-12)
+    assert np.allclose(core.sigma(a, n, hx, hz, hc), hm @ a, atol=1e-12)
+
+
+def test_c_core_gradient_with_diagonal_runs_vs_dense_shift():
+    # E(theta) through dense matrices; the exact shift rule of P^2 = I
+    # gives dE/dtheta_k = E(theta_k + pi/4) - E(theta_k - pi/4).
+    n = 8
+    occ = 0b00110101
+    xs, zs, _ = _diag_mix(n, 24, 51)
+    th = qi.random_angles(24, 52)
+    hx, hz, hc = qi.random_paulis(n, 30, 53, max_weight=4)
+    order = np.lexsort((hz, hx))
+    hx, hz, hc = hx[order], hz[order], hc[order]
+    hm = dense.pauli_sum_matrix(hx, hz, hc, n)  # Hermitian: real coefficients of Hermitian strings
+    pm = [dense.pauli_matrix(int(x), int(z), n) for x, z in zip(xs, zs)]
+
+    def e_dense(theta):
+        v = np.zeros(1 << n, dtype=np.complex128)
+        v[occ] = 1
+        for P, t in zip(pm, theta):
+            v = math.cos(t) * v - 1j * math.sin(t) * (P @ v)
+        return float(np.vdot(v, hm @ v).real)
+
+    e, g = core.energy_grad(n, occ, xs, zs, th, hx, hz, hc)
+    assert e == pytest.approx(e_dense(th), abs=1e-12)
+    for k in range(len(th)):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += math.pi / 4
+        tm[k] -= math.pi / 4
+        assert g[k] == pytest.approx(e_dense(tp) - e_dense(tm), abs=1e-11), k
+
+
+def test_number_expectation_matches_dense_operators(sys8):
+    n = sys8["n"]
+    N, _, _ = sz_number_s2(n)
+    n_alpha = dense.fermion_matrix([(1.0, (p,), (p,)) for p in range(0, n, 2)], n)
+    for seed in (61, 62):
+        psi = qi.random_state(n, seed)
+        assert sv.number_expectation(psi, n) == pytest.approx(np.vdot(psi, N @ psi).real, abs=1e-12)
+        alpha = sum(1 << p for p in range(0, n, 2))
+        assert sv.number_expectation(psi, n, alpha) == pytest.approx(np.vdot(psi, n_alpha @ psi).real, abs=1e-12)
+    psi = sv.apply_product(sv.prepare(n, sys8["occ"]), n, sys8["ax"], sys8["az"], sys8["th"])
+    assert sv.number_expectation(psi, n) == pytest.approx(4.0, abs=1e-12)
