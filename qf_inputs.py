@@ -52,14 +52,16 @@ def integrals(n_orb: int, n_elec: int, seed: int):
     h = h + h.T - np.diag(np.diag(h))
     for i in range((int(n_elec) + 1) // 2):
         h[i, i] -= 2.0
-    pairs = [(p, q) for p in range(n) for q in range(p + 1)]
-    classes = [(pairs[a], pairs[b]) for a in range(len(pairs)) for b in range(a + 1)]
-    vals = 0.1 * rng.standard_normal(len(classes))
+    # compound pairs (p, q), q <= p, in row-major order; classes (pq, rs)
+    # with rs <= pq, again row-major; one draw per class, in that order
+    P, Q = np.tril_indices(n)
+    ca, cb = np.tril_indices(len(P))
+    p, q, r, s = P[ca], Q[ca], P[cb], Q[cb]
+    vals = 0.1 * rng.standard_normal(len(ca))
     g = np.zeros((n, n, n, n))
-    for ((p, q), (r, s)), v in zip(classes, vals):
-        for (a, b, c, d) in ((p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
-                             (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)):
-            g[a, b, c, d] = v
+    for (a, b, c, d) in ((p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
+                         (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)):
+        g[a, b, c, d] = vals  # every index tuple lies in exactly one class
     return h, g
 
 
