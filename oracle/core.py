@@ -45,6 +45,7 @@ def lib():
         L.orc_vdot.argtypes = [_dp, _dp, ctypes.c_int, _dp, _dp]
         L.orc_energy_grad.argtypes = [ctypes.c_int, ctypes.c_uint64, _u64p, _u64p, _dp, ctypes.c_int64,
                                       _u64p, _u64p, _dp, ctypes.c_int64, _dp, _dp, _dp]
+        L.orc_pool_grad.argtypes = [_dp, _dp, ctypes.c_int, _u64p, _u64p, _dp, _i64p, ctypes.c_int64, _dp]
         L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -114,3 +115,13 @@ def energy_grad(n: int, occ: int, ax, az, th, hx, hz, hc):
                           _p(hx, _u64p), _p(hz, _u64p), _p(hc, _dp), len(hx),
                           _p(work, _dp), ctypes.byref(E), _p(grad, _dp))
     return float(E.value), grad
+
+
+def pool_grad(psi: np.ndarray, lam: np.ndarray, n: int, xs, zs, cs, off) -> np.ndarray:
+    """g_nu = -2 sum_{k in nu} c_k Im <lam|P_k|psi> (ADAPT pool gradients, lam = H psi)."""
+    xs, zs, cs = _u64(xs), _u64(zs), _f64(cs)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    g = np.zeros(len(off) - 1)
+    lib().orc_pool_grad(_p(psi.view(np.float64), _dp), _p(lam.view(np.float64), _dp), n, _p(xs, _u64p),
+                        _p(zs, _u64p), _p(cs, _dp), _p(off, _i64p), len(off) - 1, _p(g, _dp))
+    return g

@@ -259,3 +259,19 @@ void orc_energy_grad(int n, uint64_t occ, const uint64_t *ax, const uint64_t *az
         orc_apply_exp(lam, n, ax[k], az[k], -th[k]);
     }
 }
+
+/*
+ * ADAPT pool gradients (Sec. 3.2): for each pool member nu with strings
+ * off[nu] .. off[nu+1], g[nu] = -2 sum_k c_k Im <lam|P_k|psi>, which is
+ * 2 Re <lam|kappa_nu psi> for JW(kappa_nu) = i sum_k c_k P_k and lam = H psi.
+ */
+void orc_pool_grad(const double *psi, const double *lam, int n, const uint64_t *xs, const uint64_t *zs,
+                   const double *cs, const int64_t *off, int64_t npool, double *g)
+{
+    for (int64_t nu = 0; nu < npool; nu++) {
+        nsum acc = {0.0, 0.0};
+        for (int64_t k = off[nu]; k < off[nu + 1]; k++)
+            nadd(&acc, -2.0 * cs[k] * im_expval(lam, psi, n, xs[k], zs[k]));
+        g[nu] = acc.s + acc.c;
+    }
+}

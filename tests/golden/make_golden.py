@@ -6,7 +6,8 @@ Calls only the CPU oracle (oracle/) and the seeded input module.  Usage:
     python tests/golden/make_golden.py 20q       # ~1 min on 8 cores
     python tests/golden/make_golden.py 28q       # hours on 8 cores
     python tests/golden/make_golden.py batch22q  # ~5 min: first 22-qubit instance of the batched mix
-    python tests/golden/make_golden.py serve24q  # ~30 min: first 24-qubit request of the serving trace
+    python tests/golden/make_golden.py serve24q  # ~1 h: first 24-qubit request of the serving trace
+    python tests/golden/make_golden.py 20q_pool  # ADAPT pool gradients on the 20-qubit final state
 
 Each output JSON holds the recipe, the energy, sampled final-state
 amplitudes, and (all but 28q) the full gradient dE/dtheta and dE/dt.
@@ -62,7 +63,29 @@ def system(name):
     return w, n, an.reference_mask(w["n_elec"]), (hx, hz, hc, goff), (ax, az, ac, off, th, t)
 
 
+def main_pool(name):
+    """ADAPT pool gradients (Sec. 3.2) on the final state of a workload."""
+    from oracle import adapt
+    base = name[:-len("_pool")]
+    t0 = time.time()
+    w, n, occ, (hx, hz, hc, goff), (ax, az, ac, off, th, t) = system(base)
+    ops, px, pz, pc, poff = adapt.pool_terms(n)
+    print(f"{name}: pool of {len(ops)} operators, {len(px)} strings", flush=True)
+    psi = core.apply_product(core.prepare(n, occ), n, ax, az, th)
+    lam = core.sigma(psi, n, hx, hz, hc)
+    g = core.pool_grad(psi, lam, n, px, pz, pc, poff)
+    out = dict(workload=base, recipe=w, n_qubits=n, occ_mask=occ, n_pool=len(ops), n_pool_strings=len(px),
+               energy=core.vdot(psi, lam, n).real, pool_grad=g.tolist(), oracle_threads=core.threads(),
+               seconds=time.time() - t0)
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, f"{time.time() - t0:.0f}s", flush=True)
+
+
 def main(name):
+    if name.endswith("_pool"):
+        return main_pool(name)
     t0 = time.time()
     w, n, occ, (hx, hz, hc, goff), (ax, az, ac, off, th, t) = system(name)
     print(f"{name}: {len(hx)} strings, {len(goff) - 1} groups, K={len(ax)}", flush=True)
