@@ -58,7 +58,8 @@ typedef enum qf_kind {
     QF_UCCSD = 1,       /* kappa_mu for all S_z-conserving singles + doubles */
     QF_UCCD = 2,        /* kappa_mu for all S_z-conserving doubles */
     QF_UCCD_TOP = 3,    /* the top_k doubles by |t_rank|, canonical order */
-    QF_PUCCD = 4        /* paired (seniority-zero) doubles of Sec. 5 */
+    QF_PUCCD = 4,       /* paired (seniority-zero) doubles of Sec. 5 */
+    QF_GSD_POOL = 5     /* ADAPT pool of Sec. 3.2: generalized singles + doubles */
 } qf_kind;
 
 /*
@@ -86,6 +87,11 @@ typedef enum qf_kind {
  *   lower canonical index m), keeps top_k and emits them in canonical order;
  *   t_rank has one value per double in QF_UCCD order.  kept[] (may be NULL)
  *   receives, per emitted excitation, its index in the unfiltered list.
+ *   QF_GSD_POOL (n_elec ignored): the generalized pool of ADAPT-VQE
+ *   (Sec. 3.2), every S_z-conserving tau = a+_p a_q with p > q (singles,
+ *   ordered by (q, p)) and tau = a+_p a+_q a_s a_r with p < q, r < s,
+ *   (p, q) after (r, s) lexicographically, index sets allowed to overlap
+ *   (doubles, ordered by ((r, s), (p, q))); strings as for the ansatz kinds.
  *
  * Sizes: with out == NULL only *n_out and *n_off are written (QF_OK).  With
  * cap < *n_out or off_cap < *n_off the sizes are written and QF_E_SIZE is
@@ -156,6 +162,21 @@ typedef struct qf_plan qf_plan;
 
 int qf_plan_create(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
                    const int64_t *group_off, int64_t n_groups, qf_plan **out);
+/*
+ * A plan whose device tables live in the caller's device buffer `arena`
+ * (256-byte aligned, arena_bytes long, owned by the caller; the plan never
+ * frees it), for serving loops that must not allocate or free device memory
+ * while other work runs.  *need_bytes receives the bytes the tables need;
+ * with arena == NULL nothing else happens (size query, QF_OK); a smaller
+ * arena gives QF_E_SIZE.  Tables are uploaded on `stream` before the call
+ * returns.  block_bits and energy_tile fix the apply blocking and the energy
+ * tile as qf_plan_set_block_bits and qf_plan_set_energy_tile (merged) would
+ * (< 0: the defaults); the two setters reject arena plans.
+ * qf_plan_destroy releases the plan's host memory only.
+ */
+int qf_plan_create_arena(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
+                         const int64_t *group_off, int64_t n_groups, int block_bits, int energy_tile,
+                         void *arena, int64_t arena_bytes, int64_t *need_bytes, void *stream, qf_plan **out);
 int qf_plan_destroy(qf_plan *plan);
 /* as qf_apply_pauli_exp with the plan's ansatz */
 int qf_plan_apply(qf_plan *plan, void *psi, const double *theta, int inverse, void *stream);
@@ -203,6 +224,32 @@ int qf_plan_apply_info(const qf_plan *plan, int *block_bits, int64_t *runs, int6
 int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, void *stream);
 
 /*
+ * ADAPT-VQE pool gradients (Sec. 3.2).  For Psi = U(theta)|occ_mask> (U as
+ * in qf_apply_pauli_exp) and each pool member nu with JW(kappa_nu) =
+ * i sum_k c_k P_k (strings pool[pool_off[nu] .. pool_off[nu+1]), one flip
+ * mask per member, e.g. from qf_build_paulis(QF_GSD_POOL)):
+ *   g_nu = <Psi|[H, kappa_nu]|Psi> = 2 Re <H Psi|kappa_nu Psi>
+ *        = -sum_k c_k 2 Im <H Psi|P_k|Psi>,
+ * the derivative of the energy with respect to t of exp(t kappa_nu)
+ * appended to the ansatz, at t = 0.  One forward pass, lambda = H Psi, then
+ * read-only passes over (Psi, lambda) that evaluate every pool string.
+ * workspace: 2 * 2^n_qubits * 16 bytes of device memory (Psi, lambda; on
+ * return they hold Psi and H Psi).  E_out (the energy) and g_out (n_pool
+ * values, caller order) are host memory.
+ * qf_plan_create_pool makes a plan of a pool for repeated calls;
+ * qf_plan_pool_grad takes a plan holding the ansatz and Hamiltonian and a
+ * pool plan of the same qubit count.
+ */
+int qf_pool_grad(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta, int64_t K,
+                 const qf_term *H, const int64_t *group_off, int64_t n_groups, const qf_term *pool,
+                 const int64_t *pool_off, int64_t n_pool, void *workspace, double *E_out, double *g_out,
+                 void *stream);
+int qf_plan_create_pool(int n_qubits, const qf_term *pool, const int64_t *pool_off, int64_t n_pool,
+                        qf_plan **out);
+int qf_plan_pool_grad(qf_plan *plan, qf_plan *pool, uint64_t occ_mask, const double *theta, void *workspace,
+                      double *E_out, double *g_out, void *stream);
+
+/*
  * Batches: energy and adjoint gradient of many instances (different
  * molecules, qubit counts or parameter vectors) in ONE persistent kernel
  * launch, optionally replayed as a HIP graph.  Sec. 3.1, Eqs. (16)-(18)
@@ -226,8 +273,13 @@ int qf_plan_sigma(qf_plan *plan, const void *psi, void *lambda, double *E_out, v
  *   as theta, may be NULL) are host memory, valid on return.  use_graph != 0
  *   captures the launch (theta upload, counter reset, persistent kernel,
  *   result copies) into a HIP graph on the first call and replays it after.
- *   A team barrier that waits longer than the spin limit sets an error flag;
- *   the kernel still exits and the call returns QF_E_HIP.
+ *   A team barrier that waits longer than the spin limit sets that
+ *   instance's error flag: its members stop waiting, the kernel still
+ *   exits, the other instances complete normally, and the call returns
+ *   QF_E_HIP after writing every output; qf_batch_status tells which
+ *   instances failed (their outputs are meaningless).
+ * qf_batch_status: per-instance status of the last completed launch
+ *   (count ints, caller order): QF_OK or QF_E_HIP.
  * qf_batch_info: per-instance team sizes (count ints), device state bytes,
  *   persistent grid size; any output may be NULL.
  * qf_batch_set_spin_limit: polls before a team barrier gives up (default 2^28).
@@ -240,6 +292,17 @@ int qf_batch_create(int count, const int *n_qubits, const uint64_t *occ_mask, co
 int qf_batch_run(qf_batch *batch, const double *theta, double *E_out, double *dE_dtheta, int use_graph,
                  void *stream);
 int qf_batch_info(const qf_batch *batch, int *team, int64_t *state_bytes, int *grid);
+int qf_batch_status(const qf_batch *batch, int *status);
+/* Workgroups of the persistent batched kernel resident on the current device
+ * (the grid of a launch with at least that many tickets). */
+int qf_batch_resident_grid(int *grid);
+/*
+ * The team sizes qf_batch_create(_arena) would give (host only, no device):
+ * n_strings[i] is instance i's Hamiltonian string count, team as above,
+ * grid the resident workgroup count, concurrent as in qf_batch_create_arena.
+ */
+int qf_batch_teams(int count, const int *n_qubits, const int64_t *K, const int64_t *n_strings,
+                   const int *team, int grid, int concurrent, int *W_out);
 
 /*
  * Arena batches, for serving loops that must not allocate or free device
@@ -250,7 +313,10 @@ int qf_batch_info(const qf_batch *batch, int *team, int64_t *state_bytes, int *g
  *   caller and not freed by the batch).  *need_bytes receives the size the
  *   batch needs; with arena == NULL nothing else happens (size query, QF_OK);
  *   a smaller arena gives QF_E_SIZE.  Tables are uploaded on `stream` before
- *   the call returns.
+ *   the call returns.  concurrent (>= 1) is the number of persistent batch
+ *   launches that may run on the device at once: every team is capped at
+ *   (resident grid) / concurrent workgroups, which keeps overlapping launches
+ *   free of deadlock (each can always gather its waiting team).
  * qf_batch_launch: queue theta upload and the persistent kernel on `stream`
  *   and return at once.  qf_batch_poll: QF_OK when the launch has finished,
  *   1 while it runs.  qf_batch_collect: wait for it and copy E_out (count)
@@ -259,8 +325,8 @@ int qf_batch_info(const qf_batch *batch, int *team, int64_t *state_bytes, int *g
  */
 int qf_batch_create_arena(int count, const int *n_qubits, const uint64_t *occ_mask, const qf_term *const *A,
                           const int64_t *K, const qf_term *const *H, const int64_t *const *group_off,
-                          const int64_t *n_groups, const int *team, void *arena, int64_t arena_bytes,
-                          int64_t *need_bytes, void *stream, qf_batch **out);
+                          const int64_t *n_groups, const int *team, int concurrent, void *arena,
+                          int64_t arena_bytes, int64_t *need_bytes, void *stream, qf_batch **out);
 int qf_batch_launch(qf_batch *batch, const double *theta, void *stream);
 int qf_batch_poll(qf_batch *batch);
 int qf_batch_collect(qf_batch *batch, double *E_out, double *dE_dtheta);
@@ -274,7 +340,8 @@ int qf_batch_collect(qf_batch *batch, double *E_out, double *dE_dtheta);
  *   double E[count]; double dE_dtheta[K_total]; uint32 flag[count]
  * (qf_batch_mailbox_bytes gives the size); results are written first, then
  * flag[i] = 1 with a system-scope release, so a host that reads flag[i] == 1
- * may read E[i] and the instance's gradient.  The mailbox must stay
+ * may read E[i] and the instance's gradient; flag[i] = 2 marks an instance
+ * whose team barrier timed out (no valid result).  The mailbox must stay
  * untouched until the launch has finished (qf_batch_poll / collect).
  */
 int qf_mailbox_alloc(int64_t bytes, void **mailbox);

@@ -30,7 +30,7 @@ TERM_DTYPE = np.dtype([("x", "<u8"), ("z", "<u8"), ("c", "<f8")])
 QF_OK = 0
 STATUS = {0: "QF_OK", -1: "QF_E_ARG", -2: "QF_E_RANGE", -3: "QF_E_NOMEM", -4: "QF_E_HIP",
           -5: "QF_E_SIZE", -6: "QF_E_NOTHERM"}
-QF_HAMILTONIAN, QF_UCCSD, QF_UCCD, QF_UCCD_TOP, QF_PUCCD = 0, 1, 2, 3, 4
+QF_HAMILTONIAN, QF_UCCSD, QF_UCCD, QF_UCCD_TOP, QF_PUCCD, QF_GSD_POOL = 0, 1, 2, 3, 4, 5
 
 EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state", "qf_apply_pauli_exp",
            "qf_energy", "qf_energy_grad", "qf_plan_create", "qf_plan_destroy", "qf_plan_apply",
@@ -38,7 +38,9 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_batch_create", "qf_batch_run", "qf_batch_info", "qf_batch_set_spin_limit", "qf_batch_destroy",
            "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect",
            "qf_mailbox_alloc", "qf_mailbox_free", "qf_batch_mailbox_bytes", "qf_batch_launch_mailbox",
-           "qf_plan_set_energy_tile", "qf_plan_info", "qf_plan_set_block_bits", "qf_plan_apply_info")
+           "qf_plan_set_energy_tile", "qf_plan_info", "qf_plan_set_block_bits", "qf_plan_apply_info",
+           "qf_plan_create_arena", "qf_batch_status", "qf_batch_teams",
+           "qf_batch_resident_grid", "qf_pool_grad", "qf_plan_create_pool", "qf_plan_pool_grad")
 
 
 class QFError(RuntimeError):
@@ -63,6 +65,7 @@ _sig = {
     "qf_energy": [_vp, _int, _vp, _vp, _i64, _vp, _vp],
     "qf_energy_grad": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "qf_plan_create": [_int, _vp, _i64, _vp, _vp, _i64, _vp],
+    "qf_plan_create_arena": [_int, _vp, _i64, _vp, _vp, _i64, _int, _int, _vp, _i64, _vp, _vp, _vp],
     "qf_plan_destroy": [_vp],
     "qf_plan_apply": [_vp, _vp, _vp, _int, _vp],
     "qf_plan_energy": [_vp, _vp, _vp, _vp],
@@ -73,7 +76,13 @@ _sig = {
     "qf_batch_info": [_vp, _vp, _vp, _vp],
     "qf_batch_set_spin_limit": [_vp, ctypes.c_uint32],
     "qf_batch_destroy": [_vp],
-    "qf_batch_create_arena": [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp],
+    "qf_batch_create_arena": [_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp, _i64, _vp, _vp, _vp],
+    "qf_batch_status": [_vp, _vp],
+    "qf_pool_grad": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
+    "qf_plan_create_pool": [_int, _vp, _vp, _i64, _vp],
+    "qf_plan_pool_grad": [_vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp],
+    "qf_batch_resident_grid": [_vp],
+    "qf_batch_teams": [_int, _vp, _vp, _vp, _vp, _int, _int, _vp],
     "qf_batch_launch": [_vp, _vp, _vp],
     "qf_batch_poll": [_vp],
     "qf_batch_collect": [_vp, _vp, _vp],

@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import TERM_DTYPE, check, lib, ptr, stream_handle
 
 KINDS = {"hamiltonian": _lib.QF_HAMILTONIAN, "uccsd": _lib.QF_UCCSD, "uccd": _lib.QF_UCCD,
-         "uccd_top": _lib.QF_UCCD_TOP, "puccd": _lib.QF_PUCCD}
+         "uccd_top": _lib.QF_UCCD_TOP, "puccd": _lib.QF_PUCCD, "gsd_pool": _lib.QF_GSD_POOL}
 
 
 def _f64(a):
@@ -88,6 +88,54 @@ def energy_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarra
     return e.value, g
 
 
+def pool_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarray, group_off: np.ndarray,
+              pool: np.ndarray, pool_off: np.ndarray, workspace=None, stream=None):
+    """qf_pool_grad: (E, g) with g_nu = <Psi|[H, kappa_nu]|Psi> for the pool
+    members (ADAPT-VQE, Sec. 3.2) at Psi = U(theta)|occ_mask>."""
+    import torch
+    theta = _f64(theta)
+    group_off = np.ascontiguousarray(group_off, dtype=np.int64)
+    pool_off = np.ascontiguousarray(pool_off, dtype=np.int64)
+    if workspace is None:
+        workspace = torch.empty(2 << n_qubits, dtype=torch.complex128, device="cuda")
+    e = ctypes.c_double()
+    g = np.zeros(len(pool_off) - 1, dtype=np.float64)
+    check(lib.qf_pool_grad(n_qubits, occ_mask, ptr(A), ptr(theta), 0 if A is None else len(A), ptr(H),
+                           ptr(group_off), len(group_off) - 1, ptr(pool), ptr(pool_off), len(pool_off) - 1,
+                           ptr(workspace), ctypes.byref(e), ptr(g), stream_handle(stream)), "qf_pool_grad")
+    return e.value, g
+
+
+class PoolPlan:
+    """qf_plan_create_pool: device tables of an ADAPT operator pool."""
+
+    def __init__(self, n_qubits: int, pool: np.ndarray, pool_off: np.ndarray):
+        self.n = n_qubits
+        self.pool_off = np.ascontiguousarray(pool_off, dtype=np.int64)
+        self.n_pool = len(self.pool_off) - 1
+        self._pool = pool
+        h = ctypes.c_void_p()
+        check(lib.qf_plan_create_pool(n_qubits, ptr(pool), ptr(self.pool_off), self.n_pool, ctypes.byref(h)),
+              "qf_plan_create_pool")
+        self._h = h
+
+    def apply_info(self) -> dict:
+        bb = ctypes.c_int()
+        r = ctypes.c_int64()
+        ps = ctypes.c_int64()
+        check(lib.qf_plan_apply_info(self._h, ctypes.byref(bb), ctypes.byref(r), ctypes.byref(ps)),
+              "qf_plan_apply_info")
+        return {"block_bits": bb.value, "runs": r.value, "passes": ps.value}
+
+    def close(self, _destroy=lib.qf_plan_destroy):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
 _PLAN_TILES = None
 
 
@@ -108,7 +156,10 @@ class Plan:
     """
 
     def __init__(self, n_qubits: int, A: np.ndarray | None = None, H: np.ndarray | None = None,
-                 group_off: np.ndarray | None = None, tuned: bool = True):
+                 group_off: np.ndarray | None = None, tuned: bool = True, arena=None, stream=None):
+        """arena: (device address, bytes) of a caller buffer that receives the
+        plan's device tables (qf_plan_create_arena; size from arena_bytes());
+        the plan then allocates and frees no device memory."""
         self.n = n_qubits
         self.K = 0 if A is None else len(A)
         self._A = A
@@ -116,6 +167,14 @@ class Plan:
         self._goff = None if group_off is None else np.ascontiguousarray(group_off, dtype=np.int64)
         G = 0 if self._goff is None else len(self._goff) - 1
         h = ctypes.c_void_p()
+        if arena is not None:
+            bb, et = self._tiles(n_qubits, self.K, G, tuned)
+            need = ctypes.c_int64()
+            check(lib.qf_plan_create_arena(n_qubits, ptr(A), self.K, ptr(H), ptr(self._goff), G, bb, et,
+                                           ctypes.c_void_p(int(arena[0])), int(arena[1]), ctypes.byref(need),
+                                           stream_handle(stream), ctypes.byref(h)), "qf_plan_create_arena")
+            self._h = h
+            return
         check(lib.qf_plan_create(n_qubits, ptr(A), self.K, ptr(H), ptr(self._goff), G, ctypes.byref(h)),
               "qf_plan_create")
         self._h = h
@@ -128,6 +187,28 @@ class Plan:
                     self.set_block_bits(int(t["block_bits"]))
                 if G and t.get("energy_tile") and n_qubits > int(t["energy_tile"]):
                     self.set_energy_tile(int(t["energy_tile"]), True)
+
+    @staticmethod
+    def _tiles(n: int, K: int, G: int, tuned: bool):
+        """(block_bits, energy_tile) for an arena plan: the autotuned values
+        for this qubit count when the table matches the device, else -1
+        (library defaults)."""
+        t = _plan_tiles().get(int(n)) if tuned else None
+        bb = int(t["block_bits"]) if (t and K and t.get("block_bits")) else -1
+        et = int(t["energy_tile"]) if (t and G and t.get("energy_tile") and n > int(t["energy_tile"])) else -1
+        return bb, et
+
+    @staticmethod
+    def arena_bytes(n_qubits: int, A=None, H=None, group_off=None, tuned: bool = True) -> int:
+        """Device bytes an arena plan of these tables needs."""
+        K = 0 if A is None else len(A)
+        goff = None if group_off is None else np.ascontiguousarray(group_off, dtype=np.int64)
+        G = 0 if goff is None else len(goff) - 1
+        bb, et = Plan._tiles(n_qubits, K, G, tuned)
+        need = ctypes.c_int64()
+        check(lib.qf_plan_create_arena(n_qubits, ptr(A), K, ptr(H), ptr(goff), G, bb, et, None, 0,
+                                       ctypes.byref(need), None, None), "qf_plan_create_arena(size)")
+        return need.value
 
     def close(self, _destroy=lib.qf_plan_destroy):
         if getattr(self, "_h", None):
@@ -176,6 +257,15 @@ class Plan:
         check(lib.qf_plan_sigma(self._h, ptr(psi), ptr(lam), ctypes.byref(e), stream_handle(stream)),
               "qf_plan_sigma")
         return e.value
+
+    def pool_grad(self, pool: "PoolPlan", occ_mask: int, theta, workspace, stream=None):
+        """qf_plan_pool_grad: (E, g) for the pool members (ADAPT-VQE, Sec. 3.2)."""
+        theta = _f64(theta)
+        e = ctypes.c_double()
+        g = np.zeros(pool.n_pool, dtype=np.float64)
+        check(lib.qf_plan_pool_grad(self._h, pool._h, occ_mask, ptr(theta), ptr(workspace), ctypes.byref(e),
+                                    ptr(g), stream_handle(stream)), "qf_plan_pool_grad")
+        return e.value, g
 
     def energy_grad(self, occ_mask: int, theta, workspace, stream=None):
         theta = _f64(theta)
@@ -234,20 +324,35 @@ class Batch:
         check(lib.qf_batch_info(self._h, team, ctypes.byref(sb), ctypes.byref(grid)), "qf_batch_info")
         return {"team": list(team), "state_bytes": sb.value, "grid": grid.value}
 
+    def status(self) -> list:
+        """Per-instance status of the last completed launch: 0 (QF_OK) or -4
+        (QF_E_HIP: that instance's team barrier timed out)."""
+        st = (ctypes.c_int * self.count)()
+        check(lib.qf_batch_status(self._h, st), "qf_batch_status")
+        return list(st)
+
     def set_spin_limit(self, polls: int):
         check(lib.qf_batch_set_spin_limit(self._h, int(polls)), "qf_batch_set_spin_limit")
 
-    def run(self, thetas, use_graph: bool = True, stream=None):
-        """thetas: list of per-instance angle arrays.  Returns (E[count], [grad_i])."""
+    def run(self, thetas, use_graph: bool = True, stream=None, partial: bool = False):
+        """thetas: list of per-instance angle arrays.  Returns (E[count], [grad_i]).
+        partial: do not raise when only some instances failed (team barrier
+        timeouts); return (E, grads, status) with status as in status()."""
         theta = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in thetas])
                                      if self.count else np.zeros(0), dtype=np.float64)
         if len(theta) != self.koff[-1]:
             raise ValueError("theta lengths do not match the batch's ansatz sizes")
         E = np.zeros(self.count)
         g = np.zeros(max(len(theta), 1))
-        check(lib.qf_batch_run(self._h, ptr(theta), ptr(E), ptr(g), int(use_graph), stream_handle(stream)),
-              "qf_batch_run")
-        return E, [g[self.koff[i]:self.koff[i + 1]].copy() for i in range(self.count)]
+        st = lib.qf_batch_run(self._h, ptr(theta), ptr(E), ptr(g), int(use_graph), stream_handle(stream))
+        grads = [g[self.koff[i]:self.koff[i + 1]].copy() for i in range(self.count)]
+        if partial:
+            status = self.status()
+            if st != _lib.QF_OK and all(v == _lib.QF_OK for v in status):
+                check(st, "qf_batch_run")
+            return E, grads, status
+        check(st, "qf_batch_run")
+        return E, grads
 
     def run_completion(self, thetas, stream=None, poll_s: float = 20e-6):
         """One launch in which the kernel publishes each instance to a host

@@ -12,10 +12,18 @@
 // the state and meets at a team barrier after every pass:
 // W = 1 teams only need the workgroup barrier, so small states stay in the
 // CU's L2; larger teams use an agent-scope counter barrier with a bounded
-// spin (timeout -> error flag, every wave still exits).  The grid never
-// exceeds the resident capacity and W_e never exceeds the grid, and tickets
-// are taken in order, so every team's members are or will become resident:
-// the schedule cannot deadlock.
+// spin (timeout -> the instance's error flag, every wave still exits).  The
+// grid never exceeds the resident capacity R and tickets are taken in order,
+// so within one launch only the team being assembled waits for members, and
+// every earlier team finishes and frees its workgroups for it.  When C
+// persistent launches share the device (overlapping waves of a server),
+// every team is capped at R / C workgroups: launches stuck at once would
+// each hold fewer workgroups than their waiting team, less than R in total,
+// so a free slot remains for one of them; a launch that completes its teams
+// drains and releases its slots.  Either way the schedule cannot deadlock.
+// A barrier that times out fails only its own instance: members stop
+// waiting for each other, the instance's results are not published as
+// valid, and the other instances of the launch complete normally.
 //
 // Reductions: each member sums its slice (wavefront shuffles + LDS), writes
 // one partial per value, and member 0 sums the W partials in member order
@@ -627,10 +635,10 @@ __global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, un
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nentries * kSyncWords; i += gridDim.x * blockDim.x)
         sync[i] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nentries; i += gridDim.x * blockDim.x)
+        err[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         *ticket = 0u;
-        *err = 0u;
-    }
 }
 
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
@@ -686,6 +694,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         const double *th = theta + en.theta0;
         double *gpart = partials + en.part0;     // [W][K] string sums
         double *epart = gpart + (size_t)W * en.K; // [W] energy sums
+        unsigned *ierr = err + ei;  // this instance's error flag
         TeamSync ts;
         ts.ctr = sync + (size_t)ei * kSyncWords;
         if (threadIdx.x == 0)
@@ -698,7 +707,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         // the runs' (cos, sin) tables, once per launch (runs rank, rank + W, ...)
         for (int r = rank; r < en.nruns; r += W)
             run_table(runs[en.run0 + r], th, tabs + en.tabs0);
-        team_sync(W, ts, ++epoch, spin_limit, err);
+        team_sync(W, ts, ++epoch, spin_limit, ierr);
 
         // forward: segments of runs on sub-cubes, members take sub-cubes rank, rank + W, ...
         for (int si = 0; si < en.naseg; si++) {
@@ -722,7 +731,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                         sub_apply<0>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
                 }
             }
-            team_sync(W, ts, ++epoch, spin_limit, err);
+            team_sync(W, ts, ++epoch, spin_limit, ierr);
         }
 
         {
@@ -741,7 +750,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (threadIdx.x == 0)
                 epart[rank] = s_part[0];
         }
-        team_sync(W, ts, ++epoch, spin_limit, err);
+        team_sync(W, ts, ++epoch, spin_limit, ierr);
 
         // reverse sweep: segments last first; each member leaves its string sums in gpart[rank]
         for (int si = en.ndseg - 1; si >= 0; si--) {
@@ -781,7 +790,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
                     gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];
             }
-            team_sync(W, ts, ++epoch, spin_limit, err);
+            team_sync(W, ts, ++epoch, spin_limit, ierr);
         }
         if (rank == 0) {
             for (int k = threadIdx.x; k < en.K; k += kBT) {
@@ -799,14 +808,17 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                     mb_E[en.out] = s;
             }
             if (mb_flag) {
-                // per-instance completion: results to host memory, then the flag
+                // per-instance completion: results to host memory, then the
+                // flag (1: valid; 2: a barrier of this instance timed out)
                 __syncthreads();
                 for (int k = threadIdx.x; k < en.K; k += kBT)
                     mb_grad[en.theta0 + k] = grad_out[en.theta0 + k];
                 __threadfence_system();
                 __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_store(&mb_flag[en.out], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (threadIdx.x == 0) {
+                    const unsigned bad = __hip_atomic_load(ierr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&mb_flag[en.out], bad ? 2u : 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
             }
         }
         __syncthreads();
@@ -826,6 +838,8 @@ struct qf_batch {
     int64_t K_total = 0;
     std::vector<int64_t> koff;  // caller-order offsets into theta / grad
     std::vector<int> W;         // per caller instance
+    std::vector<int> status;    // per caller instance, from the last collected launch
+    std::vector<int> entry_out; // caller index of each entry (launch order)
     std::vector<int> nq;
     size_t state_bytes = 0;
     size_t device_bytes = 0;
@@ -918,10 +932,45 @@ struct BatchHost {
     int64_t tickets = 0, parts = 0, tabs = 0;
 };
 
+// Team sizes W[i] on a resident grid of `grid` workgroups shared by up to
+// `concurrent` persistent launches: team[i] > 0 asks for that many, 0 (or
+// team == NULL) for the built-in table; team[i] < 0 shares the grid by
+// work, 2^n (K + Hamiltonian strings), among the instances that ask for it,
+// with at least -team[i] members and at most one forward sub-cube (2^12
+// amplitudes) per member.  Every team is then clamped to one reverse-sweep
+// sub-cube (2^11 amplitudes) per member and to grid / concurrent.
+void team_sizes(int count, const int *n_qubits, const int64_t *K, const int64_t *strings, const int *team,
+                unsigned grid, int concurrent, int *W)
+{
+    for (int i = 0; i < count; i++)
+        W[i] = (team && team[i] > 0) ? team[i] : default_team(n_qubits[i]);
+    if (team) {
+        double total = 0.0;
+        for (int i = 0; i < count; i++)
+            if (team[i] < 0)
+                total += std::ldexp((double)(K[i] + strings[i]), n_qubits[i]);
+        for (int i = 0; i < count; i++)
+            if (team[i] < 0) {
+                // a shared team takes at most one forward sub-cube per member:
+                // more members mostly add barrier traffic
+                const double w = std::ldexp((double)(K[i] + strings[i]), n_qubits[i]);
+                const double cap = std::ldexp(1.0, std::max(0, n_qubits[i] - 12));
+                const int share = (int)std::min<double>({(double)grid, cap, std::floor((double)grid * w / total)});
+                W[i] = std::max(-team[i], share);
+            }
+    }
+    const int64_t per_launch = std::max<int64_t>(1, (int64_t)grid / std::max(1, concurrent));
+    for (int i = 0; i < count; i++) {
+        const int n = n_qubits[i];
+        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / 1024);
+        W[i] = (int)std::min<int64_t>({(int64_t)W[i], tiles, per_launch});
+    }
+}
+
 // Validate the instances, pick team sizes and assemble the host tables.
 void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, const uint64_t *occ_mask,
                     const qf_term *const *A, const int64_t *K, const qf_term *const *H,
-                    const int64_t *const *group_off, const int64_t *n_groups, const int *team)
+                    const int64_t *const *group_off, const int64_t *n_groups, const int *team, int concurrent = 1)
 {
     if (count < 1 || !n_qubits || !occ_mask || !K || !A || !H || !group_off || !n_groups)
         raise(QF_E_ARG, "qf_batch_create: null array or count < 1");
@@ -939,37 +988,15 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
             raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad ansatz or Hamiltonian");
         B.koff[(size_t)i + 1] = B.koff[(size_t)i] + K[i];
         B.nq[(size_t)i] = n;
-        B.W[(size_t)i] = (team && team[i] > 0) ? team[i] : default_team(n);
-        if (team && team[i] < 0 && group_off[i] && n_groups[i] >= 1 && group_off[i][n_groups[i]] < 0)
+        if (group_off[i][n_groups[i]] < 0)
             raise(QF_E_ARG, "instance " + std::to_string(i) + ": bad group offsets");
     }
     B.K_total = B.koff[(size_t)count];
     B.grid = resident_grid();
-    // team[i] < 0: share the grid by work, 2^n (K + Hamiltonian strings),
-    // among the instances that ask for it, with at least -team[i] members
-    if (team) {
-        double total = 0.0;
-        for (int i = 0; i < count; i++)
-            if (team[i] < 0)
-                total += std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
-        for (int i = 0; i < count; i++)
-            if (team[i] < 0) {
-                // a shared team takes at most one forward sub-cube per member:
-                // more members mostly add barrier traffic
-                const double w = std::ldexp((double)(K[i] + group_off[i][n_groups[i]]), n_qubits[i]);
-                const double cap = std::ldexp(1.0, std::max(0, n_qubits[i] - 12));
-                const int share =
-                    (int)std::min<double>({(double)B.grid, cap, std::floor((double)B.grid * w / total)});
-                B.W[(size_t)i] = std::max(-team[i], share);
-            }
-    }
-    for (int i = 0; i < count; i++) {
-        // a team never exceeds one 1024-pair tile (one reverse-sweep 2^11
-        // sub-cube) per member, or the grid
-        const int n = n_qubits[i];
-        const int64_t tiles = std::max<int64_t>(1, (int64_t)(1ull << (n - 1)) / 1024);
-        B.W[(size_t)i] = (int)std::min<int64_t>({(int64_t)B.W[(size_t)i], tiles, (int64_t)B.grid});
-    }
+    std::vector<int64_t> strings((size_t)count);
+    for (int i = 0; i < count; i++)
+        strings[(size_t)i] = group_off[i][n_groups[i]];
+    team_sizes(count, n_qubits, K, strings.data(), team, B.grid, concurrent, B.W.data());
     std::vector<int> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.nq[a] > B.nq[b]; });
@@ -1043,6 +1070,10 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
             raise(QF_E_ARG, "batch too large");
     }
     B.nentries = (int)T.ent.size();
+    B.entry_out.clear();
+    for (const BatchEntry &e : T.ent)
+        B.entry_out.push_back(e.out);
+    B.status.assign((size_t)count, QF_OK);
     B.total_tickets = (unsigned)T.tickets;
     B.grid = std::min<unsigned>(B.grid, B.total_tickets);
     B.state_bytes = T.state_amps * sizeof(double2);
@@ -1060,7 +1091,8 @@ Layout batch_layout(const qf_batch &B, const BatchHost &T)
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
-        (size_t)T.parts * sizeof(double), T.ent.size() * kSyncWords * sizeof(unsigned), sizeof(unsigned), sizeof(unsigned),
+        (size_t)T.parts * sizeof(double), T.ent.size() * kSyncWords * sizeof(unsigned), sizeof(unsigned),
+        T.ent.size() * sizeof(unsigned),
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
         std::max<size_t>(T.cls.size(), 1) * sizeof(ClassDesc), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2)};
@@ -1146,12 +1178,22 @@ void batch_enqueue(qf_batch &B, hipStream_t s)
                           hipMemcpyDeviceToHost, s));
 }
 
+// Per-instance status of the last launch (caller order); QF_E_HIP if any
+// instance's team barrier timed out.
 int check_err(qf_batch &B)
 {
-    unsigned err = 0;
-    QF_HIP(hipMemcpy(&err, B.d_err, sizeof err, hipMemcpyDeviceToHost));
-    if (err)
-        return fail(QF_E_HIP, "qf_batch: a team barrier timed out (spin limit %u polls)", B.spin_limit);
+    std::vector<unsigned> err((size_t)B.nentries, 0u);
+    QF_HIP(hipMemcpy(err.data(), B.d_err, err.size() * sizeof(unsigned), hipMemcpyDeviceToHost));
+    B.status.assign((size_t)B.count, QF_OK);
+    int bad = 0;
+    for (int e = 0; e < B.nentries; e++)
+        if (err[(size_t)e]) {
+            B.status[(size_t)B.entry_out[(size_t)e]] = QF_E_HIP;
+            bad++;
+        }
+    if (bad)
+        return fail(QF_E_HIP, "qf_batch: %d of %d instances failed, a team barrier timed out (spin limit %u polls)",
+                    bad, B.count, B.spin_limit);
     return QF_OK;
 }
 
@@ -1195,16 +1237,18 @@ extern "C" int qf_batch_create(int count, const int *n_qubits, const uint64_t *o
 extern "C" int qf_batch_create_arena(int count, const int *n_qubits, const uint64_t *occ_mask,
                                      const qf_term *const *A, const int64_t *K, const qf_term *const *H,
                                      const int64_t *const *group_off, const int64_t *n_groups, const int *team,
-                                     void *arena, int64_t arena_bytes, int64_t *need_bytes, void *stream,
-                                     qf_batch **out)
+                                     int concurrent, void *arena, int64_t arena_bytes, int64_t *need_bytes,
+                                     void *stream, qf_batch **out)
 {
     return guarded([&]() -> int {
         if (out)
             *out = nullptr;
+        if (concurrent < 1)
+            return fail(QF_E_ARG, "qf_batch_create_arena: concurrent < 1");
         qf_batch *B = new qf_batch();
         try {
             BatchHost T;
-            batch_assemble(*B, T, count, n_qubits, occ_mask, A, K, H, group_off, n_groups, team);
+            batch_assemble(*B, T, count, n_qubits, occ_mask, A, K, H, group_off, n_groups, team, concurrent);
             const Layout L = batch_layout(*B, T);
             if (need_bytes)
                 *need_bytes = (int64_t)L.total;
@@ -1231,6 +1275,39 @@ extern "C" int qf_batch_create_arena(int count, const int *n_qubits, const uint6
         *out = B;
         return QF_OK;
     });
+}
+
+extern "C" int qf_batch_teams(int count, const int *n_qubits, const int64_t *K, const int64_t *n_strings,
+                              const int *team, int grid, int concurrent, int *W_out)
+{
+    return guarded([&]() -> int {
+        if (count < 1 || !n_qubits || !K || !n_strings || !W_out || grid < 1 || concurrent < 1)
+            return fail(QF_E_ARG, "qf_batch_teams: bad arguments");
+        for (int i = 0; i < count; i++)
+            if (n_qubits[i] < 1 || n_qubits[i] > 30 || K[i] < 0 || n_strings[i] < 0)
+                return fail(QF_E_RANGE, "qf_batch_teams: instance %d out of range", i);
+        team_sizes(count, n_qubits, K, n_strings, team, (unsigned)grid, concurrent, W_out);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_batch_resident_grid(int *grid)
+{
+    return guarded([&]() -> int {
+        if (!grid)
+            return fail(QF_E_ARG, "qf_batch_resident_grid: grid is NULL");
+        *grid = (int)resident_grid();
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_batch_status(const qf_batch *b, int *status)
+{
+    if (!b || !status)
+        return fail(QF_E_ARG, "qf_batch_status: null argument");
+    for (int i = 0; i < b->count; i++)
+        status[i] = b->status[(size_t)i];
+    return QF_OK;
 }
 
 extern "C" int qf_batch_destroy(qf_batch *b)
@@ -1354,13 +1431,10 @@ extern "C" int qf_batch_collect(qf_batch *B, double *E_out, double *dE_dtheta)
             return fail(QF_E_ARG, "qf_batch_collect: nothing launched or E_out is NULL");
         QF_HIP(hipEventSynchronize(B->done));
         B->launched = false;
-        const int st = check_err(*B);
-        if (st != QF_OK)
-            return st;
         QF_HIP(hipMemcpy(E_out, B->d_E, (size_t)B->count * sizeof(double), hipMemcpyDeviceToHost));
         if (dE_dtheta && B->K_total > 0)
             QF_HIP(hipMemcpy(dE_dtheta, B->d_grad, (size_t)B->K_total * sizeof(double), hipMemcpyDeviceToHost));
-        return QF_OK;
+        return check_err(*B);
     });
 }
 
@@ -1410,12 +1484,9 @@ extern "C" int qf_batch_run(qf_batch *B, const double *theta, double *E_out, dou
             batch_enqueue(*B, s);
         }
         QF_HIP(hipStreamSynchronize(s));
-        const int st = check_err(*B);
-        if (st != QF_OK)
-            return st;
         std::memcpy(E_out, B->h_E, (size_t)B->count * sizeof(double));
         if (dE_dtheta && B->K_total > 0)
             std::memcpy(dE_dtheta, B->h_grad, (size_t)B->K_total * sizeof(double));
-        return QF_OK;
+        return check_err(*B);
     });
 }

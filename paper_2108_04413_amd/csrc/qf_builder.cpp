@@ -208,12 +208,40 @@ void emit_kappa(const Excitation &e, std::vector<qf_term> &out)
     }
 }
 
+// Generalized singles and doubles of an ADAPT pool (Sec. 3.2): every
+// S_z-conserving tau = a+_p a_q (p > q) and tau = a+_p a+_q a_s a_r with
+// p < q, r < s and (p, q) after (r, s), regardless of occupation; singles
+// first, ordered by (q, p), then doubles by ((r, s), (p, q)).
+std::vector<Excitation> generalized_pool(int nq)
+{
+    std::vector<Excitation> ex;
+    for (int q = 0; q < nq; q++)
+        for (int p = q + 1; p < nq; p++)
+            if (((p ^ q) & 1) == 0)
+                ex.push_back({0, 1, {p, -1}, {q, -1}});
+    for (int r = 0; r < nq; r++)
+        for (int s = r + 1; s < nq; s++)
+            for (int p = r; p < nq; p++)
+                for (int q = p + 1; q < nq; q++) {
+                    if (p == r && q <= s)
+                        continue;
+                    if ((p & 1) + (q & 1) != (r & 1) + (s & 1))
+                        continue;
+                    ex.push_back({0, 2, {p, q}, {s, r}});
+                }
+    return ex;
+}
+
 void build_ansatz(int kind, int n_orb, int ne, const double *t_rank, int64_t top_k, Built &out)
 {
     const int nq = 2 * n_orb;
     std::vector<Excitation> ex;
     std::vector<int64_t> idx;
-    if (kind == QF_PUCCD) {
+    if (kind == QF_GSD_POOL) {
+        ex = generalized_pool(nq);
+        for (size_t m = 0; m < ex.size(); m++)
+            idx.push_back((int64_t)m);
+    } else if (kind == QF_PUCCD) {
         const int nocc = ne / 2, nvir = (nq - ne) / 2;
         for (int i = 0; i < nocc; i++)
             for (int a = 0; a < nvir; a++) {
@@ -263,7 +291,7 @@ extern "C" int qf_build_paulis(int kind, int n_orb, int n_elec, const double *h,
                                int64_t *off, int64_t off_cap, int64_t *n_off, int64_t *kept)
 {
     return guarded([&]() -> int {
-        if (kind < QF_HAMILTONIAN || kind > QF_PUCCD)
+        if (kind < QF_HAMILTONIAN || kind > QF_GSD_POOL)
             return fail(QF_E_ARG, "qf_build_paulis: unknown kind %d", kind);
         if (n_orb < 1 || 2 * n_orb > 64)
             return fail(QF_E_RANGE, "qf_build_paulis: n_orb=%d out of range [1, 32]", n_orb);

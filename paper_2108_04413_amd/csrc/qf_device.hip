@@ -36,7 +36,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "qf_common.h"
@@ -109,6 +111,12 @@ __global__ __launch_bounds__(kBlock) void k_prepare(double2 *__restrict__ psi, u
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t y = (uint64_t)blockIdx.x * kBlock + threadIdx.x; y < dim; y += stride)
         psi[y] = make_double2(y == occ ? 1.0 : 0.0, 0.0);
+}
+
+__global__ __launch_bounds__(64) void k_zero_u32(unsigned *__restrict__ p, unsigned count)
+{
+    for (unsigned i = threadIdx.x; i < count; i += blockDim.x)
+        p[i] = 0u;
 }
 
 // One block per run; Theta(u) = sum_k s_k (-1)^popcount(u & e_k) theta_k.
@@ -914,7 +922,8 @@ constexpr int adj_threads(int B) { return B >= 10 ? 512 : (1 << B) / 2 >= 256 ? 
 // selects Im.  dq31 is the sign of q relative to the rotation's signs.  The
 // items' q go to accumulate(u_0, du, q) together (du[k] = u_0 ^ u_k, the
 // same for every thread).
-template <bool SW, uint32_t NB, int NT, class Acc>
+// UNDO = false only accumulates (the pool-gradient sweep: nothing is undone).
+template <bool SW, uint32_t NB, int NT, bool UNDO, class Acc>
 __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const double2 *tb, const LocalRun &d,
                                               uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31,
                                               uint32_t dq31, Acc &&accumulate)
@@ -937,19 +946,24 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
         const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
         const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
         const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
-        const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
-        rot_pair<SW>(cs.x, s1, s2, a, b);
-        rot_pair<SW>(cs.x, s1, s2, la, lb);
-        sp[y1] = a;
-        sp[y2] = b;
-        sl[y1] = la;
-        sl[y2] = lb;
+        if constexpr (UNDO) {
+            const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+            rot_pair<SW>(cs.x, s1, s2, a, b);
+            rot_pair<SW>(cs.x, s1, s2, la, lb);
+            sp[y1] = a;
+            sp[y2] = b;
+            sl[y1] = la;
+            sl[y2] = lb;
+        }
         qs[k] = q;
     }
     accumulate(ut ^ i0, du, qs);
 }
 
-template <int B, int NT>
+// UNDO = false: the same string sums 2 Im <lambda|P_k|phi> with phi and
+// lambda left as they are (read-only sub-cubes, no write-back): the ADAPT
+// pool gradients of Sec. 3.2 on a fixed state.
+template <int B, int NT, bool UNDO = true>
 __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
                                                       Segment sg, const LocalRun *__restrict__ lruns,
                                                       const double2 *__restrict__ tab, int sk0, int nstr,
@@ -977,8 +991,9 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 o |= ((tid >> q) & 1u) << sg.hi[q];
         hoff[tid] = o;
     }
-    for (int t = (int)tid; t < sg.ntab; t += NT)
-        stab[t] = tab[sg.tab0 + t];
+    if constexpr (UNDO)
+        for (int t = (int)tid; t < sg.ntab; t += NT)
+            stab[t] = tab[sg.tab0 + t];
     for (int t = (int)tid; t < nstr; t += NT)
         lacc[t] = 0.0;
     const uint32_t nsub = 1u << (n - B);
@@ -1032,9 +1047,9 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 const uint32_t px31 = par(d.x & d.z0) << 31;
                 const uint32_t dq31 = ((d.a0 >> 1) ^ (m >> 1)) << 31;
                 if (m & 1u)
-                    adjoint_pairs<true, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
+                    adjoint_pairs<true, NB, NT, UNDO>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
                 else
-                    adjoint_pairs<false, NB, NT>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
+                    adjoint_pairs<false, NB, NT, UNDO>(sp, sl, tb, d, yt, ut, pt31, px31, dq31, accumulate);
             } else {
                 const uint32_t ut = (pbz & 63u) ^ gf2_coords(tid, d.b, d.r);
                 const uint32_t i0 = item_part(item_table(d), 0);
@@ -1049,8 +1064,10 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                     const double c = cs.x, s = cs.y;
                     const double2 a = sp[y], la = sl[y];
                     qs[kk] = la.x * a.y - la.y * a.x;
-                    sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
-                    sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+                    if constexpr (UNDO) {
+                        sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
+                        sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
+                    }
                 }
                 accumulate(ut ^ i0, du, qs);
             }
@@ -1080,12 +1097,14 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             }
         }
         __syncthreads();
+        if constexpr (UNDO) {
 #pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const uint32_t l = tid + (uint32_t)i * NT;
-            const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
-            phi[y] = sp[l];
-            lam[y] = sl[l];
+            for (int i = 0; i < PER; i++) {
+                const uint32_t l = tid + (uint32_t)i * NT;
+                const uint32_t y = base | (l & lomask) | hoff[l >> sg.q0];
+                phi[y] = sp[l];
+                lam[y] = sl[l];
+            }
         }
     }
     // this workgroup's sums; k_grad_reduce adds the workgroups after the
@@ -1432,12 +1451,65 @@ struct qf_plan {
     unsigned *d_counter = nullptr;
     double *d_result = nullptr;
 
+    bool sigma_tables = true;             // build the sigma classes (not needed for energy only)
+
+    // ADAPT pool plans (qf_plan_create_pool): the pool's strings are the
+    // plan's "ansatz", members sorted by flip mask so that the blocked sweep
+    // packs them into few segments; member i of the sorted order is caller
+    // member pool_perm[i], its strings pool_off[i] .. pool_off[i + 1].
+    bool is_pool = false;
+    std::vector<int64_t> pool_off, pool_perm;
+    std::vector<double> pool_c;
+
+    // Where the device arrays live.  kOwned: one hipMalloc per array, freed
+    // with the plan.  kRegion: bump-allocated (256-byte aligned) from a
+    // caller's region (an arena), never
+    // freed; uploads go through region_stream.  kMeasure: nothing touches
+    // the device; region_used ends as the bytes a kRegion plan would need.
+    enum Mem { kOwned, kRegion, kMeasure } mem = kOwned;
+    char *region = nullptr;
+    size_t region_cap = 0, region_used = 0;
+    hipStream_t region_stream = nullptr;
+
+    template <class T> T *dalloc(size_t count)
+    {
+        if (mem == kOwned)
+            return qf::dev_alloc<T>(count);
+        const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+        if (mem == kRegion && region_used + bytes > region_cap)
+            qf::raise(QF_E_SIZE, "plan tables need more than the " + std::to_string(region_cap) +
+                                     " bytes of the caller's region");
+        // (a measuring plan hands out distinct non-null addresses that are never dereferenced)
+        T *p = reinterpret_cast<T *>((mem == kRegion ? region : reinterpret_cast<char *>(256)) + region_used);
+        region_used += bytes;
+        return p;
+    }
+    void upload(void *dst, const void *src, size_t bytes)
+    {
+        if (mem == kMeasure || bytes == 0)
+            return;
+        if (mem == kOwned) {
+            QF_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+            return;
+        }
+        // the host source is a temporary: wait for the copy before it goes
+        QF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, region_stream));
+        QF_HIP(hipStreamSynchronize(region_stream));
+    }
+    void release(void *p)
+    {
+        if (mem == kOwned && p)
+            QF_HIP(hipFree(p));
+    }
+
     ~qf_plan()
     {
         if (theta_done)
             (void)hipEventDestroy(theta_done);
         if (h_theta)
             (void)hipHostFree(h_theta);
+        if (mem != kOwned)
+            return;
         void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_sclasses, d_sgroups};
         for (void *p : bufs)
@@ -1486,8 +1558,8 @@ void build_pieces(qf_plan &P, const std::vector<ClassDesc> &cls, const std::vect
         stride++;
     for (uint32_t i = 0; i < nv; i++)
         placed[(uint64_t)i * stride % nv] = pieces[rank[i]];
-    P.d_vcls = dev_alloc<VClass>(nv);
-    QF_HIP(hipMemcpy(P.d_vcls, placed.data(), nv * sizeof(VClass), hipMemcpyHostToDevice));
+    P.d_vcls = P.dalloc<VClass>(nv);
+    P.upload(P.d_vcls, placed.data(), nv * sizeof(VClass));
     P.n_vcls = nv;
     P.per_vcls = per;
 }
@@ -1501,8 +1573,7 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
                               std::to_string(L));
     void *old[] = {P.d_classes, P.d_work_off, P.d_tgroups, P.d_recs, P.d_vcls};
     for (void *p : old)
-        if (p)
-            QF_HIP(hipFree(p));
+        P.release(p);
     P.d_classes = nullptr;
     P.d_work_off = nullptr;
     P.d_tgroups = nullptr;
@@ -1567,17 +1638,17 @@ void set_energy_tile(qf_plan &P, int L, bool merged)
             ng.k1 = (int32_t)recs.size();
             g = ng;
         }
-        P.d_recs = dev_alloc<ERec>(recs.size());
-        QF_HIP(hipMemcpy(P.d_recs, recs.data(), recs.size() * sizeof(ERec), hipMemcpyHostToDevice));
+        P.d_recs = P.dalloc<ERec>(recs.size());
+        P.upload(P.d_recs, recs.data(), recs.size() * sizeof(ERec));
         if (L == 11)
             build_pieces(P, cls, tg);
     }
-    P.d_classes = dev_alloc<ClassDesc>(cls.size());
-    P.d_work_off = dev_alloc<uint64_t>(woff.size());
-    P.d_tgroups = dev_alloc<GroupDesc>(tg.size());
-    QF_HIP(hipMemcpy(P.d_classes, cls.data(), cls.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
-    QF_HIP(hipMemcpy(P.d_work_off, woff.data(), woff.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    QF_HIP(hipMemcpy(P.d_tgroups, tg.data(), tg.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+    P.d_classes = P.dalloc<ClassDesc>(cls.size());
+    P.d_work_off = P.dalloc<uint64_t>(woff.size());
+    P.d_tgroups = P.dalloc<GroupDesc>(tg.size());
+    P.upload(P.d_classes, cls.data(), cls.size() * sizeof(ClassDesc));
+    P.upload(P.d_work_off, woff.data(), woff.size() * sizeof(uint64_t));
+    P.upload(P.d_tgroups, tg.data(), tg.size() * sizeof(GroupDesc));
     P.tiled_classes = (int64_t)cls.size();
     P.tiled_work = woff.back();
 }
@@ -1602,8 +1673,7 @@ void set_block_bits(qf_plan &P, int B)
         raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
     void *old[] = {P.d_lruns, P.d_alruns, P.d_apart, P.d_ablocked};
     for (void *p : old)
-        if (p)
-            QF_HIP(hipFree(p));
+        P.release(p);
     P.d_lruns = nullptr;
     P.d_alruns = nullptr;
     P.d_apart = nullptr;
@@ -1620,9 +1690,9 @@ void set_block_bits(qf_plan &P, int B)
         return;
     std::vector<LocalRun> lr;
     build_segments(P.runs, P.n, B, std::min(6, B), P.segs, lr);
-    P.d_lruns = dev_alloc<LocalRun>(lr.size());
+    P.d_lruns = P.dalloc<LocalRun>(lr.size());
     if (!lr.empty())
-        QF_HIP(hipMemcpy(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun), hipMemcpyHostToDevice));
+        P.upload(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun));
     if (P.adj_bits) {
         build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr);
         for (const Segment &sg : P.asegs) {
@@ -1630,22 +1700,26 @@ void set_block_bits(qf_plan &P, int B)
             P.aseg_k0.push_back(k0);
             P.aseg_nstr.push_back(sg.Q ? lr[(size_t)sg.r1 - 1].k0 + lr[(size_t)sg.r1 - 1].m - k0 : 0);
         }
-        P.d_alruns = dev_alloc<LocalRun>(lr.size());
+        P.d_alruns = P.dalloc<LocalRun>(lr.size());
         if (!lr.empty())
-            QF_HIP(hipMemcpy(P.d_alruns, lr.data(), lr.size() * sizeof(LocalRun), hipMemcpyHostToDevice));
+            P.upload(P.d_alruns, lr.data(), lr.size() * sizeof(LocalRun));
         std::vector<uint8_t> blocked((size_t)P.K, 0);
         for (size_t i = 0; i < P.asegs.size(); i++)
             for (int t = 0; t < P.aseg_nstr[i]; t++)
                 blocked[(size_t)(P.aseg_k0[i] + t)] = 1;
-        P.d_ablocked = dev_alloc<uint8_t>((size_t)P.K);
-        QF_HIP(hipMemcpy(P.d_ablocked, blocked.data(), blocked.size(), hipMemcpyHostToDevice));
+        P.d_ablocked = P.dalloc<uint8_t>((size_t)P.K);
+        P.upload(P.d_ablocked, blocked.data(), blocked.size());
         P.adj_grid = P.adj_bits == 10 ? adj_grid<10>(P.n) : adj_grid<11>(P.n);
-        P.d_apart = dev_alloc<double>((size_t)P.adj_grid * (size_t)P.K);
+        P.d_apart = P.dalloc<double>((size_t)P.adj_grid * (size_t)P.K);
     }
 }
 
+// Plan tables on the device.  block_bits / energy_tile < 0 take the
+// defaults (blocked apply over min(12, n) qubits from 6 qubits up; merged
+// energy tiles of 2^11 from 16 qubits up); otherwise as qf_plan_set_block_bits
+// and qf_plan_set_energy_tile (merged) would set them.
 void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H, const int64_t *goff,
-               int64_t G)
+               int64_t G, int block_bits = -1, int energy_tile = -1)
 {
     if (n < 1 || n > QF_MAX_QUBITS)
         raise(QF_E_RANGE, "n_qubits=" + std::to_string(n) + " out of range [1, 32]");
@@ -1660,14 +1734,18 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
     if (K > 0) {
         check_terms("ansatz", n, A, K);
         P.runs = make_runs(A, K, P.tab_entries);
-        P.d_runs = dev_alloc<RunDesc>(P.runs.size());
-        P.d_theta = dev_alloc<double>((size_t)K);
-        P.d_tab = dev_alloc<double2>((size_t)P.tab_entries);
-        P.d_grad = dev_alloc<double>((size_t)K);
-        QF_HIP(hipMemcpy(P.d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice));
-        set_block_bits(P, n >= 6 ? std::min(n, 12) : 0);
-        QF_HIP(hipHostMalloc((void **)&P.h_theta, (size_t)K * sizeof(double), hipHostMallocDefault));
-        QF_HIP(hipEventCreateWithFlags(&P.theta_done, hipEventDisableTiming));
+        P.d_runs = P.dalloc<RunDesc>(P.runs.size());
+        P.d_theta = P.dalloc<double>((size_t)K);
+        P.d_tab = P.dalloc<double2>((size_t)P.tab_entries);
+        P.d_grad = P.dalloc<double>((size_t)K);
+        P.upload(P.d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
+        set_block_bits(P, block_bits >= 0 ? block_bits : n >= 6 ? std::min(n, 12) : 0);
+        // pinned staging for theta (an arena plan stages nothing: freeing
+        // pinned memory may wait for the device, which a serving loop avoids)
+        if (P.mem == qf_plan::kOwned) {
+            QF_HIP(hipHostMalloc((void **)&P.h_theta, (size_t)K * sizeof(double), hipHostMallocDefault));
+            QF_HIP(hipEventCreateWithFlags(&P.theta_done, hipEventDisableTiming));
+        }
     }
     if (G > 0) {
         std::vector<GroupDesc> gd;
@@ -1676,34 +1754,40 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         build_groups(n, H, goff, G, gd, zs, cs);
         const int64_t KH = goff[G];
         P.G = (int)G;
-        P.d_groups = dev_alloc<GroupDesc>((size_t)G);
-        P.d_z = dev_alloc<uint32_t>((size_t)KH);
-        P.d_c = dev_alloc<double>((size_t)KH);
-        QF_HIP(hipMemcpy(P.d_groups, gd.data(), gd.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
-        QF_HIP(hipMemcpy(P.d_z, zs.data(), zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-        QF_HIP(hipMemcpy(P.d_c, cs.data(), cs.size() * sizeof(double), hipMemcpyHostToDevice));
+        P.d_groups = P.dalloc<GroupDesc>((size_t)G);
+        P.d_z = P.dalloc<uint32_t>((size_t)KH);
+        P.d_c = P.dalloc<double>((size_t)KH);
+        P.upload(P.d_groups, gd.data(), gd.size() * sizeof(GroupDesc));
+        P.upload(P.d_z, zs.data(), zs.size() * sizeof(uint32_t));
+        P.upload(P.d_c, cs.data(), cs.size() * sizeof(double));
         P.groups = gd;
         P.hz = zs;
         P.hc = cs;
-        if (n > kSigL) {
+        if (n > kSigL && P.sigma_tables) {
             std::vector<GroupDesc> sg(gd);
             std::vector<ClassDesc> sc;
             sigma_classes(sg, sc);
-            P.d_sclasses = dev_alloc<ClassDesc>(sc.size());
-            P.d_sgroups = dev_alloc<GroupDesc>(sg.size());
-            QF_HIP(hipMemcpy(P.d_sclasses, sc.data(), sc.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
-            QF_HIP(hipMemcpy(P.d_sgroups, sg.data(), sg.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+            P.d_sclasses = P.dalloc<ClassDesc>(sc.size());
+            P.d_sgroups = P.dalloc<GroupDesc>(sg.size());
+            P.upload(P.d_sclasses, sc.data(), sc.size() * sizeof(ClassDesc));
+            P.upload(P.d_sgroups, sg.data(), sg.size() * sizeof(GroupDesc));
             P.n_sclasses = (int)sc.size();
         }
         for (const GroupDesc &g : gd)
             if (g.k1 > g.kre)
                 P.has_imag = true;
-        set_energy_tile(P, n >= 16 ? 11 : 0, true);
+        set_energy_tile(P, energy_tile >= 0 ? energy_tile : n >= 16 ? 11 : 0, true);
     }
-    P.d_partials = dev_alloc<double>((size_t)kMaxBlocks * kMaxRun);
-    P.d_counter = dev_alloc<unsigned>(1);
-    P.d_result = dev_alloc<double>(4);
-    QF_HIP(hipMemset(P.d_counter, 0, sizeof(unsigned)));
+    P.d_partials = P.dalloc<double>((size_t)kMaxBlocks * kMaxRun);
+    P.d_counter = P.dalloc<unsigned>(1);
+    P.d_result = P.dalloc<double>(4);
+    if (P.mem == qf_plan::kOwned) {
+        QF_HIP(hipMemset(P.d_counter, 0, sizeof(unsigned)));
+    } else if (P.mem == qf_plan::kRegion) {
+        // a kernel, not a memset node, so that the clear is also safe to capture
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, P.region_stream, P.d_counter, 1u);
+        QF_HIP(hipGetLastError());
+    }
 }
 
 inline unsigned grid_for(uint64_t work, uint64_t per, unsigned cap)
@@ -1720,10 +1804,16 @@ void upload_theta(qf_plan &P, const double *theta, hipStream_t s)
 {
     if (!theta)
         raise(QF_E_ARG, "theta is NULL");
-    QF_HIP(hipEventSynchronize(P.theta_done));  // previous upload has left the staging buffer
-    std::memcpy(P.h_theta, theta, (size_t)P.K * sizeof(double));
-    QF_HIP(hipMemcpyAsync(P.d_theta, P.h_theta, (size_t)P.K * sizeof(double), hipMemcpyHostToDevice, s));
-    QF_HIP(hipEventRecord(P.theta_done, s));
+    if (P.h_theta) {
+        QF_HIP(hipEventSynchronize(P.theta_done));  // previous upload has left the staging buffer
+        std::memcpy(P.h_theta, theta, (size_t)P.K * sizeof(double));
+        QF_HIP(hipMemcpyAsync(P.d_theta, P.h_theta, (size_t)P.K * sizeof(double), hipMemcpyHostToDevice, s));
+        QF_HIP(hipEventRecord(P.theta_done, s));
+    } else {
+        // from the caller's memory, which may be reused once the copy is done
+        QF_HIP(hipMemcpyAsync(P.d_theta, theta, (size_t)P.K * sizeof(double), hipMemcpyHostToDevice, s));
+        QF_HIP(hipStreamSynchronize(s));
+    }
     hipLaunchKernelGGL(k_run_tables, dim3((unsigned)P.runs.size()), dim3(64), 0, s, P.d_runs, P.d_theta,
                        P.d_tab);
     QF_HIP(hipGetLastError());
@@ -1941,6 +2031,38 @@ void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
     QF_HIP(hipGetLastError());
 }
 
+// String sums 2 Im <lambda|P_k|phi> of every string of a pool plan, with phi
+// and lambda left unchanged: the blocked sweep's segments read-only, runs
+// too wide for a sub-cube through the one-run kernel with identity tables.
+void launch_pool_sweep(qf_plan &Q, double2 *phi, double2 *lam, hipStream_t s)
+{
+    if (Q.adj_bits) {
+        for (size_t i = 0; i < Q.asegs.size(); i++) {
+            const Segment &sg = Q.asegs[i];
+            if (!sg.Q) {
+                launch_adjoint_run(Q, phi, lam, Q.runs[(size_t)sg.r0], s);
+                continue;
+            }
+            const int sk0 = Q.aseg_k0[i], nstr = Q.aseg_nstr[i];
+            if (Q.adj_bits == 10)
+                hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10), false>), dim3(Q.adj_grid),
+                                   dim3(adj_threads(10)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, Q.d_tab, sk0, nstr,
+                                   Q.d_apart, (int)Q.K);
+            else
+                hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11), false>), dim3(Q.adj_grid),
+                                   dim3(adj_threads(11)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, Q.d_tab, sk0, nstr,
+                                   Q.d_apart, (int)Q.K);
+        }
+        hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((Q.K + 63) / 64)), dim3(kBlock), 0, s, Q.d_apart,
+                           (int)Q.adj_grid, (int)Q.K, Q.d_ablocked, Q.d_grad);
+        QF_HIP(hipGetLastError());
+        return;
+    }
+    for (size_t i = 0; i < Q.runs.size(); i++)
+        launch_adjoint_run(Q, phi, lam, Q.runs[i], s);
+    QF_HIP(hipGetLastError());
+}
+
 void fetch(double *host, const double *dev, size_t count, hipStream_t s)
 {
     QF_HIP(hipMemcpyAsync(host, dev, count * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1978,9 +2100,129 @@ void energy_grad_impl(qf_plan &P, uint64_t occ, const double *theta, void *works
     QF_HIP(hipStreamSynchronize(s));
 }
 
+// A pool plan: members sorted by the flip mask of their strings (stable), the
+// strings concatenated in that order as the plan's ansatz, identity (cos,
+// sin) tables for the runs that go through the one-run kernel.
+void pool_init(qf_plan &Q, int n, const qf_term *pool, const int64_t *pool_off, int64_t n_pool)
+{
+    if (n_pool < 1 || !pool || !pool_off)
+        raise(QF_E_ARG, "pool: needs at least one member");
+    if (pool_off[0] != 0)
+        raise(QF_E_ARG, "pool: pool_off[0] must be 0");
+    for (int64_t i = 0; i < n_pool; i++) {
+        if (pool_off[i + 1] <= pool_off[i])
+            raise(QF_E_ARG, "pool: member " + std::to_string(i) + " has no strings");
+        for (int64_t k = pool_off[i] + 1; k < pool_off[i + 1]; k++)
+            if (pool[k].x != pool[pool_off[i]].x)
+                raise(QF_E_ARG, "pool: the strings of member " + std::to_string(i) + " differ in flip mask");
+    }
+    std::vector<int64_t> order((size_t)n_pool);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return pool[pool_off[a]].x < pool[pool_off[b]].x; });
+    std::vector<qf_term> sorted;
+    sorted.reserve((size_t)pool_off[n_pool]);
+    Q.pool_off.assign(1, 0);
+    for (int64_t i : order) {
+        for (int64_t k = pool_off[i]; k < pool_off[i + 1]; k++)
+            sorted.push_back(pool[k]);
+        Q.pool_off.push_back((int64_t)sorted.size());
+    }
+    Q.pool_perm = order;
+    Q.pool_c.resize(sorted.size());
+    for (size_t k = 0; k < sorted.size(); k++)
+        Q.pool_c[k] = sorted[k].c;
+    plan_init(Q, n, sorted.data(), (int64_t)sorted.size(), nullptr, nullptr, 0);
+    Q.is_pool = true;
+    std::vector<double> zero(sorted.size(), 0.0);
+    upload_theta(Q, zero.data(), nullptr);
+    QF_HIP(hipStreamSynchronize(nullptr));
+}
+
+// E and g_nu = -sum_k c_k (2 Im <lambda|P_k|psi>) for Psi = U(theta) Phi.
+void pool_grad_impl(qf_plan &P, qf_plan &Q, uint64_t occ, const double *theta, void *workspace, double *E_out,
+                    double *g_out, hipStream_t s)
+{
+    if (!Q.is_pool)
+        raise(QF_E_ARG, "pool_grad: the second plan is not a pool plan");
+    if (Q.n != P.n)
+        raise(QF_E_ARG, "pool_grad: plan and pool have different qubit counts");
+    if (!workspace || !E_out || !g_out)
+        raise(QF_E_ARG, "pool_grad: null workspace or output");
+    if (P.G == 0)
+        raise(QF_E_ARG, "pool_grad: plan has no Hamiltonian");
+    if (occ >> P.n)
+        raise(QF_E_RANGE, "occ_mask has a bit >= n_qubits");
+    double2 *phi = (double2 *)workspace;
+    double2 *lam = phi + (1ull << P.n);
+    launch_prepare(phi, P.n, occ, s);
+    if (P.K > 0) {
+        upload_theta(P, theta, s);
+        launch_runs(P, phi, false, s);
+    }
+    launch_sigma(P, phi, lam, P.d_result, s);
+    launch_pool_sweep(Q, phi, lam, s);
+    std::vector<double> gk((size_t)Q.K);
+    QF_HIP(hipMemcpyAsync(E_out, P.d_result, sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipMemcpyAsync(gk.data(), Q.d_grad, (size_t)Q.K * sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i + 1 < Q.pool_off.size(); i++) {
+        double v = 0.0;
+        for (int64_t k = Q.pool_off[i]; k < Q.pool_off[i + 1]; k++)
+            v += -Q.pool_c[(size_t)k] * gk[(size_t)k];
+        g_out[Q.pool_perm[i]] = v;
+    }
+}
+
 } // namespace qf
 
 using namespace qf;
+
+extern "C" int qf_plan_create_pool(int n_qubits, const qf_term *pool, const int64_t *pool_off, int64_t n_pool,
+                                   qf_plan **out)
+{
+    return guarded([&]() -> int {
+        if (!out)
+            return fail(QF_E_ARG, "qf_plan_create_pool: out is NULL");
+        *out = nullptr;
+        qf_plan *Q = new qf_plan();
+        try {
+            pool_init(*Q, n_qubits, pool, pool_off, n_pool);
+        } catch (...) {
+            delete Q;
+            throw;
+        }
+        *out = Q;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_pool_grad(qf_plan *plan, qf_plan *pool, uint64_t occ_mask, const double *theta,
+                                 void *workspace, double *E_out, double *g_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!plan || !pool)
+            return fail(QF_E_ARG, "qf_plan_pool_grad: null plan");
+        pool_grad_impl(*plan, *pool, occ_mask, theta, workspace, E_out, g_out, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_pool_grad(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta, int64_t K,
+                            const qf_term *H, const int64_t *group_off, int64_t n_groups, const qf_term *pool,
+                            const int64_t *pool_off, int64_t n_pool, void *workspace, double *E_out,
+                            double *g_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (n_groups < 1)
+            return fail(QF_E_ARG, "qf_pool_grad: needs a Hamiltonian (n_groups >= 1)");
+        qf_plan P, Q;
+        plan_init(P, n_qubits, A, K, H, group_off, n_groups);
+        pool_init(Q, n_qubits, pool, pool_off, n_pool);
+        pool_grad_impl(P, Q, occ_mask, theta, workspace, E_out, g_out, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
 
 extern "C" int qf_plan_create(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
                               const int64_t *group_off, int64_t n_groups, qf_plan **out)
@@ -1992,6 +2234,47 @@ extern "C" int qf_plan_create(int n_qubits, const qf_term *A, int64_t K, const q
         qf_plan *P = new qf_plan();
         try {
             plan_init(*P, n_qubits, A, K, H, group_off, n_groups);
+        } catch (...) {
+            delete P;
+            throw;
+        }
+        *out = P;
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_create_arena(int n_qubits, const qf_term *A, int64_t K, const qf_term *H,
+                                    const int64_t *group_off, int64_t n_groups, int block_bits, int energy_tile,
+                                    void *arena, int64_t arena_bytes, int64_t *need_bytes, void *stream,
+                                    qf_plan **out)
+{
+    return guarded([&]() -> int {
+        if (!need_bytes)
+            return fail(QF_E_ARG, "qf_plan_create_arena: need_bytes is NULL");
+        if (arena && !out)
+            return fail(QF_E_ARG, "qf_plan_create_arena: out is NULL");
+        if (out)
+            *out = nullptr;
+        {
+            qf_plan M;
+            M.mem = qf_plan::kMeasure;
+            plan_init(M, n_qubits, A, K, H, group_off, n_groups, block_bits, energy_tile);
+            *need_bytes = (int64_t)M.region_used;
+        }
+        if (!arena)
+            return QF_OK;
+        if (reinterpret_cast<uintptr_t>(arena) % 256)
+            return fail(QF_E_ARG, "qf_plan_create_arena: arena is not 256-byte aligned");
+        if (arena_bytes < *need_bytes)
+            return fail(QF_E_SIZE, "qf_plan_create_arena: arena of %lld bytes, plan needs %lld",
+                        (long long)arena_bytes, (long long)*need_bytes);
+        qf_plan *P = new qf_plan();
+        P->mem = qf_plan::kRegion;
+        P->region = (char *)arena;
+        P->region_cap = (size_t)arena_bytes;
+        P->region_stream = (hipStream_t)stream;
+        try {
+            plan_init(*P, n_qubits, A, K, H, group_off, n_groups, block_bits, energy_tile);
         } catch (...) {
             delete P;
             throw;
@@ -2142,6 +2425,8 @@ extern "C" int qf_plan_set_energy_tile(qf_plan *P, int tile_bits, int merged)
     return guarded([&]() -> int {
         if (!P)
             return fail(QF_E_ARG, "qf_plan_set_energy_tile: plan is NULL");
+        if (P->mem != qf_plan::kOwned)
+            return fail(QF_E_ARG, "qf_plan_set_energy_tile: an arena plan fixes its tiles at creation");
         set_energy_tile(*P, tile_bits, merged != 0);
         return QF_OK;
     });
@@ -2165,6 +2450,8 @@ extern "C" int qf_plan_set_block_bits(qf_plan *P, int block_bits)
     return guarded([&]() -> int {
         if (!P)
             return fail(QF_E_ARG, "qf_plan_set_block_bits: plan is NULL");
+        if (P->mem != qf_plan::kOwned)
+            return fail(QF_E_ARG, "qf_plan_set_block_bits: an arena plan fixes its tiles at creation");
         set_block_bits(*P, block_bits);
         return QF_OK;
     });

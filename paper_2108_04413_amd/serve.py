@@ -23,32 +23,40 @@ serving (hipFree would synchronize the device).  Scheduling:
   sigma, blocked adjoint, each a full-grid launch) run it faster than a team
   of the persistent kernel, which has to meet at a barrier after every pass.
   Such requests queue FIFO for one solo lane: a host thread that runs the
-  plan path on its own stream with its two states in the arena, while the
-  batched waves of the smaller requests go on beside it.  The plan's own
-  tables (a few MB to ~100 MB) are allocated by the library when the request
-  starts; plans are destroyed when the replay has drained, since hipFree
-  would wait for the whole device.
+  plan path on its own stream while the batched waves of the smaller
+  requests go on beside it.  The plan's tables and the request's two states
+  share one arena range (qf_plan_create_arena), released when the request
+  finishes, so the lane never allocates or frees device memory and its
+  footprint is bounded by one request;
+* co-residency: up to `slots` persistent launches overlap, so every team is
+  capped at (resident grid) / slots workgroups (the library enforces it and
+  the server checks it): overlapping waves can always gather their teams;
+* failures: a request whose team barrier times out (its wave's mailbox flag
+  reads 2) or whose solo-lane call raises is marked failed with its error;
+  the other requests of the wave and of the trace complete normally.
 
-Latency is measured from a request's arrival to the collection of its wave.
-The plain path (`serve_plain`) runs the same trace one request at a time
-with per-request plans and the single-instance kernels.
+Latency is measured from a request's arrival to its completion (mailbox
+flag or solo-lane return).  The plain path (`serve_plain`) runs the same
+trace one request at a time with the single-instance kernels.
 """
 from __future__ import annotations
 
 import ctypes
 import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
 
 from . import api
-from ._lib import check, lib, ptr, stream_handle
+from ._lib import QF_OK, QFError, check, lib, ptr, stream_handle
 
 ALIGN = 256
-# Requests of at least this many qubits take the solo lane.  On MI355X the
-# 200-request mixed trace (12-24 qubits) served 61 req/s with 20, 61 with
-# 22, 59 with 18 and 51 with every request batched.
+QF_E_HIP = -4
+# Requests of at least this many qubits take the solo lane (on MI355X a
+# 24-qubit request takes 235 ms on the plan kernels and 292 ms as a team of
+# the persistent kernel; below 20 qubits the batched waves win).
 SOLO_QUBITS = 20
 
 
@@ -69,6 +77,8 @@ class Request:
     footprint: int = 0
     team: int = 0  # workgroups the request's instance ran with (0: solo lane)
     solo: bool = False  # ran on the solo lane (plan kernels)
+    plan_bytes: int = 0  # solo lane: arena bytes of the plan's tables
+    error: str | None = None  # set when the request failed (t_done is then its failure time)
 
 
 class RangeAllocator:
@@ -114,9 +124,10 @@ class Arena(RangeAllocator):
         self.base = (self.buf.data_ptr() + ALIGN - 1) // ALIGN * ALIGN
 
 
-def _arrays(reqs, team_table, share: bool = False):
+def _arrays(reqs, team_table, share: bool = False, concurrent: int = 1):
     """C arrays of a wave.  share: ask the library to split the resident grid
-    by work (team < 0), with the table's team size as each floor."""
+    by work (team < 0), with the table's team size as each floor;
+    concurrent: persistent launches that may overlap (caps the teams)."""
     c = len(reqs)
     keep = [np.ascontiguousarray(r.off, dtype=np.int64) for r in reqs]
     n = (ctypes.c_int * c)(*[r.n for r in reqs])
@@ -128,7 +139,7 @@ def _arrays(reqs, team_table, share: bool = False):
     G = (ctypes.c_int64 * c)(*[len(o) - 1 for o in keep])
     base = [int(team_table.get(r.n, 0)) if team_table else 0 for r in reqs]
     T = (ctypes.c_int * c)(*[-max(1, w) if share else w for w in base])
-    return (c, n, occ, A, K, H, O, G, T), keep
+    return (c, n, occ, A, K, H, O, G, T, int(concurrent)), keep
 
 
 def default_team_table() -> dict:
@@ -137,11 +148,11 @@ def default_team_table() -> dict:
     return load_table(device_arch()) or {}
 
 
-def footprint(reqs, team_table=None, share: bool = False) -> int:
+def footprint(reqs, team_table=None, share: bool = False, concurrent: int = 1) -> int:
     """Exact arena bytes a wave of these requests needs (with the same team
     policy as the launch).  With share, a request's team in a wave is never
     larger than alone, so footprint([r], ..., share=True) bounds its part."""
-    args, keep = _arrays(reqs, team_table, share)
+    args, keep = _arrays(reqs, team_table, share, concurrent)
     need = ctypes.c_int64()
     check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "qf_batch_create_arena(size)")
     return need.value
@@ -172,9 +183,16 @@ class _Addr:
         return self.addr
 
 
+def _align(v: int) -> int:
+    return (int(v) + ALIGN - 1) // ALIGN * ALIGN
+
+
 def solo_footprint(r) -> int:
-    """Arena bytes of a solo-lane request: its two states (phi, lambda)."""
-    return 2 * (1 << r.n) * 16
+    """Arena bytes of a solo-lane request: its plan's tables, then its two
+    states (phi, lambda)."""
+    if not r.plan_bytes:
+        r.plan_bytes = _align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off))
+    return r.plan_bytes + 2 * (1 << r.n) * 16
 
 
 def _view(addr: int, ctype, count: int) -> np.ndarray:
@@ -183,19 +201,23 @@ def _view(addr: int, ctype, count: int) -> np.ndarray:
 
 class Server:
     def __init__(self, arena_bytes: int, slots: int = 2, max_wave: int = 64, team_table=None,
-                 mailbox_bytes: int = 32 << 20, share: bool = True, solo_qubits: int | None = SOLO_QUBITS):
+                 mailbox_bytes: int = 32 << 20, share: bool = True, solo_qubits: int | None = SOLO_QUBITS,
+                 spin_limit: int | None = None):
+        """spin_limit: polls before a wave's team barrier gives up (None: the
+        library default); a tiny value forces barrier timeouts from the host."""
         import torch
         if team_table is None:
             team_table = default_team_table()
         self.team = team_table
         self.share = share  # split the grid among a wave's requests by work
         self.solo_qubits = solo_qubits  # None: every request goes through batched waves
+        self.spin_limit = spin_limit
         self.arena = Arena(arena_bytes)
         self.solo_stream = torch.cuda.Stream()
         self.solo_job = None      # (thread, request, arena range)
-        self.solo_error = None
-        self.solo_plans = []      # finished plans, destroyed when a replay drains
         self.solo_runs = 0
+        self.solo_live = 0        # solo-lane plans alive now / at most (one request at a time)
+        self.solo_live_max = 0
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.busy = [None] * slots
         self.max_wave = max_wave
@@ -219,7 +241,7 @@ class Server:
             self.close()
 
     def _launch(self, reqs, slot, now):
-        args, keep = _arrays(reqs, self.team, self.share)
+        args, keep = _arrays(reqs, self.team, self.share, len(self.streams))
         need = ctypes.c_int64()
         check(lib.qf_batch_create_arena(*args, None, 0, ctypes.byref(need), None, None), "arena size")
         rng = self.arena.alloc(need.value)
@@ -230,9 +252,18 @@ class Server:
         check(lib.qf_batch_create_arena(*args, ctypes.c_void_p(self.arena.base + rng[0]), rng[1],
                                         ctypes.byref(need), st, ctypes.byref(h)), "qf_batch_create_arena")
         teams = (ctypes.c_int * len(reqs))()
-        check(lib.qf_batch_info(h, teams, None, None), "qf_batch_info")
+        grid = ctypes.c_int()
+        check(lib.qf_batch_info(h, teams, None, ctypes.byref(grid)), "qf_batch_info")
+        # co-residency of overlapping waves: no team above the grid's share
+        # (the grid is already trimmed to the wave's tickets, so compare with
+        # what the library used: resident grid / slots >= any team it made)
+        cap = max(1, self.resident_grid // len(self.streams))
+        if max(teams) > cap:
+            raise RuntimeError(f"team of {max(teams)} workgroups above the co-residency cap {cap}")
         for r, w in zip(reqs, teams):
             r.team = int(w)
+        if self.spin_limit is not None:
+            check(lib.qf_batch_set_spin_limit(h, int(self.spin_limit)), "qf_batch_set_spin_limit")
         theta = np.ascontiguousarray(np.concatenate([r.theta for r in reqs]), dtype=np.float64)
         keep.append(theta)
         mb = self.mailbox[slot].value
@@ -249,35 +280,43 @@ class Server:
                     flag=_view(mb + 8 * c + 8 * kt, ctypes.c_uint32, c), koff=koff, open=c)
 
     def _publish(self, w: Wave, now):
-        """Complete every request of w whose mailbox flag is up."""
+        """Complete every request of w whose mailbox flag is up (1: result,
+        2: its team barrier timed out)."""
         for i, r in enumerate(w.reqs):
-            if r.t_done is None and w.flag[i] == 1:
-                r.E = float(w.E[i])
-                r.grad = w.grad[w.koff[i]:w.koff[i + 1]].copy()
+            if r.t_done is None and w.flag[i] in (1, 2):
+                if w.flag[i] == 1:
+                    r.E = float(w.E[i])
+                    r.grad = w.grad[w.koff[i]:w.koff[i + 1]].copy()
+                else:
+                    r.error = "team barrier timed out"
                 r.t_done = now
                 w.open -= 1
 
     def _solo_run(self, r, addr: int, t0: float):
-        """Solo lane body (host thread): plan, energy + gradient, publish."""
+        """Solo lane body (host thread): arena plan, energy + gradient.  A
+        failure marks this request only."""
         try:
-            plan = api.Plan(r.n, r.A, r.H, r.off)
-            self.solo_plans.append(plan)
-            r.E, r.grad = plan.energy_grad(r.occ, r.theta, _Addr(addr), self.solo_stream)
-            r.t_done = time.perf_counter() - t0
-        except BaseException as e:  # reported by the serving loop
-            self.solo_error = e
+            plan = api.Plan(r.n, r.A, r.H, r.off, arena=(addr, r.plan_bytes), stream=self.solo_stream)
+            self.solo_live += 1
+            self.solo_live_max = max(self.solo_live_max, self.solo_live)
+            try:
+                r.E, r.grad = plan.energy_grad(r.occ, r.theta, _Addr(addr + r.plan_bytes), self.solo_stream)
+            finally:
+                plan.close()
+                self.solo_live -= 1
+        except Exception as e:  # recorded on the request; the loop goes on
+            r.error = f"{type(e).__name__}: {e}"
+        r.t_done = time.perf_counter() - t0
 
     def _solo_poll(self, pending_solo, t0) -> int:
-        """Retire a finished solo request, start the next if its states fit.
-        Returns the number of requests completed."""
+        """Retire a finished solo request, start the next if it fits.
+        Returns the number of requests completed (or failed)."""
         done = 0
         if self.solo_job is not None and not self.solo_job[0].is_alive():
             th, r, rng = self.solo_job
             th.join()
             self.solo_job = None
             self.arena.release(*rng)
-            if self.solo_error is not None:
-                raise RuntimeError(f"solo lane failed on request {r.rid}") from self.solo_error
             done += 1
         if self.solo_job is None and pending_solo:
             r = pending_solo[0]
@@ -292,19 +331,25 @@ class Server:
                 th.start()
         return done
 
-    def _drain_plans(self):
-        for p in self.solo_plans:
-            p.close()
-        self.solo_plans = []
-
     def _finish(self, w: Wave, now):
         E = np.zeros(len(w.reqs))
         g = np.zeros(max(1, sum(len(r.A) for r in w.reqs)))
-        check(lib.qf_batch_collect(w.handle, ptr(E), ptr(g)), "qf_batch_collect")
+        st = lib.qf_batch_collect(w.handle, ptr(E), ptr(g))
+        status = (ctypes.c_int * len(w.reqs))()
+        check(lib.qf_batch_status(w.handle, status), "qf_batch_status")
+        if st != QF_OK and not (st == QF_E_HIP and any(v != QF_OK for v in status)):
+            raise QFError(st, "qf_batch_collect", lib.qf_last_error().decode())
         lib.qf_batch_destroy(w.handle)
         self._publish(w, now)
-        if w.open:
-            raise RuntimeError("a finished wave left requests unpublished")
+        for i, r in enumerate(w.reqs):  # requests whose flag the host had not seen
+            if r.t_done is None:
+                if status[i] == QF_OK:
+                    r.E = float(E[i])
+                    r.grad = g[w.koff[i]:w.koff[i + 1]].copy()
+                else:
+                    r.error = "team barrier timed out"
+                r.t_done = now
+                w.open -= 1
         self.arena.release(*w.arena_range)
 
     def serve(self, requests, poll_s: float = 50e-6):
@@ -312,9 +357,14 @@ class Server:
         def is_solo(r):
             return self.solo_qubits is not None and r.n >= self.solo_qubits
 
+        self.resident_grid = resident_grid()
         for r in requests:
-            if not r.footprint:
-                r.footprint = solo_footprint(r) if is_solo(r) else footprint([r], self.team, self.share)
+            if not r.footprint and r.error is None:
+                try:
+                    r.footprint = (solo_footprint(r) if is_solo(r)
+                                   else footprint([r], self.team, self.share, len(self.streams)))
+                except QFError as e:  # an invalid request is rejected at its arrival
+                    r.error = f"rejected: {e}"
             if r.footprint > self.arena.nbytes:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena has {self.arena.nbytes}")
         pending, pending_solo = [], []
@@ -328,7 +378,6 @@ class Server:
                 self.solo_job = None
             import torch
             torch.cuda.synchronize()
-            self._drain_plans()
         out = stats(requests, self.waves, self.wave_sizes)
         out["max_waves_in_flight"] = self.max_busy
         out["solo_requests"] = self.solo_runs
@@ -340,8 +389,13 @@ class Server:
         while done < len(requests):
             now = time.perf_counter() - t0
             while nxt < len(requests) and requests[nxt].arrival <= now:
-                (pending_solo if is_solo(requests[nxt]) else pending).append(requests[nxt])
+                r = requests[nxt]
                 nxt += 1
+                if r.error is not None:  # rejected at admission
+                    r.t_done = now
+                    done += 1
+                    continue
+                (pending_solo if is_solo(r) else pending).append(r)
             done += self._solo_poll(pending_solo, t0)
             for s, w in enumerate(self.busy):
                 if w is None:
@@ -381,41 +435,63 @@ class Server:
                 time.sleep(poll_s)
 
 
-def serve_plain(requests, max_qubits: int):
-    """One request at a time, FIFO, single-instance kernels (qf_plan_*)."""
+def resident_grid() -> int:
+    """Workgroups of the persistent batched kernel resident on this device."""
+    g = ctypes.c_int()
+    check(lib.qf_batch_resident_grid(ctypes.byref(g)), "qf_batch_resident_grid")
+    return g.value
+
+
+def serve_plain(requests, max_qubits: int, arena_bytes: int | None = None):
+    """One request at a time, FIFO, single-instance kernels (qf_plan_*), each
+    request's plan tables and states in one preallocated arena (no device
+    allocation per request)."""
     import torch
-    ws = torch.empty(2 << max_qubits, dtype=torch.complex128, device="cuda")
+    need = max(_align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off)) + 2 * (1 << r.n) * 16
+               for r in requests) if arena_bytes is None else int(arena_bytes)
+    arena = Arena(need)
+    stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     for r in requests:
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.t_admit = time.perf_counter() - t0
-        plan = api.Plan(r.n, r.A, r.H, r.off)
-        r.E, r.grad = plan.energy_grad(r.occ, r.theta, ws)
-        plan.close()
+        pb = _align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off))
+        try:
+            plan = api.Plan(r.n, r.A, r.H, r.off, arena=(arena.base, pb), stream=stream)
+            try:
+                r.E, r.grad = plan.energy_grad(r.occ, r.theta, _Addr(arena.base + pb), stream)
+            finally:
+                plan.close()
+        except Exception as e:
+            r.error = f"{type(e).__name__}: {e}"
         r.t_done = time.perf_counter() - t0
     return stats(requests, len(requests), [1] * len(requests))
 
 
 def stats(requests, waves, wave_sizes):
-    lat = np.array([r.t_done - r.arrival for r in requests])
+    ok = [r for r in requests if r.error is None]
+    lat = np.array([r.t_done - r.arrival for r in ok]) if ok else np.zeros(1)
     span = max(r.t_done for r in requests) - min(r.arrival for r in requests)
-    return {"requests": len(requests), "throughput_req_per_s": len(requests) / span,
+    return {"requests": len(requests), "completed": len(ok), "failed": len(requests) - len(ok),
+            "throughput_req_per_s": len(ok) / span,
             "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
             "latency_ms_p99": float(np.percentile(lat, 99) * 1e3),
             "latency_ms_max": float(lat.max() * 1e3), "makespan_s": span, "waves": waves,
             "mean_wave_size": float(np.mean(wave_sizes)) if wave_sizes else 0.0}
 
 
-def make_requests(qf, qi, trace):
+def make_requests(qf, qi, trace, workers: int = 16):
     """Requests for (arrival, recipe) pairs; tables are built on the host
-    before the replay (a request carries its tables)."""
-    out = []
-    for j, (t, rcp) in enumerate(trace):
+    before the replay (a request carries its tables), `workers` at a time
+    (the builder calls release the interpreter lock)."""
+    def one(item):
+        j, (t, rcp) = item
         h, g = qi.integrals(rcp["n_orb"], rcp["n_elec"], rcp["seed"])
         H, off, _ = qf.build_paulis("hamiltonian", rcp["n_orb"], rcp["n_elec"], h, g)
         A, aoff, _ = qf.build_paulis("uccsd", rcp["n_orb"], rcp["n_elec"])
         theta = qf.ansatz_angles(A, aoff, qi.amplitudes(len(aoff) - 1, rcp["seed"], rcp["t_scale"]))
-        out.append(Request(j, float(t), 2 * rcp["n_orb"], (1 << rcp["n_elec"]) - 1, A, H, off, theta))
-    return out
+        return Request(j, float(t), 2 * rcp["n_orb"], (1 << rcp["n_elec"]) - 1, A, H, off, theta)
+    with ThreadPoolExecutor(max_workers=max(1, int(workers))) as ex:
+        return list(ex.map(one, enumerate(trace)))

@@ -113,6 +113,15 @@ def test_puccd_builder_matches_oracle(qf):
     _compare(terms, eoff, x, z, c, off)
 
 
+@pytest.mark.parametrize("n_orb", [2, 4, 7])
+def test_gsd_pool_builder_matches_oracle(qf, n_orb):
+    from oracle import adapt
+    ops, x, z, c, off = adapt.pool_terms(2 * n_orb)
+    terms, poff, kept = qf.build_paulis("gsd_pool", n_orb, 0)
+    _compare(terms, poff, x, z, c, off)
+    assert np.array_equal(kept, np.arange(len(ops)))
+
+
 def test_angles_and_chain_rule_match_oracle(qf):
     excs, x, z, c, off, _ = an.build(5, 4)
     terms, eoff, _ = qf.build_paulis("uccsd", 5, 4)

@@ -129,6 +129,25 @@ def test_batch_barrier_timeout_reports_error_and_recovers(qf):
     check_vs_oracle(d, E[0], grads[0])
 
 
+def test_batch_timeout_fails_only_its_instance(qf):
+    """Instances are independent: a team that times out marks only its own
+    instance failed; single-workgroup instances of the same launch (no team
+    barrier) still return their oracle values."""
+    ds = [instance(qf, 6, 6, 52), instance(qf, 8, 8, 53), instance(qf, 6, 6, 54)]
+    B = qf.Batch(ds, team=[1, 4, 1])
+    B.set_spin_limit(1)
+    E, grads, st = B.run([d["theta"] for d in ds], use_graph=False, partial=True)
+    print("status with a one-poll barrier limit:", st, flush=True)
+    assert st[0] == 0 and st[2] == 0 and st[1] in (0, -4)
+    for i in (0, 2):
+        check_vs_oracle(ds[i], E[i], grads[i])
+    B.set_spin_limit(1 << 28)
+    E, grads = B.run([d["theta"] for d in ds], use_graph=False)
+    assert B.status() == [0, 0, 0]
+    for i in range(3):
+        check_vs_oracle(ds[i], E[i], grads[i])
+
+
 def test_batch_recipe_instances(qf):
     """A slice of the batched workload recipe (qubits 12-16 here), one launch."""
     recs = [r for r in qi.batched_instances(256) if r["n_orb"] <= 8][:6]

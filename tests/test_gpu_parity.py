@@ -489,3 +489,81 @@ def test_sigma_shared_pattern_groups_match_oracle(qf, n):
     want = core.sigma(psi0, n, xs, zs, cs)
     assert np.max(np.abs(host(lam) - want)) < 1e-11
     assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
+
+
+# ------------------------------------ largest batched and served instances
+
+def _mix_instance(qf, gold):
+    r = gold["recipe"]
+    h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
+    H, off, _ = qf.build_paulis("hamiltonian", r["n_orb"], r["n_elec"], h, g)
+    A, aoff, _ = qf.build_paulis("uccsd", r["n_orb"], r["n_elec"])
+    th = qf.ansatz_angles(A, aoff, qi.amplitudes(len(aoff) - 1, r["seed"], r["t_scale"]))
+    assert (len(H), len(off) - 1, len(A)) == (gold["n_strings"], gold["n_groups"], gold["K"])
+    return dict(n=2 * r["n_orb"], occ=(1 << r["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff, theta=th)
+
+
+def _check_gold(qf, gold, d, e, g):
+    assert e == pytest.approx(gold["energy"], abs=E_TOL)
+    assert np.max(np.abs(g - np.array(gold["grad_theta"]))) < G_TOL
+    assert np.max(np.abs(qf.grad_t(d["A"], d["aoff"], g) - np.array(gold["grad_t"]))) < G_TOL
+
+
+def test_batch22q_instance_vs_oracle_golden(qf):
+    """The first 22-qubit instance of the 256-instance batched recipe: plan
+    path, the batched kernel alone with its tuned team, and the batched kernel
+    inside a mix, each against the oracle's energy and full gradient."""
+    gold = _golden("batch22q")
+    d = _mix_instance(qf, gold)
+    n = d["n"]
+    plan = qf.Plan(n, d["A"], d["H"], d["off"])
+    ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+    e, g = plan.energy_grad(d["occ"], d["theta"], ws)
+    _check_gold(qf, gold, d, e, g)
+    psi = ws[: 1 << n]
+    qf.prepare_state(psi, n, d["occ"])
+    plan.apply(psi, d["theta"])
+    idx = np.array(gold["sample_index"])
+    want = np.array(gold["sample_re"]) + 1j * np.array(gold["sample_im"])
+    assert np.max(np.abs(host(psi)[idx] - want)) < A_TOL
+    plan.close()
+    del ws, psi
+    B = qf.Batch([d])
+    print("tuned team at 22 qubits:", B.info()["team"], flush=True)
+    E, G = B.run([d["theta"]], use_graph=False)
+    _check_gold(qf, gold, d, E[0], G[0])
+    B.close()
+    small = []
+    for s in (2101, 2102, 2103):
+        h, gg = qi.integrals(6, 6, s)
+        H, off, _ = qf.build_paulis("hamiltonian", 6, 6, h, gg)
+        A, aoff, _ = qf.build_paulis("uccsd", 6, 6)
+        small.append(dict(n=12, occ=63, H=H, off=off, A=A, aoff=aoff,
+                          theta=qf.ansatz_angles(A, aoff, qi.amplitudes(len(aoff) - 1, s, 0.2))))
+    B = qf.Batch(small[:2] + [d] + small[2:])
+    E, G = B.run([x["theta"] for x in small[:2]] + [d["theta"]] + [small[2]["theta"]], use_graph=True)
+    _check_gold(qf, gold, d, E[2], G[2])
+    B.close()
+    torch.cuda.empty_cache()
+
+
+def test_serve24q_request_vs_oracle_golden(qf):
+    """The first 24-qubit request of the serving trace (the solo lane's
+    kernels: an arena plan) against the oracle's energy and full gradient."""
+    gold = _golden("serve24q")
+    d = _mix_instance(qf, gold)
+    n = d["n"]
+    need = qf.Plan.arena_bytes(n, d["A"], d["H"], d["off"])
+    buf = torch.empty(need + (2 << n) * 16 + 512, dtype=torch.uint8, device="cuda")
+    base = (buf.data_ptr() + 255) // 256 * 256
+    plan = qf.Plan(n, d["A"], d["H"], d["off"], arena=(base, need))
+
+    class _At:
+        def data_ptr(self):
+            return (base + need + 255) // 256 * 256
+
+    e, g = plan.energy_grad(d["occ"], d["theta"], _At())
+    _check_gold(qf, gold, d, e, g)
+    plan.close()
+    del buf
+    torch.cuda.empty_cache()

@@ -104,7 +104,8 @@ def test_solo_lane_runs_large_requests_beside_waves(qf):
     srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=8, solo_qubits=18)
     st = srv.serve(reqs)
     srv.close()
-    assert st["requests"] == 10 and st["solo_requests"] == 2
+    assert st["requests"] == 10 and st["solo_requests"] == 2 and st["failed"] == 0
+    assert srv.solo_live_max == 1  # one solo plan alive at a time, its tables in the arena
     ws = torch.empty(2 << 18, dtype=torch.complex128, device="cuda")
     for r in reqs:
         assert r.solo == (r.n >= 18)
@@ -121,3 +122,65 @@ def test_solo_lane_runs_large_requests_beside_waves(qf):
         assert np.max(np.abs(r.grad - g_o)) < 1e-9
     # the small requests did not wait for both large ones
     assert min(r.t_done for r in reqs[2:]) < max(r.t_done for r in reqs[:2])
+
+
+def test_failed_team_fails_only_its_requests(qf):
+    """A one-poll barrier limit (forced from the host) makes teams of more
+    than one workgroup time out; their requests are marked failed, every
+    single-workgroup request still completes with its alone result, and the
+    loop serves the rest of the trace."""
+    from paper_2108_04413_amd import serve
+    tr = [(0.0, dict(n_orb=8, n_elec=8, seed=6100 + j, t_scale=0.1)) for j in range(3)] + \
+         [(0.0, dict(n_orb=6, n_elec=6, seed=6110 + j, t_scale=0.1)) for j in range(5)] + \
+         [(2e-3, dict(n_orb=6, n_elec=6, seed=6120 + j, t_scale=0.1)) for j in range(4)]
+    reqs = serve.make_requests(qf, qi, tr)
+    srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=16, team_table={12: 1, 16: 4}, share=False,
+                       solo_qubits=None, spin_limit=1)
+    st = srv.serve(reqs)
+    srv.close()
+    assert st["requests"] == 12 and st["failed"] >= 1
+    for r in reqs:
+        assert r.t_done is not None
+        if r.n == 12:
+            assert r.team == 1 and r.error is None
+            e, g = alone(qf, r, 1)
+            assert e == r.E and np.array_equal(g, r.grad)
+        elif r.error is not None:
+            assert r.team == 4 and "timed out" in r.error
+        else:  # a team that happened to meet within one poll every time
+            e, g = alone(qf, r, 4)
+            assert e == pytest.approx(r.E, abs=1e-10)
+    assert st["completed"] == sum(1 for r in reqs if r.error is None)
+
+
+def test_solo_lane_failure_and_invalid_request_are_isolated(qf, monkeypatch):
+    """A solo-lane call that raises (forced from the host) and a request
+    with a malformed table fail alone; the others complete and match the
+    oracle."""
+    from paper_2108_04413_amd import serve
+    tr = [(0.0, dict(n_orb=9, n_elec=9, seed=7100, t_scale=0.1)),
+          (0.0, dict(n_orb=9, n_elec=9, seed=7101, t_scale=0.1)),
+          (0.0, dict(n_orb=6, n_elec=6, seed=7102, t_scale=0.1)),
+          (0.0, dict(n_orb=6, n_elec=6, seed=7103, t_scale=0.1))]
+    reqs = serve.make_requests(qf, qi, tr)
+    bad_theta = reqs[0].theta
+    reqs[3].A = reqs[3].A.copy()
+    reqs[3].A["x"][0] |= np.uint64(1 << 40)  # a mask bit beyond the qubit count
+    real = serve.api.Plan.energy_grad
+
+    def flaky(self, occ, theta, ws, stream=None):
+        if theta is bad_theta:
+            raise RuntimeError("injected solo-lane failure")
+        return real(self, occ, theta, ws, stream)
+
+    monkeypatch.setattr(serve.api.Plan, "energy_grad", flaky)
+    srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=8, solo_qubits=18)
+    st = srv.serve(reqs)
+    srv.close()
+    assert st["failed"] == 2 and st["completed"] == 2
+    assert "injected" in reqs[0].error and reqs[3].error.startswith("rejected")
+    for r in (reqs[1], reqs[2]):
+        assert r.error is None
+        e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
+        assert r.E == pytest.approx(e_o, abs=1e-10)
+        assert np.max(np.abs(r.grad - g_o)) < 1e-9

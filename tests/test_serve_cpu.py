@@ -45,3 +45,30 @@ def test_random_alloc_release_never_overlaps():
             assert o == pos and s > 0
             pos = o + s
         assert pos == a.nbytes
+
+
+def _teams(n_qubits, team, grid, concurrent):
+    import ctypes
+    from paper_2108_04413_amd._lib import check, lib
+    c = len(n_qubits)
+    n = (ctypes.c_int * c)(*n_qubits)
+    K = (ctypes.c_int64 * c)(*[10 * q for q in n_qubits])
+    S = (ctypes.c_int64 * c)(*[100 * q for q in n_qubits])
+    T = None if team is None else (ctypes.c_int * c)(*team)
+    W = (ctypes.c_int * c)()
+    check(lib.qf_batch_teams(c, n, K, S, T, grid, concurrent, W), "qf_batch_teams")
+    return list(W)
+
+
+def test_batch_teams_respect_the_co_residency_cap():
+    """Teams of overlapping persistent launches stay within grid / concurrent
+    (host-only computation of the library's team sizes)."""
+    big = [24, 22, 20, 18]
+    alone = _teams(big, [-1] * 4, 512, 1)
+    assert max(alone) > 256  # a lone large instance may take most of the grid
+    for conc in (2, 3, 4):
+        for team in ([-1] * 4, [512, 400, 300, 4], None, [-64, -64, 1, 1]):
+            w = _teams(big, team, 512, conc)
+            assert max(w) <= 512 // conc and min(w) >= 1
+    # small instances are limited by their tiles, not by the cap
+    assert _teams([12, 14], [64, 64], 512, 2) == [2, 8]
