@@ -61,6 +61,20 @@ def residuals(n, occ, ax, az, th, hx, hz, hc, excs):
     return e, r
 
 
+def residuals_core(n, occ, ax, az, th, hx, hz, hc, excs):
+    """(E, r) by the direct form with the C core's loops (20+ qubits)."""
+    from . import core
+    psi = core.apply_product(core.prepare(n, occ), n, ax, az, th)
+    lam = core.sigma(psi, n, hx, hz, hc)
+    e = core.vdot(psi, lam, n).real
+    back = core.apply_product(lam, n, ax, az, th, inverse=True)
+    r = np.zeros(len(excs))
+    for mu, (cre, ann) in enumerate(excs):
+        s, d = excitation_sign(occ, cre, ann)
+        r[mu] = s * back[d].real
+    return e, r
+
+
 def residuals_three_energies(n, occ, ax, az, th, hx, hz, hc, excs):
     """r by the symmetric expectation values of Sec. 3.3 (three energies per mu)."""
     def e_of(chi):

@@ -8,6 +8,7 @@ Calls only the CPU oracle (oracle/) and the seeded input module.  Usage:
     python tests/golden/make_golden.py batch22q  # ~5 min: first 22-qubit instance of the batched mix
     python tests/golden/make_golden.py serve24q  # ~1 h: first 24-qubit request of the serving trace
     python tests/golden/make_golden.py 20q_pool  # ADAPT pool gradients on the 20-qubit final state
+    python tests/golden/make_golden.py 20q_pqe   # PQE residuals of the 20-qubit workload
 
 Each output JSON holds the recipe, the energy, sampled final-state
 amplitudes, and (all but 28q) the full gradient dE/dtheta and dE/dt.
@@ -83,9 +84,27 @@ def main_pool(name):
     print("wrote", path, f"{time.time() - t0:.0f}s", flush=True)
 
 
+def main_pqe(name):
+    """PQE residuals (Sec. 3.3) of a workload's ansatz at its amplitudes."""
+    from oracle import pqe
+    base = name[:-len("_pqe")]
+    t0 = time.time()
+    w, n, occ, (hx, hz, hc, goff), (ax, az, ac, off, th, t) = system(base)
+    excs = an.excitations(n, w["n_elec"])
+    e, r = pqe.residuals_core(n, occ, ax, az, th, hx, hz, hc, excs)
+    out = dict(workload=base, recipe=w, n_qubits=n, occ_mask=occ, n_par=len(excs), energy=e,
+               residuals=r.tolist(), oracle_threads=core.threads(), seconds=time.time() - t0)
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, f"{time.time() - t0:.0f}s", flush=True)
+
+
 def main(name):
     if name.endswith("_pool"):
         return main_pool(name)
+    if name.endswith("_pqe"):
+        return main_pqe(name)
     t0 = time.time()
     w, n, occ, (hx, hz, hc, goff), (ax, az, ac, off, th, t) = system(name)
     print(f"{name}: {len(hx)} strings, {len(goff) - 1} groups, K={len(ax)}", flush=True)
