@@ -250,6 +250,61 @@ int qf_plan_pool_grad(qf_plan *plan, qf_plan *pool, uint64_t occ_mask, const dou
                       double *E_out, double *g_out, void *stream);
 
 /*
+ * PQE (Sec. 3.3).  qf_excited_determinants: for each excitation of an
+ * ansatz kind, in qf_build_paulis order, the excited determinant
+ * tau_mu |ref> = sign[mu] |det[mu]> (bit strings; sign 0 if tau_mu
+ * annihilates the reference, which particle-hole kinds never do); with
+ * det == NULL only *n_out is written.  qf_mp_denominators: the
+ * Moller-Plesset denominators Delta_mu = sum eps_occ - sum eps_vir of the
+ * particle-hole kinds, with eps_P the diagonal of the reference's Fock
+ * matrix, h_pp + sum_{J occupied} <PJ||PJ> (the reading for references that
+ * are not canonical Hartree-Fock determinants).
+ * qf_pqe_residuals / qf_plan_pqe_residuals: for Psi = U(theta)|occ_mask>,
+ *   r_mu = <Phi_mu|U^dagger H U|Phi_0> = sign[mu] [U^dagger H Psi](det[mu])
+ * (Eq. (ucc2)) for n_res <= K determinants: one forward pass, lambda = H Psi,
+ * the ansatz undone on lambda in reverse, and the amplitudes at det[] (the
+ * real part; U and H are real).  E_out receives <Psi|H|Psi>.  workspace:
+ * 2 * 2^n_qubits * 16 bytes of device memory.  det, sign, r_out: host.
+ * qf_plan_pqe_solve: the fixed-point iteration of Eq. (fixed_point),
+ *   t_mu <- t_mu + r_mu / Delta_mu,
+ * from t (host, n_par amplitudes, updated in place) until max |r_mu| < tol
+ * or max_iter updates; theta_k = -c_k t_mu as qf_ansatz_angles.  r_out
+ * holds the last residuals, *iters the number of updates made.
+ */
+int qf_excited_determinants(int kind, int n_orb, int n_elec, const double *t_rank, int64_t top_k,
+                            uint64_t *det, int *sign, int64_t cap, int64_t *n_out);
+int qf_mp_denominators(int kind, int n_orb, int n_elec, const double *h, const double *g,
+                       const double *t_rank, int64_t top_k, double *delta, int64_t cap, int64_t *n_out);
+int qf_pqe_residuals(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta, int64_t K,
+                     const qf_term *H, const int64_t *group_off, int64_t n_groups, const uint64_t *det,
+                     const int *sign, int64_t n_res, void *workspace, double *E_out, double *r_out, void *stream);
+int qf_plan_pqe_residuals(qf_plan *plan, uint64_t occ_mask, const double *theta, const uint64_t *det,
+                          const int *sign, int64_t n_res, void *workspace, double *E_out, double *r_out,
+                          void *stream);
+int qf_plan_pqe_solve(qf_plan *plan, uint64_t occ_mask, const qf_term *A, const int64_t *exc_off, int64_t n_par,
+                      const uint64_t *det, const int *sign, const double *delta, double *t, int max_iter,
+                      double tol, void *workspace, double *E_out, double *r_out, int *iters, void *stream);
+
+/*
+ * Quantum Krylov basis by Trotterized real-time evolution (Sec. 3.7).
+ * The plan must hold the Hamiltonian twice: as its ansatz (A = H's strings
+ * with their coefficients h_l, in the order of the product) and as its
+ * grouped Hamiltonian (qf_plan_create(n, H, K_H, H, group_off, G)).
+ * qf_plan_trotter: psi <- (prod_l exp(-i t h_l P_l / r))^r psi
+ *   (Eq. (m_trotter_step2); the first string acts first; r >= 1).
+ * qf_plan_qk_matrices: the basis psi_k = Trotter(k dt, r)|occ_mask>,
+ *   k = 0 .. s (0 <= s < 16), each evolved from the reference, and
+ *   S_out[m][k] = <psi_m|psi_k>, H_out[m][k] = <psi_m|H|psi_k>
+ *   ((s+1)^2 complex values each, row-major, interleaved re/im, host).
+ *   states: device memory for s + 2 states ((s+2) * 2^n_qubits * 16 bytes);
+ *   on return states[k] holds psi_k.  The generalized eigenproblem
+ *   H c = S c E is left to the caller.
+ */
+int qf_plan_trotter(qf_plan *plan, void *psi, double t, int r, void *stream);
+int qf_plan_qk_matrices(qf_plan *plan, uint64_t occ_mask, double dt, int s, int r, void *states,
+                        double *S_out, double *H_out, void *stream);
+
+/*
  * Batches: energy and adjoint gradient of many instances (different
  * molecules, qubit counts or parameter vectors) in ONE persistent kernel
  * launch, optionally replayed as a HIP graph.  Sec. 3.1, Eqs. (16)-(18)

@@ -40,7 +40,9 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_mailbox_alloc", "qf_mailbox_free", "qf_batch_mailbox_bytes", "qf_batch_launch_mailbox",
            "qf_plan_set_energy_tile", "qf_plan_info", "qf_plan_set_block_bits", "qf_plan_apply_info",
            "qf_plan_create_arena", "qf_batch_status", "qf_batch_teams",
-           "qf_batch_resident_grid", "qf_pool_grad", "qf_plan_create_pool", "qf_plan_pool_grad")
+           "qf_batch_resident_grid", "qf_pool_grad", "qf_plan_create_pool", "qf_plan_pool_grad",
+           "qf_excited_determinants", "qf_mp_denominators", "qf_pqe_residuals", "qf_plan_pqe_residuals",
+           "qf_plan_pqe_solve", "qf_plan_trotter", "qf_plan_qk_matrices")
 
 
 class QFError(RuntimeError):
@@ -80,6 +82,13 @@ _sig = {
     "qf_batch_status": [_vp, _vp],
     "qf_pool_grad": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "qf_plan_create_pool": [_int, _vp, _vp, _i64, _vp],
+    "qf_plan_trotter": [_vp, _vp, _dbl, _int, _vp],
+    "qf_plan_qk_matrices": [_vp, _u64, _dbl, _int, _int, _vp, _vp, _vp, _vp],
+    "qf_excited_determinants": [_int, _int, _int, _vp, _i64, _vp, _vp, _i64, _vp],
+    "qf_mp_denominators": [_int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _vp],
+    "qf_pqe_residuals": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
+    "qf_plan_pqe_residuals": [_vp, _u64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
+    "qf_plan_pqe_solve": [_vp, _u64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _int, _dbl, _vp, _vp, _vp, _vp, _vp],
     "qf_plan_pool_grad": [_vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp],
     "qf_batch_resident_grid": [_vp],
     "qf_batch_teams": [_int, _vp, _vp, _vp, _vp, _int, _int, _vp],

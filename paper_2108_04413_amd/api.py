@@ -106,6 +106,50 @@ def pool_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarray,
     return e.value, g
 
 
+def excited_determinants(kind: str, n_orb: int, n_elec: int, t_rank=None, top_k: int = 0):
+    """qf_excited_determinants: (det[uint64], sign[int32]) with
+    tau_mu |ref> = sign_mu |det_mu> per excitation of the ansatz kind."""
+    t_rank = _f64(t_rank)
+    n = ctypes.c_int64()
+    check(lib.qf_excited_determinants(KINDS[kind], n_orb, n_elec, ptr(t_rank), int(top_k), None, None, 0,
+                                      ctypes.byref(n)), "qf_excited_determinants(size)")
+    det = np.zeros(n.value, dtype=np.uint64)
+    sign = np.zeros(n.value, dtype=np.int32)
+    check(lib.qf_excited_determinants(KINDS[kind], n_orb, n_elec, ptr(t_rank), int(top_k), ptr(det), ptr(sign),
+                                      n.value, ctypes.byref(n)), "qf_excited_determinants")
+    return det, sign
+
+
+def mp_denominators(kind: str, n_orb: int, n_elec: int, h, g, t_rank=None, top_k: int = 0) -> np.ndarray:
+    """qf_mp_denominators: Delta_mu of Eq. (fixed_point) per excitation."""
+    h, g, t_rank = _f64(h), _f64(g), _f64(t_rank)
+    n = ctypes.c_int64()
+    check(lib.qf_mp_denominators(KINDS[kind], n_orb, n_elec, ptr(h), ptr(g), ptr(t_rank), int(top_k), None, 0,
+                                 ctypes.byref(n)), "qf_mp_denominators(size)")
+    out = np.zeros(n.value, dtype=np.float64)
+    check(lib.qf_mp_denominators(KINDS[kind], n_orb, n_elec, ptr(h), ptr(g), ptr(t_rank), int(top_k), ptr(out),
+                                 n.value, ctypes.byref(n)), "qf_mp_denominators")
+    return out
+
+
+def pqe_residuals(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarray, group_off: np.ndarray,
+                  det: np.ndarray, sign: np.ndarray, workspace=None, stream=None):
+    """qf_pqe_residuals: (E, r) with r_mu = <Phi_mu|U^dagger H U|Phi_0> (Sec. 3.3)."""
+    import torch
+    theta = _f64(theta)
+    group_off = np.ascontiguousarray(group_off, dtype=np.int64)
+    det = np.ascontiguousarray(det, dtype=np.uint64)
+    sign = np.ascontiguousarray(sign, dtype=np.int32)
+    if workspace is None:
+        workspace = torch.empty(2 << n_qubits, dtype=torch.complex128, device="cuda")
+    e = ctypes.c_double()
+    r = np.zeros(len(det), dtype=np.float64)
+    check(lib.qf_pqe_residuals(n_qubits, occ_mask, ptr(A), ptr(theta), len(A), ptr(H), ptr(group_off),
+                               len(group_off) - 1, ptr(det), ptr(sign), len(det), ptr(workspace), ctypes.byref(e),
+                               ptr(r), stream_handle(stream)), "qf_pqe_residuals")
+    return e.value, r
+
+
 class PoolPlan:
     """qf_plan_create_pool: device tables of an ADAPT operator pool."""
 
@@ -257,6 +301,52 @@ class Plan:
         check(lib.qf_plan_sigma(self._h, ptr(psi), ptr(lam), ctypes.byref(e), stream_handle(stream)),
               "qf_plan_sigma")
         return e.value
+
+    def trotter(self, psi, t: float, r: int, stream=None) -> None:
+        """qf_plan_trotter: psi <- (prod_l exp(-i t h_l P_l / r))^r psi over
+        the plan's ansatz strings (a plan made with the Hamiltonian as ansatz)."""
+        check(lib.qf_plan_trotter(self._h, ptr(psi), float(t), int(r), stream_handle(stream)), "qf_plan_trotter")
+
+    def qk_matrices(self, occ_mask: int, dt: float, s: int, r: int, states=None, stream=None):
+        """qf_plan_qk_matrices: (S, Hm) complex (s+1) x (s+1) for the basis
+        psi_k = Trotter(k dt, r)|occ> (Sec. 3.7).  states: complex128 tensor
+        of (s + 2) * 2^n (allocated if None); returns states too."""
+        import torch
+        if states is None:
+            states = torch.empty((s + 2) << self.n, dtype=torch.complex128, device="cuda")
+        S = np.zeros((s + 1, s + 1), dtype=np.complex128)
+        Hm = np.zeros_like(S)
+        check(lib.qf_plan_qk_matrices(self._h, occ_mask, float(dt), int(s), int(r), ptr(states), ptr(S), ptr(Hm),
+                                      stream_handle(stream)), "qf_plan_qk_matrices")
+        return S, Hm, states
+
+    def pqe_residuals(self, occ_mask: int, theta, det, sign, workspace, stream=None):
+        """qf_plan_pqe_residuals: (E, r), r_mu = <Phi_mu|U^dagger H U|Phi_0>."""
+        theta = _f64(theta)
+        det = np.ascontiguousarray(det, dtype=np.uint64)
+        sign = np.ascontiguousarray(sign, dtype=np.int32)
+        e = ctypes.c_double()
+        r = np.zeros(len(det), dtype=np.float64)
+        check(lib.qf_plan_pqe_residuals(self._h, occ_mask, ptr(theta), ptr(det), ptr(sign), len(det), ptr(workspace),
+                                        ctypes.byref(e), ptr(r), stream_handle(stream)), "qf_plan_pqe_residuals")
+        return e.value, r
+
+    def pqe_solve(self, occ_mask: int, exc_off, det, sign, delta, t0, workspace, max_iter: int = 100,
+                  tol: float = 1e-8, stream=None):
+        """qf_plan_pqe_solve: fixed-point PQE (Eq. (fixed_point)) from t0.
+        Returns (t, E, r, updates)."""
+        exc_off = np.ascontiguousarray(exc_off, dtype=np.int64)
+        t = np.array(t0, dtype=np.float64)
+        det = np.ascontiguousarray(det, dtype=np.uint64)
+        sign = np.ascontiguousarray(sign, dtype=np.int32)
+        delta = _f64(delta)
+        e = ctypes.c_double()
+        r = np.zeros(len(t), dtype=np.float64)
+        it = ctypes.c_int()
+        check(lib.qf_plan_pqe_solve(self._h, occ_mask, ptr(self._A), ptr(exc_off), len(t), ptr(det), ptr(sign),
+                                    ptr(delta), ptr(t), int(max_iter), float(tol), ptr(workspace), ctypes.byref(e),
+                                    ptr(r), ctypes.byref(it), stream_handle(stream)), "qf_plan_pqe_solve")
+        return t, e.value, r, it.value
 
     def pool_grad(self, pool: "PoolPlan", occ_mask: int, theta, workspace, stream=None):
         """qf_plan_pool_grad: (E, g) for the pool members (ADAPT-VQE, Sec. 3.2)."""

@@ -280,10 +280,140 @@ void build_ansatz(int kind, int n_orb, int ne, const double *t_rank, int64_t top
     out.kept = idx;
 }
 
+// The excitations of an ansatz kind, in emission order (as build_ansatz).
+std::vector<Excitation> ansatz_excitations(int kind, int n_orb, int ne, const double *t_rank, int64_t top_k)
+{
+    const int nq = 2 * n_orb;
+    if (kind == QF_GSD_POOL)
+        return generalized_pool(nq);
+    if (kind == QF_PUCCD) {
+        std::vector<Excitation> ex;
+        const int nocc = ne / 2, nvir = (nq - ne) / 2;
+        for (int i = 0; i < nocc; i++)
+            for (int a = 0; a < nvir; a++) {
+                const int ia = 2 * i, ib = 2 * i + 1, aa = 2 * nocc + 2 * a, ab = 2 * nocc + 2 * a + 1;
+                ex.push_back(Excitation{0, 2, {ab, aa}, {ia, ib}});
+            }
+        return ex;
+    }
+    std::vector<Excitation> ex = enumerate(nq, ne, kind == QF_UCCSD, true);
+    if (kind == QF_UCCD_TOP) {
+        std::vector<int64_t> order(ex.size());
+        for (size_t m = 0; m < ex.size(); m++)
+            order[m] = (int64_t)m;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t u, int64_t v) { return std::fabs(t_rank[u]) > std::fabs(t_rank[v]); });
+        if ((size_t)top_k < order.size())
+            order.resize((size_t)top_k);
+        std::sort(order.begin(), order.end());
+        std::vector<Excitation> keep;
+        for (int64_t m : order)
+            keep.push_back(ex[(size_t)m]);
+        ex.swap(keep);
+    }
+    return ex;
+}
+
+// tau |ref> = sign |det>: the ladder operators act right to left, a_p and
+// a+_p each contribute (-1)^(occupied spin orbitals below p); sign 0 if tau
+// annihilates the reference.
+void excite(uint64_t ref, const Excitation &e, uint64_t &det, int &sign)
+{
+    int ops[4];
+    bool cre[4];
+    int m = 0;
+    for (int c = 0; c < e.ncre; c++) {
+        ops[m] = e.cre[c];
+        cre[m++] = true;
+    }
+    for (int c = 0; c < e.ncre; c++) {
+        ops[m] = e.ann[c];
+        cre[m++] = false;
+    }
+    uint64_t b = ref;
+    int s = 1;
+    for (int j = m - 1; j >= 0; j--) {
+        const uint64_t bit = 1ull << ops[j];
+        if (((b & bit) != 0) == cre[j]) {
+            det = 0;
+            sign = 0;
+            return;
+        }
+        if (popc64(b & (bit - 1)) & 1)
+            s = -s;
+        b ^= bit;
+    }
+    det = b;
+    sign = s;
+}
+
 } // namespace
 } // namespace qf
 
 using namespace qf;
+
+extern "C" int qf_excited_determinants(int kind, int n_orb, int n_elec, const double *t_rank, int64_t top_k,
+                                       uint64_t *det, int *sign, int64_t cap, int64_t *n_out)
+{
+    return guarded([&]() -> int {
+        if (kind < QF_UCCSD || kind > QF_GSD_POOL)
+            return fail(QF_E_ARG, "qf_excited_determinants: not an ansatz kind: %d", kind);
+        if (n_orb < 1 || 2 * n_orb > 64 || n_elec < 0 || n_elec > 2 * n_orb)
+            return fail(QF_E_RANGE, "qf_excited_determinants: n_orb=%d n_elec=%d out of range", n_orb, n_elec);
+        if (!n_out || (kind == QF_UCCD_TOP && (!t_rank || top_k < 0)))
+            return fail(QF_E_ARG, "qf_excited_determinants: bad arguments");
+        const std::vector<Excitation> ex = ansatz_excitations(kind, n_orb, n_elec, t_rank, top_k);
+        *n_out = (int64_t)ex.size();
+        if (!det)
+            return QF_OK;
+        if (!sign || cap < *n_out)
+            return fail(QF_E_SIZE, "qf_excited_determinants: need %lld entries", (long long)*n_out);
+        const uint64_t ref = n_elec >= 64 ? ~0ull : ((1ull << n_elec) - 1);
+        for (size_t m = 0; m < ex.size(); m++)
+            excite(ref, ex[m], det[m], sign[m]);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_mp_denominators(int kind, int n_orb, int n_elec, const double *h, const double *g,
+                                  const double *t_rank, int64_t top_k, double *delta, int64_t cap, int64_t *n_out)
+{
+    return guarded([&]() -> int {
+        if (kind < QF_UCCSD || kind > QF_PUCCD)
+            return fail(QF_E_ARG, "qf_mp_denominators: not a particle-hole ansatz kind: %d", kind);
+        if (n_orb < 1 || 2 * n_orb > 64 || n_elec < 0 || n_elec > 2 * n_orb)
+            return fail(QF_E_RANGE, "qf_mp_denominators: n_orb=%d n_elec=%d out of range", n_orb, n_elec);
+        if (!n_out || !h || !g || (kind == QF_UCCD_TOP && (!t_rank || top_k < 0)))
+            return fail(QF_E_ARG, "qf_mp_denominators: bad arguments");
+        const std::vector<Excitation> ex = ansatz_excitations(kind, n_orb, n_elec, t_rank, top_k);
+        *n_out = (int64_t)ex.size();
+        if (!delta)
+            return QF_OK;
+        if (cap < *n_out)
+            return fail(QF_E_SIZE, "qf_mp_denominators: need %lld entries", (long long)*n_out);
+        // reference Fock diagonal: eps_P = h_pp + sum_{J occ} [(pp|jj) - d(sP,sJ) (pj|jp)]
+        const int n = n_orb, N = 2 * n_orb;
+        std::vector<double> eps((size_t)N);
+        for (int P = 0; P < N; P++) {
+            const int p = P / 2;
+            double e = h[p * n + p];
+            for (int J = 0; J < n_elec; J++) {
+                const int j = J / 2;
+                e += g[((size_t)(p * n + p) * n + j) * n + j];
+                if ((P & 1) == (J & 1))
+                    e -= g[((size_t)(p * n + j) * n + j) * n + p];
+            }
+            eps[(size_t)P] = e;
+        }
+        for (size_t m = 0; m < ex.size(); m++) {
+            double d = 0.0;
+            for (int c = 0; c < ex[m].ncre; c++)
+                d += eps[(size_t)ex[m].ann[c]] - eps[(size_t)ex[m].cre[c]];
+            delta[m] = d;
+        }
+        return QF_OK;
+    });
+}
 
 extern "C" int qf_build_paulis(int kind, int n_orb, int n_elec, const double *h, const double *g,
                                double e_core, const double *t_rank, int64_t top_k,

@@ -113,6 +113,44 @@ __global__ __launch_bounds__(kBlock) void k_prepare(double2 *__restrict__ psi, u
         psi[y] = make_double2(y == occ ? 1.0 : 0.0, 0.0);
 }
 
+// <a|x_j> and <b|x_j> for the J <= JMAX states x_j = xs + j * dim: out[2j],
+// out[2j + 1] the real and imaginary parts of <a|x_j>, out[2 JMAX + 2j],
+// out[2 JMAX + 2j + 1] those of <b|x_j>; fixed-order reduction.
+constexpr int kMaxDots = 16;
+template <int JMAX>
+__global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ a, const double2 *__restrict__ b,
+                                                 const double2 *__restrict__ xs, uint64_t dim, int J,
+                                                 double *partials, unsigned *counter, double *out)
+{
+    double v[4 * JMAX];
+#pragma unroll
+    for (int k = 0; k < 4 * JMAX; k++)
+        v[k] = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t y = (uint64_t)blockIdx.x * kBlock + threadIdx.x; y < dim; y += stride) {
+        const double2 av = a[y], bv = b[y];
+#pragma unroll
+        for (int j = 0; j < JMAX; j++) {
+            if (j < J) {
+                const double2 x = xs[(uint64_t)j * dim + y];
+                v[2 * j] += av.x * x.x + av.y * x.y;
+                v[2 * j + 1] += av.x * x.y - av.y * x.x;
+                v[2 * JMAX + 2 * j] += bv.x * x.x + bv.y * x.y;
+                v[2 * JMAX + 2 * j + 1] += bv.x * x.y - bv.y * x.x;
+            }
+        }
+    }
+    reduce_finish<4 * JMAX>(v, partials, counter, out, 1.0, 4 * JMAX);
+}
+
+// out[i] = psi[idx[i]]: the amplitudes at a list of basis states.
+__global__ __launch_bounds__(kBlock) void k_gather(const double2 *__restrict__ psi, const uint64_t *__restrict__ idx,
+                                                   int64_t count, double2 *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+        out[i] = psi[idx[i]];
+}
+
 __global__ __launch_bounds__(64) void k_zero_u32(unsigned *__restrict__ p, unsigned count)
 {
     for (unsigned i = threadIdx.x; i < count; i += blockDim.x)
@@ -1457,6 +1495,10 @@ struct qf_plan {
     // plan's "ansatz", members sorted by flip mask so that the blocked sweep
     // packs them into few segments; member i of the sorted order is caller
     // member pool_perm[i], its strings pool_off[i] .. pool_off[i + 1].
+    std::vector<double> ac;      // the ansatz strings' coefficients (Trotter angles)
+    double *d_dots = nullptr;    // QK: inner products of one state with a list of states
+    uint64_t *d_pidx = nullptr;  // PQE: determinant indices to read (K entries)
+    double2 *d_pout = nullptr;   // PQE: the amplitudes read there
     bool is_pool = false;
     std::vector<int64_t> pool_off, pool_perm;
     std::vector<double> pool_c;
@@ -1511,7 +1553,8 @@ struct qf_plan {
         if (mem != kOwned)
             return;
         void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
-                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_sclasses, d_sgroups};
+                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_sclasses, d_sgroups, d_pidx, d_pout,
+                        d_dots};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -1734,10 +1777,15 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
     if (K > 0) {
         check_terms("ansatz", n, A, K);
         P.runs = make_runs(A, K, P.tab_entries);
+        P.ac.resize((size_t)K);
+        for (int64_t k = 0; k < K; k++)
+            P.ac[(size_t)k] = A[k].c;
         P.d_runs = P.dalloc<RunDesc>(P.runs.size());
         P.d_theta = P.dalloc<double>((size_t)K);
         P.d_tab = P.dalloc<double2>((size_t)P.tab_entries);
         P.d_grad = P.dalloc<double>((size_t)K);
+        P.d_pidx = P.dalloc<uint64_t>((size_t)K);
+        P.d_pout = P.dalloc<double2>((size_t)K);
         P.upload(P.d_runs, P.runs.data(), P.runs.size() * sizeof(RunDesc));
         set_block_bits(P, block_bits >= 0 ? block_bits : n >= 6 ? std::min(n, 12) : 0);
         // pinned staging for theta (an arena plan stages nothing: freeing
@@ -1781,6 +1829,7 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
     P.d_partials = P.dalloc<double>((size_t)kMaxBlocks * kMaxRun);
     P.d_counter = P.dalloc<unsigned>(1);
     P.d_result = P.dalloc<double>(4);
+    P.d_dots = P.dalloc<double>(4 * kMaxDots);
     if (P.mem == qf_plan::kOwned) {
         QF_HIP(hipMemset(P.d_counter, 0, sizeof(unsigned)));
     } else if (P.mem == qf_plan::kRegion) {
@@ -2174,9 +2223,202 @@ void pool_grad_impl(qf_plan &P, qf_plan &Q, uint64_t occ, const double *theta, v
     }
 }
 
+// PQE residuals (Sec. 3.3): r_mu = s_mu [U^dagger H U Phi_0](d_mu): the
+// forward pass, lambda = H psi, lambda <- U^dagger lambda (the runs undone in
+// reverse), then the amplitudes of lambda at the excited determinants.
+void pqe_impl(qf_plan &P, uint64_t occ, const double *theta, const uint64_t *det, const int *sign, int64_t n_res,
+              void *workspace, double *E_out, double *r_out, hipStream_t s)
+{
+    if (!workspace || !E_out || (n_res > 0 && (!det || !sign || !r_out)))
+        raise(QF_E_ARG, "pqe_residuals: null workspace, determinants or output");
+    if (P.G == 0 || P.K == 0)
+        raise(QF_E_ARG, "pqe_residuals: the plan needs an ansatz and a Hamiltonian");
+    if (n_res < 0 || n_res > P.K)
+        raise(QF_E_ARG, "pqe_residuals: between 0 and K residuals");
+    if (occ >> P.n)
+        raise(QF_E_RANGE, "occ_mask has a bit >= n_qubits");
+    for (int64_t i = 0; i < n_res; i++)
+        if (det[i] >> P.n)
+            raise(QF_E_RANGE, "pqe_residuals: determinant " + std::to_string(i) + " has a bit >= n_qubits");
+    double2 *phi = (double2 *)workspace;
+    double2 *lam = phi + (1ull << P.n);
+    launch_prepare(phi, P.n, occ, s);
+    upload_theta(P, theta, s);
+    launch_runs(P, phi, false, s);
+    launch_sigma(P, phi, lam, P.d_result, s);
+    launch_runs(P, lam, true, s);
+    std::vector<double2> amp((size_t)std::max<int64_t>(n_res, 1));
+    if (n_res > 0) {
+        QF_HIP(hipMemcpyAsync(P.d_pidx, det, (size_t)n_res * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gather, dim3(grid_for((uint64_t)n_res, kBlock, 64)), dim3(kBlock), 0, s, lam, P.d_pidx,
+                           n_res, P.d_pout);
+        QF_HIP(hipGetLastError());
+        QF_HIP(hipMemcpyAsync(amp.data(), P.d_pout, (size_t)n_res * sizeof(double2), hipMemcpyDeviceToHost, s));
+    }
+    QF_HIP(hipMemcpyAsync(E_out, P.d_result, sizeof(double), hipMemcpyDeviceToHost, s));
+    QF_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n_res; i++)
+        r_out[i] = (double)sign[i] * amp[(size_t)i].x;
+}
+
+// psi <- (prod_k exp(-i t c_k P_k / r))^r psi over the plan's ansatz strings
+// (Sec. 3.7, Eq. (m_trotter_step2) with the Hamiltonian's strings as the
+// ansatz): theta_k = t c_k / r, the fused runs applied r times.
+void trotter_impl(qf_plan &P, double2 *psi, double t, int r, hipStream_t s)
+{
+    if (P.K == 0)
+        raise(QF_E_ARG, "trotter: the plan has no strings to exponentiate");
+    if (r < 1)
+        raise(QF_E_ARG, "trotter: r must be >= 1");
+    std::vector<double> th((size_t)P.K);
+    for (int64_t k = 0; k < P.K; k++)
+        th[(size_t)k] = t * P.ac[(size_t)k] / (double)r;
+    upload_theta(P, th.data(), s);
+    for (int i = 0; i < r; i++)
+        launch_runs(P, psi, false, s);
+}
+
+void dots(qf_plan &P, const double2 *a, const double2 *b, const double2 *xs, int J, hipStream_t s)
+{
+    const uint64_t dim = 1ull << P.n;
+    // partials hold kMaxBlocks * kMaxRun doubles: 4 * JMAX per block
+    if (J <= 4) {
+        const unsigned nb = grid_for(dim, (uint64_t)kBlock * 4, (unsigned)(kMaxBlocks * kMaxRun / 16));
+        hipLaunchKernelGGL(k_dots<4>, dim3(nb), dim3(kBlock), 0, s, a, b, xs, dim, J, P.d_partials, P.d_counter,
+                           P.d_dots);
+    } else {
+        const unsigned nb = grid_for(dim, (uint64_t)kBlock * 4, (unsigned)(kMaxBlocks * kMaxRun / 64));
+        hipLaunchKernelGGL(k_dots<kMaxDots>, dim3(nb), dim3(kBlock), 0, s, a, b, xs, dim, J, P.d_partials,
+                           P.d_counter, P.d_dots);
+    }
+    QF_HIP(hipGetLastError());
+}
+
+// QK basis psi_k = Trotter(k dt, r) |occ>, k = 0 .. s, in states[0 .. s];
+// states[s + 1] holds H psi_m in turn.  S[m][k] = <psi_m|psi_k>,
+// Hm[m][k] = <H psi_m|psi_k> = <psi_m|H|psi_k>, complex, row-major.
+void qk_impl(qf_plan &P, uint64_t occ, double dt, int s_max, int r, double2 *states, double *S, double *Hm,
+             hipStream_t s)
+{
+    if (P.G == 0 || P.K == 0)
+        raise(QF_E_ARG, "qk_matrices: the plan needs the Hamiltonian as both ansatz and Hamiltonian");
+    if (s_max < 0 || s_max + 1 > kMaxDots)
+        raise(QF_E_ARG, "qk_matrices: 0 <= s < " + std::to_string(kMaxDots));
+    if (!states || !S || !Hm)
+        raise(QF_E_ARG, "qk_matrices: null states or output");
+    if (occ >> P.n)
+        raise(QF_E_RANGE, "occ_mask has a bit >= n_qubits");
+    const uint64_t dim = 1ull << P.n;
+    const int J = s_max + 1;
+    for (int k = 0; k < J; k++) {
+        launch_prepare(states + (uint64_t)k * dim, P.n, occ, s);
+        if (k > 0)
+            trotter_impl(P, states + (uint64_t)k * dim, k * dt, r, s);
+    }
+    double2 *sig = states + (uint64_t)J * dim;
+    const int JM = J <= 4 ? 4 : kMaxDots;
+    std::vector<double> out((size_t)4 * JM);
+    for (int m = 0; m < J; m++) {
+        launch_sigma(P, states + (uint64_t)m * dim, sig, P.d_result, s);
+        dots(P, states + (uint64_t)m * dim, sig, states, J, s);
+        QF_HIP(hipMemcpyAsync(out.data(), P.d_dots, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        QF_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < J; k++) {
+            S[2 * (m * J + k)] = out[(size_t)(2 * k)];
+            S[2 * (m * J + k) + 1] = out[(size_t)(2 * k + 1)];
+            Hm[2 * (m * J + k)] = out[(size_t)(2 * JM + 2 * k)];
+            Hm[2 * (m * J + k) + 1] = out[(size_t)(2 * JM + 2 * k + 1)];
+        }
+    }
+}
+
 } // namespace qf
 
 using namespace qf;
+
+extern "C" int qf_plan_trotter(qf_plan *plan, void *psi, double t, int r, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!plan || !psi)
+            return fail(QF_E_ARG, "qf_plan_trotter: null plan or state");
+        trotter_impl(*plan, (double2 *)psi, t, r, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_qk_matrices(qf_plan *plan, uint64_t occ_mask, double dt, int s, int r, void *states,
+                                   double *S_out, double *H_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!plan)
+            return fail(QF_E_ARG, "qf_plan_qk_matrices: plan is NULL");
+        qk_impl(*plan, occ_mask, dt, s, r, (double2 *)states, S_out, H_out, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_pqe_residuals(qf_plan *plan, uint64_t occ_mask, const double *theta, const uint64_t *det,
+                                     const int *sign, int64_t n_res, void *workspace, double *E_out, double *r_out,
+                                     void *stream)
+{
+    return guarded([&]() -> int {
+        if (!plan)
+            return fail(QF_E_ARG, "qf_plan_pqe_residuals: plan is NULL");
+        pqe_impl(*plan, occ_mask, theta, det, sign, n_res, workspace, E_out, r_out, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_pqe_residuals(int n_qubits, uint64_t occ_mask, const qf_term *A, const double *theta, int64_t K,
+                                const qf_term *H, const int64_t *group_off, int64_t n_groups, const uint64_t *det,
+                                const int *sign, int64_t n_res, void *workspace, double *E_out, double *r_out,
+                                void *stream)
+{
+    return guarded([&]() -> int {
+        if (n_groups < 1 || K < 1)
+            return fail(QF_E_ARG, "qf_pqe_residuals: needs an ansatz and a Hamiltonian");
+        qf_plan P;
+        plan_init(P, n_qubits, A, K, H, group_off, n_groups);
+        pqe_impl(P, occ_mask, theta, det, sign, n_res, workspace, E_out, r_out, (hipStream_t)stream);
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_plan_pqe_solve(qf_plan *plan, uint64_t occ_mask, const qf_term *A, const int64_t *exc_off,
+                                 int64_t n_par, const uint64_t *det, const int *sign, const double *delta,
+                                 double *t, int max_iter, double tol, void *workspace, double *E_out, double *r_out,
+                                 int *iters, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!plan || !A || !exc_off || !det || !sign || !delta || !t || !r_out || !iters || max_iter < 0)
+            return fail(QF_E_ARG, "qf_plan_pqe_solve: bad arguments");
+        if (n_par < 1 || exc_off[n_par] != plan->K)
+            return fail(QF_E_ARG, "qf_plan_pqe_solve: exc_off does not cover the plan's ansatz");
+        for (int64_t mu = 0; mu < n_par; mu++)
+            if (delta[mu] == 0.0)
+                return fail(QF_E_ARG, "qf_plan_pqe_solve: Delta_%lld is zero", (long long)mu);
+        std::vector<double> theta((size_t)plan->K);
+        hipStream_t s = (hipStream_t)stream;
+        *iters = 0;
+        for (int it = 0;; it++) {
+            // theta_k = -c_k t_mu (Sec. 3.1 product of exponentials)
+            for (int64_t mu = 0; mu < n_par; mu++)
+                for (int64_t k = exc_off[mu]; k < exc_off[mu + 1]; k++)
+                    theta[(size_t)k] = -A[k].c * t[mu];
+            pqe_impl(*plan, occ_mask, theta.data(), det, sign, n_par, workspace, E_out, r_out, s);
+            double rmax = 0.0;
+            for (int64_t mu = 0; mu < n_par; mu++)
+                rmax = std::max(rmax, std::fabs(r_out[mu]));
+            *iters = it;
+            if (rmax < tol || it >= max_iter)
+                break;
+            // Eq. (fixed_point): t_mu <- t_mu + r_mu / Delta_mu
+            for (int64_t mu = 0; mu < n_par; mu++)
+                t[mu] += r_out[mu] / delta[mu];
+        }
+        return QF_OK;
+    });
+}
 
 extern "C" int qf_plan_create_pool(int n_qubits, const qf_term *pool, const int64_t *pool_off, int64_t n_pool,
                                    qf_plan **out)

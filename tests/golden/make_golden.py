@@ -9,6 +9,7 @@ Calls only the CPU oracle (oracle/) and the seeded input module.  Usage:
     python tests/golden/make_golden.py serve24q  # ~1 h: first 24-qubit request of the serving trace
     python tests/golden/make_golden.py 20q_pool  # ADAPT pool gradients on the 20-qubit final state
     python tests/golden/make_golden.py 20q_pqe   # PQE residuals of the 20-qubit workload
+    python tests/golden/make_golden.py 20q_qk    # QK matrices (dt 0.5, s 2, r 1) of the 20-qubit Hamiltonian
 
 Each output JSON holds the recipe, the energy, sampled final-state
 amplitudes, and (all but 28q) the full gradient dE/dtheta and dE/dt.
@@ -100,7 +101,26 @@ def main_pqe(name):
     print("wrote", path, f"{time.time() - t0:.0f}s", flush=True)
 
 
+def main_qk(name, dt=0.5, s=2, r=1):
+    """QK overlap and Hamiltonian matrices (Sec. 3.7) of a workload's
+    Hamiltonian from its reference."""
+    from oracle import krylov
+    base = name[:-len("_qk")]
+    t0 = time.time()
+    w, n, occ, (hx, hz, hc, goff), _ = system(base)
+    S, Hm = krylov.qk_matrices(n, occ, hx, hz, hc, dt, s, r, use_core=True)
+    out = dict(workload=base, recipe=w, n_qubits=n, occ_mask=occ, dt=dt, s=s, r=r,
+               S_re=S.real.tolist(), S_im=S.imag.tolist(), H_re=Hm.real.tolist(), H_im=Hm.imag.tolist(),
+               oracle_threads=core.threads(), seconds=time.time() - t0)
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path, f"{time.time() - t0:.0f}s", flush=True)
+
+
 def main(name):
+    if name.endswith("_qk"):
+        return main_qk(name)
     if name.endswith("_pool"):
         return main_pool(name)
     if name.endswith("_pqe"):

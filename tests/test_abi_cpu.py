@@ -122,6 +122,29 @@ def test_gsd_pool_builder_matches_oracle(qf, n_orb):
     assert np.array_equal(kept, np.arange(len(ops)))
 
 
+@pytest.mark.parametrize("kind,n_orb,n_e", [("uccsd", 4, 4), ("uccsd", 7, 7), ("uccsd", 5, 3), ("puccd", 4, 4)])
+def test_excited_determinants_and_denominators_match_oracle(qf, kind, n_orb, n_e):
+    from oracle import pqe
+    det, sign = qf.excited_determinants(kind, n_orb, n_e)
+    excs = an.build(n_orb, n_e, "pduccd" if kind == "puccd" else "uccsd")[0]
+    want = [pqe.excitation_sign((1 << n_e) - 1, c, a) for c, a in excs]
+    assert [(int(s), int(d)) for s, d in zip(sign, det)] == want
+    h, g = qi.integrals(n_orb, n_e, 31)
+    delta = qf.mp_denominators(kind, n_orb, n_e, h, g)
+    assert np.max(np.abs(delta - pqe.mp_denominators(pqe.fock_diagonal(h, g, n_e), excs))) < 1e-13
+
+
+def test_excited_determinants_of_truncated_doubles(qf):
+    from oracle import pqe
+    w = qi.WORKLOADS["28q"]
+    n_d = len(an.excitations(28, 14, singles=False))
+    t_all = qi.amplitudes(n_d, w["seed"], w["t_scale"])
+    det, sign = qf.excited_determinants("uccd_top", 14, 14, t_rank=t_all, top_k=512)
+    excs = an.build(14, 14, "uccd_top", t_all, 512)[0]
+    assert [(int(s), int(d)) for s, d in zip(sign, det)] == [pqe.excitation_sign((1 << 14) - 1, c, a)
+                                                               for c, a in excs]
+
+
 def test_angles_and_chain_rule_match_oracle(qf):
     excs, x, z, c, off, _ = an.build(5, 4)
     terms, eoff, _ = qf.build_paulis("uccsd", 5, 4)
