@@ -141,6 +141,20 @@ int qf_energy(const void *psi, int n_qubits, const qf_term *H, const int64_t *gr
               int64_t n_groups, double *E_out, void *stream);
 
 /*
+ * qf_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same result from the same kernels, with every device table and scratch
+ * array carved from a 16 MiB static device array that the library holds on
+ * each GPU until the process ends (Hamiltonians up to 32 qubits fit; larger
+ * tables give QF_E_SIZE).  The call performs no hipMalloc, hipFree or other
+ * allocating device call.  All calls on one GPU share that array and leave
+ * it holding their tables: calls that overlap on one GPU (two host threads,
+ * two streams) race and must be serialized by the caller.
+ */
+int qf_energy_static(const void *psi, int n_qubits, const qf_term *H, const int64_t *group_off,
+                     int64_t n_groups, double *E_out, void *stream);
+
+/*
  * Energy E(theta) = <Phi|U^dagger H U|Phi> (Sec. 3.1, Eq. (16)) with
  * U from qf_apply_pauli_exp and Phi = |occ_mask>, and its gradient
  * dE_dtheta[k] = dE/dtheta_k = 2 Im <lambda_k|P_k|phi_k> by one reverse

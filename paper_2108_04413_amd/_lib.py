@@ -39,7 +39,7 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_batch_create_arena", "qf_batch_launch", "qf_batch_poll", "qf_batch_collect",
            "qf_mailbox_alloc", "qf_mailbox_free", "qf_batch_mailbox_bytes", "qf_batch_launch_mailbox",
            "qf_plan_set_energy_tile", "qf_plan_info", "qf_plan_set_block_bits", "qf_plan_apply_info",
-           "qf_plan_create_arena", "qf_batch_status", "qf_batch_teams",
+           "qf_plan_create_arena", "qf_energy_static", "qf_batch_status", "qf_batch_teams",
            "qf_batch_resident_grid", "qf_pool_grad", "qf_plan_create_pool", "qf_plan_pool_grad",
            "qf_excited_determinants", "qf_mp_denominators", "qf_pqe_residuals", "qf_plan_pqe_residuals",
            "qf_plan_pqe_solve", "qf_plan_trotter", "qf_plan_qk_matrices")
@@ -68,6 +68,7 @@ _sig = {
     "qf_energy_grad": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "qf_plan_create": [_int, _vp, _i64, _vp, _vp, _i64, _vp],
     "qf_plan_create_arena": [_int, _vp, _i64, _vp, _vp, _i64, _int, _int, _vp, _i64, _vp, _vp, _vp],
+    "qf_energy_static": [_vp, _int, _vp, _vp, _i64, _vp, _vp],
     "qf_plan_destroy": [_vp],
     "qf_plan_apply": [_vp, _vp, _vp, _int, _vp],
     "qf_plan_energy": [_vp, _vp, _vp, _vp],

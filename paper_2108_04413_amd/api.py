@@ -88,6 +88,16 @@ def energy_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarra
     return e.value, g
 
 
+def energy_static(psi, n_qubits: int, H: np.ndarray, group_off: np.ndarray, stream=None) -> float:
+    """qf_energy_static: qf_energy with no device allocation (the library's
+    static scratch holds the tables); calls on one GPU must not overlap."""
+    group_off = np.ascontiguousarray(group_off, dtype=np.int64)
+    e = ctypes.c_double()
+    check(lib.qf_energy_static(ptr(psi), n_qubits, ptr(H), ptr(group_off), len(group_off) - 1, ctypes.byref(e),
+                               stream_handle(stream)), "qf_energy_static")
+    return e.value
+
+
 def pool_grad(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndarray, group_off: np.ndarray,
               pool: np.ndarray, pool_off: np.ndarray, workspace=None, stream=None):
     """qf_pool_grad: (E, g) with g_nu = <Psi|[H, kappa_nu]|Psi> for the pool

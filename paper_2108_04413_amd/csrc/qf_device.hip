@@ -1505,7 +1505,7 @@ struct qf_plan {
 
     // Where the device arrays live.  kOwned: one hipMalloc per array, freed
     // with the plan.  kRegion: bump-allocated (256-byte aligned) from a
-    // caller's region (an arena), never
+    // caller's region (an arena, or the library's static scratch), never
     // freed; uploads go through region_stream.  kMeasure: nothing touches
     // the device; region_used ends as the bytes a kRegion plan would need.
     enum Mem { kOwned, kRegion, kMeasure } mem = kOwned;
@@ -2642,6 +2642,74 @@ extern "C" int qf_energy(const void *psi, int n_qubits, const qf_term *H, const 
         qf_plan P;
         plan_init(P, n_qubits, nullptr, 0, H, group_off, n_groups);
         hipStream_t s = (hipStream_t)stream;
+        launch_energy(P, (const double2 *)psi, P.d_result, s);
+        fetch(E_out, P.d_result, 1, s);
+        return QF_OK;
+    });
+}
+
+namespace qf {
+namespace {
+
+// Device memory of qf_energy_static: every table and scratch array of its
+// one-shot plan is carved from this array, so the call allocates nothing.
+// Each GPU holds its own copy until the process ends; host code must use the
+// per-device address from hipGetSymbolAddress, never the array's name.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex scratch_mu;
+void *scratch_dev[256];  // per device index
+
+void *scratch_address()
+{
+    int dev = 0;
+    QF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 256)
+        raise(QF_E_HIP, "device index " + std::to_string(dev) + " out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            raise(QF_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        scratch_dev[dev] = ptr;
+    }
+    return scratch_dev[dev];
+}
+
+} // namespace
+} // namespace qf
+
+extern "C" int qf_energy_static(const void *psi, int n_qubits, const qf_term *H, const int64_t *group_off,
+                                int64_t n_groups, double *E_out, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!psi || !E_out)
+            return fail(QF_E_ARG, "qf_energy_static: null psi or E_out");
+        if (n_groups < 0)
+            return fail(QF_E_ARG, "qf_energy_static: n_groups < 0");
+        if (n_qubits < 1 || n_qubits > QF_MAX_QUBITS)
+            return fail(QF_E_RANGE, "qf_energy_static: n_qubits=%d out of range", n_qubits);
+        if (n_groups == 0) {
+            *E_out = 0.0;
+            return QF_OK;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        qf_plan P;
+        P.mem = qf_plan::kRegion;
+        P.region = (char *)scratch_address();
+        P.region_cap = kStaticScratchBytes;
+        P.region_stream = s;
+        P.sigma_tables = false;  // energy only
+        try {
+            plan_init(P, n_qubits, nullptr, 0, H, group_off, n_groups);
+        } catch (const Error &e) {
+            if (e.status == QF_E_SIZE)
+                return fail(QF_E_SIZE, "qf_energy_static: the Hamiltonian's device tables exceed the %zu-byte "
+                                       "static scratch", kStaticScratchBytes);
+            throw;
+        }
         launch_energy(P, (const double2 *)psi, P.d_result, s);
         fetch(E_out, P.d_result, 1, s);
         return QF_OK;
