@@ -47,6 +47,7 @@ def lib():
                                       _u64p, _u64p, _dp, ctypes.c_int64, _dp, _dp, _dp]
         L.orc_pool_grad.argtypes = [_dp, _dp, ctypes.c_int, _u64p, _u64p, _dp, _i64p, ctypes.c_int64, _dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -65,6 +66,11 @@ def _f64(a):
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following calls."""
+    lib().orc_set_threads(int(n))
 
 
 def prepare(n: int, occ: int) -> np.ndarray:

@@ -52,6 +52,8 @@ static inline void mul_ik(int k, double re, double im, double *ore, double *oim)
 
 int orc_threads(void) { return omp_get_max_threads(); }
 
+void orc_set_threads(int n) { omp_set_num_threads(n); }
+
 void orc_prepare(double *psi, int n, uint64_t occ)
 {
     int64_t dim = (int64_t)1 << n;
