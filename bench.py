@@ -12,8 +12,16 @@ Algorithmic bytes (S = 2^n * 16 B), counted from the passes executed:
 prepare S (write), each apply pass 2S (read + write), each energy pass S
 (read).
 
-Extra legs: the 20-qubit energy + adjoint gradient (evals/s), and the CPU
-oracle timed on a bounded sample of the 28-qubit step (rank 0, N = 1).
+Extra legs (each with the state bytes of the passes it executes):
+- energy + adjoint gradient at 20 and 24 qubits (evals/s; the 24-qubit step
+  is the second roofline entry);
+- ADAPT pool gradients (Sec. 3.2), PQE residuals (Sec. 3.3) and the QK
+  Trotter basis with its S and H matrices (Sec. 3.7) at 20 qubits;
+- 256 batched instances in one persistent launch vs plain calls;
+- the 10 000-request serving trace (2000 req/s) through continuous batching
+  and through the plain serial path, plus an arrival-rate sweep;
+- the CPU oracle timed on a bounded sample of the 28-qubit step (rank 0,
+  N = 1), with a one-thread sample and the host's triad bandwidth.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -64,7 +72,8 @@ def device_system(qf, qi, name):
         A, aoff, _ = qf.build_paulis("uccsd", w["n_orb"], w["n_elec"])
         t = qi.amplitudes(len(aoff) - 1, w["seed"], w["t_scale"])
     th = qf.ansatz_angles(A, aoff, t)
-    return dict(w=w, n=n, occ=(1 << w["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff, theta=th)
+    return dict(w=w, n=n, n_elec=w["n_elec"], occ=(1 << w["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff,
+                theta=th)
 
 
 def cpu_baseline(qi, sysd, budget_s=20.0):
@@ -107,12 +116,70 @@ def cpu_baseline(qi, sysd, budget_s=20.0):
                       f"{t_used:.1f} s on the host; same algorithmic byte count as the GPU step"}
 
 
+def core_threads():
+    from oracle import core
+    return core.threads()
+
+
+def host_info():
+    """CPU model and thread count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def triad_gbps(n=1 << 25, reps=3):
+    """Host STREAM-style triad a = b + s c over float64 arrays (numpy, one
+    thread), in GB/s of 3 arrays moved; the best of reps."""
+    b = np.ones(n)
+    c = np.full(n, 2.0)
+    a = np.empty(n)
+    best = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        np.multiply(c, 3.0, out=a)
+        np.add(a, b, out=a)
+        dt = time.perf_counter() - t0
+        best = max(best, 3 * 8 * n / dt / 1e9)
+    return best
+
+
+def oracle_group_sample(qf, qi, n_threads, budget_s):
+    """Energy groups 1.. of the first 24-qubit served request's Hamiltonian on
+    its reference state by the oracle's C core with n_threads threads, until
+    budget_s is spent: GB/s of state read (one 256 MiB read per group)."""
+    from oracle import core, hamiltonian as ham
+    r = mix_recipe(qi, 24)
+    h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
+    x, z, c, goff = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
+    before = core.threads()
+    core.set_threads(n_threads)
+    try:
+        psi = core.prepare(24, (1 << 12) - 1)
+        t_used, k = 0.0, 1
+        while t_used < budget_s and k < len(goff) - 1:
+            t0 = time.perf_counter()
+            core.energy(psi, 24, x, z, c, goff[k:k + 2])
+            t_used += time.perf_counter() - t0
+            k += 1
+    finally:
+        core.set_threads(before)
+    return {"threads": n_threads, "workload": "24q served request, energy groups 1..", "groups": k - 1,
+            "seconds": t_used, "GBps": (k - 1) * (1 << 24) * 16 / t_used / 1e9}
+
+
 def instance_from_recipe(qf, qi, r):
     h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
     H, off, _ = qf.build_paulis("hamiltonian", r["n_orb"], r["n_elec"], h, g)
     A, aoff, _ = qf.build_paulis("uccsd", r["n_orb"], r["n_elec"])
     t = qi.amplitudes(len(aoff) - 1, r["seed"], r["t_scale"])
-    return dict(n=2 * r["n_orb"], occ=(1 << r["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff,
+    return dict(n=2 * r["n_orb"], n_elec=r["n_elec"], occ=(1 << r["n_elec"]) - 1, H=H, off=off, A=A, aoff=aoff,
                 theta=qf.ansatz_angles(A, aoff, t))
 
 
@@ -177,9 +244,17 @@ def batched_leg(qf, qi, count=256, reps=2):
             "teams": sorted(set(zip((d["n"] for d in insts), info["team"]))), "grid": info["grid"]}
 
 
-def serving_leg(qf, qi, n_req=200):
-    """The first n_req requests of the 10k Poisson trace (2000 req/s, 12-24
-    qubits): continuous batching vs the plain one-at-a-time path."""
+def _reset(reqs):
+    for r in reqs:
+        r.E = r.grad = r.t_admit = r.t_done = r.error = None
+        r.team, r.solo = 0, False
+
+
+def serving_leg(qf, qi, n_req=10000, plain_req=10000, sweep=(25.0, 50.0, 100.0), sweep_req=200):
+    """The Poisson trace of n_req requests (2000 req/s, 12-24 qubits):
+    continuous batching vs the plain one-at-a-time path on the first
+    plain_req of the same requests; then continuous batching on the first
+    sweep_req requests re-timed to lower arrival rates (context)."""
     from paper_2108_04413_amd import serve
     trace = qi.serving_trace(10000)[:n_req]
     t0 = time.perf_counter()
@@ -189,18 +264,152 @@ def serving_leg(qf, qi, n_req=200):
     st_b = srv.serve(reqs)
     srv.close()
     log(f"serving (continuous batching): {st_b}")
-    plain = serve.make_requests(qf, qi, trace)
+    E_b = [r.E for r in reqs[:plain_req]]
+    plain = reqs[:plain_req]
+    _reset(plain)
     st_p = serve.serve_plain(plain, max(r.n for r in plain))
-    log(f"serving (plain serial): {st_p}")
-    dE = max(abs(a.E - b.E) for a, b in zip(reqs, plain))
+    log(f"serving (plain serial, first {plain_req}): {st_p}")
+    dE = max(abs(a - b.E) for a, b in zip(E_b, plain) if a is not None and b.E is not None)
     mix = {}
     for r in reqs:
         mix[r.n] = mix.get(r.n, 0) + 1
+    rates = []
+    for rate in sweep:
+        sub = reqs[:sweep_req]
+        _reset(sub)
+        arr0 = [r.arrival for r in sub]
+        gaps = qi.serving_trace(sweep_req, rate=rate)  # same draws, arrivals scaled to the rate
+        for r, (t, _) in zip(sub, gaps):
+            r.arrival = float(t)
+        srv = serve.Server(arena_bytes=48 << 30, slots=2, max_wave=64, solo_qubits=serve.SOLO_QUBITS)
+        st = srv.serve(sub)
+        srv.close()
+        for r, a in zip(sub, arr0):
+            r.arrival = a
+        rates.append({"offered_req_per_s": rate, "requests": sweep_req,
+                      **{k: st[k] for k in ("throughput_req_per_s", "latency_ms_p50", "latency_ms_p99", "failed")}})
+        log(f"serving sweep at {rate} req/s: {rates[-1]}")
     return {"requests": n_req, "offered_rate_req_per_s": 2000.0, "qubit_mix": dict(sorted(mix.items())),
             "solo_qubits": serve.SOLO_QUBITS,
-            "continuous_batching": st_b, "plain_serial": st_p,
+            "continuous_batching": st_b, "plain_serial": dict(st_p, requests_replayed=plain_req),
             "throughput_ratio": st_b["throughput_req_per_s"] / st_p["throughput_req_per_s"],
-            "max_abs_dE_batched_vs_plain": dE}
+            "max_abs_dE_batched_vs_plain": dE, "rate_sweep_continuous_batching": rates}
+
+
+def mix_recipe(qi, nq):
+    """The first request of nq qubits in the serving trace."""
+    for _, r in qi.serving_trace(10000):
+        if 2 * r["n_orb"] == nq:
+            return r
+    raise ValueError(nq)
+
+
+def eg_leg(qf, qi, name, reps=5):
+    """Energy + adjoint gradient of one workload on the plan kernels, with
+    the state bytes of the passes executed: prepare S, each forward segment
+    2S, sigma (classes + 1) S read + S write, each sweep segment 4S."""
+    import torch
+    if name == "24q":
+        r = mix_recipe(qi, 24)
+        d = instance_from_recipe(qf, qi, r)
+    else:
+        d = device_system(qf, qi, name)
+    n = d["n"]
+    S = (1 << n) * 16
+    p = qf.Plan(n, d["A"], d["H"], d["off"])
+    ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+    p.energy_grad(d["occ"], d["theta"], ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e, g = p.energy_grad(d["occ"], d["theta"], ws)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    ai, gi = p.apply_info(), p.grad_info()
+    nbytes = S + 2 * S * ai["passes"] + (gi["sigma_passes"] + 2) * S + 4 * S * gi["sweep_passes"]
+    out = {"ms": dt * 1e3, "evals_per_s": 1.0 / dt, "energy": e, "apply_passes": ai["passes"],
+           "sigma_passes": gi["sigma_passes"], "sweep_passes": gi["sweep_passes"], "state_bytes": nbytes,
+           "GBps": nbytes / dt / 1e9, "frac_of_hbm_peak": nbytes / dt / 1e9 / HBM_PEAK_GBS}
+    log(f"energy+grad {name}: {out}")
+    return out, (d, p, ws)
+
+
+def pool_leg(qf, qi, d, p, ws, reps=3):
+    """ADAPT pool gradients (Sec. 3.2) on the state of d: forward, sigma,
+    then one read-only pass (2S) per pool-sweep segment."""
+    import torch
+    n = d["n"]
+    S = (1 << n) * 16
+    pool, poff, _ = qf.build_paulis("gsd_pool", n // 2, 0)
+    Q = qf.PoolPlan(n, pool, poff)
+    p.pool_grad(Q, d["occ"], d["theta"], ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e, g = p.pool_grad(Q, d["occ"], d["theta"], ws)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    ai, gi, qi_ = p.apply_info(), p.grad_info(), Q.grad_info()
+    nbytes = S + 2 * S * ai["passes"] + (gi["sigma_passes"] + 2) * S + 2 * S * qi_["sweep_passes"]
+    out = {"ms": dt * 1e3, "pool_members": len(poff) - 1, "pool_strings": len(pool),
+           "pool_sweep_passes": qi_["sweep_passes"], "state_bytes": nbytes, "GBps": nbytes / dt / 1e9,
+           "max_abs_g": float(np.max(np.abs(g)))}
+    log(f"pool gradients {n}q: {out}")
+    Q.close()
+    return out
+
+
+def pqe_leg(qf, qi, d, p, ws, reps=3):
+    """PQE residuals (Sec. 3.3): forward, sigma, the inverse pass on lambda,
+    a gather: S + 4S per segment pass + sigma."""
+    import torch
+    n = d["n"]
+    S = (1 << n) * 16
+    det, sign = qf.excited_determinants("uccsd", n // 2, d["n_elec"])
+    p.pqe_residuals(d["occ"], d["theta"], det, sign, ws)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e, r = p.pqe_residuals(d["occ"], d["theta"], det, sign, ws)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    ai, gi = p.apply_info(), p.grad_info()
+    nbytes = S + 4 * S * ai["passes"] + (gi["sigma_passes"] + 2) * S
+    out = {"ms": dt * 1e3, "residuals": len(det), "state_bytes": nbytes, "GBps": nbytes / dt / 1e9,
+           "max_abs_r": float(np.max(np.abs(r)))}
+    log(f"PQE residuals {n}q: {out}")
+    return out
+
+
+def qk_leg(qf, qi, name="20q", dt_=0.5, s_=3, r_=1):
+    """QK basis (Sec. 3.7): s Trotter evolutions of r steps over H's strings,
+    s + 1 sigma passes and the S, H inner products."""
+    import torch
+    w, h, g = qi.workload(name)
+    n = 2 * w["n_orb"]
+    S = (1 << n) * 16
+    H, off, _ = qf.build_paulis("hamiltonian", w["n_orb"], w["n_elec"], h, g)
+    p = qf.Plan(n, H, H, off)
+    states = torch.empty((s_ + 2) << n, dtype=torch.complex128, device="cuda")
+    p.qk_matrices((1 << w["n_elec"]) - 1, dt_, s_, r_, states)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Sm, Hm, _ = p.qk_matrices((1 << w["n_elec"]) - 1, dt_, s_, r_, states)
+    dt = time.perf_counter() - t0
+    ai, gi = p.apply_info(), p.grad_info()
+    J = s_ + 1
+    nbytes = J * S + s_ * r_ * 2 * S * ai["passes"] + J * (gi["sigma_passes"] + 2) * S + J * (J + 2) * S
+    from oracle import krylov  # the generalized eigenproblem is the caller's (host)
+    out = {"ms": dt * 1e3, "s": s_, "r": r_, "dt": dt_, "trotter_step_passes": ai["passes"],
+           "hamiltonian_strings": len(H), "state_bytes": nbytes, "GBps": nbytes / dt / 1e9,
+           "qk_lowest_root": krylov.qk_energy(Sm, Hm), "H00": float(Hm[0, 0].real)}
+    log(f"QK {name}: {out}")
+    del states
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -212,6 +421,10 @@ def main():
     ap.add_argument("--no-20q", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the serving trace replayed (default: all 10 000)")
+    ap.add_argument("--plain-requests", type=int, default=10000,
+                    help="of those, requests replayed through the plain serial path")
     ap.add_argument("--calib", action="store_true",
                     help="run one torch copy of one state (4 GiB) first: a plain copy kernel of known "
                          "size for scaling hardware byte counters")
@@ -273,6 +486,7 @@ def main():
             t_step.append(ta + te)
     ms = float(np.mean(t_step))
     value = step_bytes / (ms * 1e-3) / 1e9
+    traffic = profiled_traffic("k_energy_stream", qf.__version__)
     e_ms = float(np.mean(t_energy))
     achieved = energy_bytes / (e_ms * 1e-3) / 1e9
     # the one-pass-per-group energy kernel on the same state, for comparison
@@ -296,27 +510,27 @@ def main():
              "energy_speedup_vs_untiled": e0_ms / e_ms}
 
     if not args.no_20q:
-        log("20q energy + adjoint gradient")
-        s20 = device_system(qf, qi, "20q")
-        p20 = qf.Plan(s20["n"], s20["A"], s20["H"], s20["off"])
-        ws = torch.empty(2 << s20["n"], dtype=torch.complex128, device="cuda")
-        p20.energy_grad(s20["occ"], s20["theta"], ws)
-        torch.cuda.synchronize()
-        reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            e20, g20 = p20.energy_grad(s20["occ"], s20["theta"], ws)
-        dt = (time.perf_counter() - t0) / reps
-        extra.update({"energy_grad_20q_ms": dt * 1e3, "energy_grad_20q_evals_per_s": 1.0 / dt,
-                      "energy_20q": e20})
+        eg = {}
+        for name in ("20q", "24q"):
+            res, (d, p, ws) = eg_leg(qf, qi, name)
+            eg[name] = res
+            if name == "20q":
+                extra["pool_gradients_20q"] = pool_leg(qf, qi, d, p, ws)
+                extra["pqe_residuals_20q"] = pqe_leg(qf, qi, d, p, ws)
+            p.close()
+            del ws
+            torch.cuda.empty_cache()
+        extra["energy_grad"] = eg
+        extra["qk_20q"] = qk_leg(qf, qi, "20q")
 
     if not args.no_batch:
         log("batched leg (256 instances, 12-22 qubits)")
         extra["batched_256"] = batched_leg(qf, qi)
 
     if not args.no_serve:
-        log("serving leg (first 200 requests of the 10k trace)")
-        extra["serving_200"] = serving_leg(qf, qi)
+        log(f"serving leg ({args.serve_requests} requests of the 10k trace)")
+        extra["serving"] = serving_leg(qf, qi, n_req=args.serve_requests,
+                                       plain_req=min(args.serve_requests, args.plain_requests))
 
     line = {"metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -327,13 +541,27 @@ def main():
                                    "energy (tiled passes)",
                        "n_qubits": n, "state_bytes": S, "step_algorithmic_bytes": step_bytes},
             "roofline": {"bound": "hbm", "kernel": "k_energy_stream", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": profiled_traffic("k_energy_stream", qf.__version__),
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                         "achieved_from_counters": None if traffic is None else traffic / (e_ms * 1e-3) / 1e9,
                          "bytes_per_launch": energy_bytes, "launch_ms": e_ms},
             "extra": extra}
+    if "energy_grad" in extra:
+        r24 = extra["energy_grad"]["24q"]
+        line["roofline_energy_grad"] = {
+            "bound": "hbm", "kernel": "energy + gradient step at 24 qubits (k_apply_block, k_sigma_tiled, "
+                                      "k_adjoint_block, k_grad_reduce)",
+            "achieved": r24["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r24["GBps"] / HBM_PEAK_GBS,
+            "traffic": None, "bytes_per_step": r24["state_bytes"], "step_ms": r24["ms"]}
     if not args.no_cpu:
         log("cpu baseline (oracle on a bounded sample)")
-        line["cpu_baseline"] = cpu_baseline(qi, s28)
+        cb = cpu_baseline(qi, s28)
+        model, nthreads = host_info()
+        one = oracle_group_sample(qf, qi, 1, 5.0)
+        allt = oracle_group_sample(qf, qi, core_threads(), 5.0)
+        cb.update({"host_cpu": model, "host_threads": nthreads, "one_thread_24q": one, "all_threads_24q": allt,
+                   "host_triad_GBps_one_thread": triad_gbps()})
+        log(f"cpu baseline: {cb}")
+        line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
 
 

@@ -229,6 +229,11 @@ int qf_plan_info(const qf_plan *plan, int *tile_bits, int64_t *classes, int64_t 
  * energy tile per qubit count when its table matches the device.
  */
 int qf_plan_set_block_bits(qf_plan *plan, int block_bits);
+/* passes over the state of the plan's sigma (lambda = H psi: one per class
+ * of 2^11-amplitude tiles from 12 qubits up, else one per group, each
+ * reading psi) and of its reverse sweep (one per segment, or per run below
+ * 10 block bits) */
+int qf_plan_grad_info(const qf_plan *plan, int64_t *sigma_passes, int64_t *sweep_passes);
 /* block bits, number of fused runs, passes over the state per application */
 int qf_plan_apply_info(const qf_plan *plan, int *block_bits, int64_t *runs, int64_t *passes);
 /* lambda <- H psi and *E_out = Re <psi|lambda> (device states, host E_out).
@@ -317,6 +322,49 @@ int qf_plan_pqe_solve(qf_plan *plan, uint64_t occ_mask, const qf_term *A, const 
 int qf_plan_trotter(qf_plan *plan, void *psi, double t, int r, void *stream);
 int qf_plan_qk_matrices(qf_plan *plan, uint64_t occ_mask, double dt, int s, int r, void *states,
                         double *S_out, double *H_out, void *stream);
+
+/*
+ * qf_excitations: the operators of each excitation of an ansatz kind, in
+ * qf_build_paulis order: ops[4 mu .. 4 mu + 3] = (c0, c1, a0, a1) for
+ * tau_mu = a+_{c0} a+_{c1} a_{a0} a_{a1} (spin orbitals; -1 in the unused
+ * slots of a single).  With ops == NULL only *n_out is written.
+ */
+int qf_excitations(int kind, int n_orb, int n_elec, const double *t_rank, int64_t top_k, int32_t *ops,
+                   int64_t cap, int64_t *n_out);
+
+/*
+ * Particle-number and S_z restricted state vector (the restriction Sec. 6
+ * names for going past ~24 qubits).  Only determinants with n_alpha alpha
+ * and n_beta beta electrons are stored: an alpha (beta) string is the
+ * n_orb-bit mask of the occupied alpha (beta) orbitals (spin orbital 2j is
+ * alpha, 2j + 1 beta of spatial orbital j), strings of one spin are ranked
+ * in increasing order, and determinant (a, b) is element
+ * rank(a) * D_beta + rank(b) of a complex128 device vector of
+ * dim = C(n_orb, n_alpha) C(n_orb, n_beta) entries (caller-owned).
+ * qf_sector_create: n_orb <= 20; exc (4 ints per excitation, as from
+ *   qf_excitations; may be NULL with n_exc = 0) for the dUCC factors of
+ *   Sec. 3.1 Eq. (ducc), each conserving N_alpha and N_beta; H grouped by flip
+ *   mask as for qf_energy (may be NULL with n_groups = 0).  Host arrays are
+ *   read during the call; the sector holds its own device tables.
+ * qf_sector_info: dim, D_alpha, D_beta, and the number of Hamiltonian groups
+ *   that can map sector determinants onto sector determinants.
+ * qf_sector_prepare: psi = |occ_mask> (a spin-orbital bit string in the
+ *   sector).
+ * qf_sector_apply: psi <- prod_mu exp(t_mu kappa_mu) psi (the first
+ *   excitation acts first; inverse != 0 applies the adjoint in reverse):
+ *   each determinant D with tau_mu D = s D' is rotated with D',
+ *   D -> cos t D + s sin t D'.  t: host, one amplitude per excitation.
+ * qf_sector_energy: <psi|H|psi> as the grouped Pauli sum of Eq. (17) over
+ *   pairs of sector determinants (host E_out; the stream is synchronized).
+ */
+typedef struct qf_sector qf_sector;
+int qf_sector_create(int n_orb, int n_alpha, int n_beta, const int32_t *exc, int64_t n_exc, const qf_term *H,
+                     const int64_t *group_off, int64_t n_groups, qf_sector **out);
+int qf_sector_info(const qf_sector *sector, int64_t *dim, int64_t *d_alpha, int64_t *d_beta, int64_t *groups);
+int qf_sector_prepare(qf_sector *sector, void *psi, uint64_t occ_mask, void *stream);
+int qf_sector_apply(qf_sector *sector, void *psi, const double *t, int inverse, void *stream);
+int qf_sector_energy(qf_sector *sector, const void *psi, double *E_out, void *stream);
+int qf_sector_destroy(qf_sector *sector);
 
 /*
  * Batches: energy and adjoint gradient of many instances (different

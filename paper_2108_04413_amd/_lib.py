@@ -42,7 +42,9 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_plan_create_arena", "qf_energy_static", "qf_batch_status", "qf_batch_teams",
            "qf_batch_resident_grid", "qf_pool_grad", "qf_plan_create_pool", "qf_plan_pool_grad",
            "qf_excited_determinants", "qf_mp_denominators", "qf_pqe_residuals", "qf_plan_pqe_residuals",
-           "qf_plan_pqe_solve", "qf_plan_trotter", "qf_plan_qk_matrices")
+           "qf_plan_pqe_solve", "qf_plan_trotter", "qf_plan_qk_matrices",
+           "qf_plan_grad_info", "qf_excitations", "qf_sector_create", "qf_sector_info", "qf_sector_prepare",
+           "qf_sector_apply", "qf_sector_energy", "qf_sector_destroy")
 
 
 class QFError(RuntimeError):
@@ -84,6 +86,14 @@ _sig = {
     "qf_pool_grad": [_int, _u64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp],
     "qf_plan_create_pool": [_int, _vp, _vp, _i64, _vp],
     "qf_plan_trotter": [_vp, _vp, _dbl, _int, _vp],
+    "qf_plan_grad_info": [_vp, _vp, _vp],
+    "qf_excitations": [_int, _int, _int, _vp, _i64, _vp, _i64, _vp],
+    "qf_sector_create": [_int, _int, _int, _vp, _i64, _vp, _vp, _i64, _vp],
+    "qf_sector_info": [_vp, _vp, _vp, _vp, _vp],
+    "qf_sector_prepare": [_vp, _vp, _u64, _vp],
+    "qf_sector_apply": [_vp, _vp, _vp, _int, _vp],
+    "qf_sector_energy": [_vp, _vp, _vp, _vp],
+    "qf_sector_destroy": [_vp],
     "qf_plan_qk_matrices": [_vp, _u64, _dbl, _int, _int, _vp, _vp, _vp, _vp],
     "qf_excited_determinants": [_int, _int, _int, _vp, _i64, _vp, _vp, _i64, _vp],
     "qf_mp_denominators": [_int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _vp],

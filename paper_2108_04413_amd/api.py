@@ -160,6 +160,60 @@ def pqe_residuals(n_qubits: int, occ_mask: int, A: np.ndarray, theta, H: np.ndar
     return e.value, r
 
 
+def excitations(kind: str, n_orb: int, n_elec: int, t_rank=None, top_k: int = 0) -> np.ndarray:
+    """qf_excitations: int32 [n_par, 4] rows (c0, c1, a0, a1) of
+    tau = a+_c0 a+_c1 a_a0 a_a1 (-1 where a single has no second operator)."""
+    t_rank = _f64(t_rank)
+    n = ctypes.c_int64()
+    check(lib.qf_excitations(KINDS[kind], n_orb, n_elec, ptr(t_rank), int(top_k), None, 0, ctypes.byref(n)),
+          "qf_excitations(size)")
+    ops = np.zeros((n.value, 4), dtype=np.int32)
+    check(lib.qf_excitations(KINDS[kind], n_orb, n_elec, ptr(t_rank), int(top_k), ptr(ops), n.value,
+                             ctypes.byref(n)), "qf_excitations")
+    return ops
+
+
+class Sector:
+    """qf_sector_*: the (N_alpha, N_beta) restricted state vector.  States are
+    complex128 tensors of `dim` entries (alpha-string rank major)."""
+
+    def __init__(self, n_orb: int, n_alpha: int, n_beta: int, exc=None, H=None, group_off=None):
+        self.n_orb = n_orb
+        self._exc = None if exc is None else np.ascontiguousarray(exc, dtype=np.int32)
+        self._goff = None if group_off is None else np.ascontiguousarray(group_off, dtype=np.int64)
+        self._H = H
+        ne = 0 if self._exc is None else len(self._exc)
+        G = 0 if self._goff is None else len(self._goff) - 1
+        h = ctypes.c_void_p()
+        check(lib.qf_sector_create(n_orb, n_alpha, n_beta, ptr(self._exc), ne, ptr(H), ptr(self._goff), G,
+                                   ctypes.byref(h)), "qf_sector_create")
+        self._h = h
+        d, da, db, g = (ctypes.c_int64() for _ in range(4))
+        check(lib.qf_sector_info(h, ctypes.byref(d), ctypes.byref(da), ctypes.byref(db), ctypes.byref(g)),
+              "qf_sector_info")
+        self.dim, self.d_alpha, self.d_beta, self.groups = d.value, da.value, db.value, g.value
+
+    def close(self, _destroy=lib.qf_sector_destroy):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def prepare(self, psi, occ_mask: int, stream=None) -> None:
+        check(lib.qf_sector_prepare(self._h, ptr(psi), int(occ_mask), stream_handle(stream)), "qf_sector_prepare")
+
+    def apply(self, psi, t, inverse: bool = False, stream=None) -> None:
+        t = _f64(t)
+        check(lib.qf_sector_apply(self._h, ptr(psi), ptr(t), int(inverse), stream_handle(stream)), "qf_sector_apply")
+
+    def energy(self, psi, stream=None) -> float:
+        e = ctypes.c_double()
+        check(lib.qf_sector_energy(self._h, ptr(psi), ctypes.byref(e), stream_handle(stream)), "qf_sector_energy")
+        return e.value
+
+
 class PoolPlan:
     """qf_plan_create_pool: device tables of an ADAPT operator pool."""
 
@@ -180,6 +234,12 @@ class PoolPlan:
         check(lib.qf_plan_apply_info(self._h, ctypes.byref(bb), ctypes.byref(r), ctypes.byref(ps)),
               "qf_plan_apply_info")
         return {"block_bits": bb.value, "runs": r.value, "passes": ps.value}
+
+    def grad_info(self) -> dict:
+        """Read-only passes of the pool sweep."""
+        b = ctypes.c_int64()
+        check(lib.qf_plan_grad_info(self._h, None, ctypes.byref(b)), "qf_plan_grad_info")
+        return {"sweep_passes": b.value}
 
     def close(self, _destroy=lib.qf_plan_destroy):
         if getattr(self, "_h", None):
@@ -283,6 +343,13 @@ class Plan:
         ps = ctypes.c_int64()
         check(lib.qf_plan_info(self._h, ctypes.byref(tb), ctypes.byref(cl), ctypes.byref(ps)), "qf_plan_info")
         return {"tile_bits": tb.value, "classes": cl.value, "energy_passes": ps.value}
+
+    def grad_info(self) -> dict:
+        """Passes over the state of sigma and of the reverse sweep."""
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        check(lib.qf_plan_grad_info(self._h, ctypes.byref(a), ctypes.byref(b)), "qf_plan_grad_info")
+        return {"sigma_passes": a.value, "sweep_passes": b.value}
 
     def set_block_bits(self, block_bits: int) -> None:
         """0: one pass per fused run; 6-12: runs applied in LDS sub-cubes of 2^B amplitudes."""

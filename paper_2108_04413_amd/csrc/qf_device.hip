@@ -2755,6 +2755,17 @@ extern "C" int qf_plan_info(const qf_plan *P, int *tile_bits, int64_t *classes, 
     return QF_OK;
 }
 
+extern "C" int qf_plan_grad_info(const qf_plan *P, int64_t *sigma_passes, int64_t *sweep_passes)
+{
+    if (!P)
+        return fail(QF_E_ARG, "qf_plan_grad_info: plan is NULL");
+    if (sigma_passes)
+        *sigma_passes = P->G == 0 ? 0 : P->n_sclasses ? (int64_t)P->n_sclasses : (int64_t)P->G;
+    if (sweep_passes)
+        *sweep_passes = P->adj_bits ? (int64_t)P->asegs.size() : (int64_t)P->runs.size();
+    return QF_OK;
+}
+
 extern "C" int qf_plan_set_block_bits(qf_plan *P, int block_bits)
 {
     return guarded([&]() -> int {

@@ -358,13 +358,20 @@ class Server:
             return self.solo_qubits is not None and r.n >= self.solo_qubits
 
         self.resident_grid = resident_grid()
-        for r in requests:
+
+        def size(r):
             if not r.footprint and r.error is None:
                 try:
                     r.footprint = (solo_footprint(r) if is_solo(r)
                                    else footprint([r], self.team, self.share, len(self.streams)))
                 except QFError as e:  # an invalid request is rejected at its arrival
                     r.error = f"rejected: {e}"
+
+        # the size queries are host work of the library (they release the
+        # interpreter lock): taken before the replay, 16 at a time
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            list(ex.map(size, requests))
+        for r in requests:
             if r.footprint > self.arena.nbytes:
                 raise ValueError(f"request {r.rid} needs {r.footprint} bytes, arena has {self.arena.nbytes}")
         pending, pending_solo = [], []
@@ -447,17 +454,19 @@ def serve_plain(requests, max_qubits: int, arena_bytes: int | None = None):
     request's plan tables and states in one preallocated arena (no device
     allocation per request)."""
     import torch
-    need = max(_align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off)) + 2 * (1 << r.n) * 16
-               for r in requests) if arena_bytes is None else int(arena_bytes)
+    # plan sizes are taken before the replay, as the server takes footprints
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        sizes = list(ex.map(lambda r: _align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off)), requests))
+    need = max(pb + 2 * (1 << r.n) * 16 for pb, r in zip(sizes, requests)) if arena_bytes is None \
+        else int(arena_bytes)
     arena = Arena(need)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    for r in requests:
+    for r, pb in zip(requests, sizes):
         now = time.perf_counter() - t0
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.t_admit = time.perf_counter() - t0
-        pb = _align(api.Plan.arena_bytes(r.n, r.A, r.H, r.off))
         try:
             plan = api.Plan(r.n, r.A, r.H, r.off, arena=(arena.base, pb), stream=stream)
             try:
