@@ -37,11 +37,13 @@ def build(verbose: bool = True) -> str:
     dev_o = os.path.join(OUT_DIR, "qf_device.o")
     bat_o = os.path.join(OUT_DIR, "qf_batch.o")
     bld_o = os.path.join(OUT_DIR, "qf_builder.o")
+    sec_o = os.path.join(OUT_DIR, "qf_sector.o")
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "qf_device.hip"), "-o", dev_o])
     _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "qf_batch.hip"), "-o", bat_o])
+    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "qf_sector.hip"), "-o", sec_o])
     _run(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, "qf_builder.cpp"), "-o", bld_o])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, dev_o, bat_o, bld_o])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, dev_o, bat_o, sec_o, bld_o])
     os.replace(tmp, LIB)
     return LIB
 

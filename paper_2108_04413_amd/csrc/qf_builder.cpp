@@ -375,6 +375,33 @@ extern "C" int qf_excited_determinants(int kind, int n_orb, int n_elec, const do
     });
 }
 
+extern "C" int qf_excitations(int kind, int n_orb, int n_elec, const double *t_rank, int64_t top_k, int32_t *ops,
+                              int64_t cap, int64_t *n_out)
+{
+    return guarded([&]() -> int {
+        if (kind < QF_UCCSD || kind > QF_GSD_POOL)
+            return fail(QF_E_ARG, "qf_excitations: not an ansatz kind: %d", kind);
+        if (n_orb < 1 || 2 * n_orb > 64 || n_elec < 0 || n_elec > 2 * n_orb)
+            return fail(QF_E_RANGE, "qf_excitations: n_orb=%d n_elec=%d out of range", n_orb, n_elec);
+        if (!n_out || (kind == QF_UCCD_TOP && (!t_rank || top_k < 0)))
+            return fail(QF_E_ARG, "qf_excitations: bad arguments");
+        const std::vector<Excitation> ex = ansatz_excitations(kind, n_orb, n_elec, t_rank, top_k);
+        *n_out = (int64_t)ex.size();
+        if (!ops)
+            return QF_OK;
+        if (cap < *n_out)
+            return fail(QF_E_SIZE, "qf_excitations: need %lld entries", (long long)*n_out);
+        for (size_t m = 0; m < ex.size(); m++) {
+            int32_t *o = ops + 4 * m;
+            o[0] = ex[m].cre[0];
+            o[1] = ex[m].ncre > 1 ? ex[m].cre[1] : -1;
+            o[2] = ex[m].ann[0];
+            o[3] = ex[m].ncre > 1 ? ex[m].ann[1] : -1;
+        }
+        return QF_OK;
+    });
+}
+
 extern "C" int qf_mp_denominators(int kind, int n_orb, int n_elec, const double *h, const double *g,
                                   const double *t_rank, int64_t top_k, double *delta, int64_t cap, int64_t *n_out)
 {
