@@ -15,6 +15,8 @@ prepare S (write), each apply pass 2S (read + write), each energy pass S
 Extra legs (each with the state bytes of the passes it executes):
 - energy + adjoint gradient at 20 and 24 qubits (evals/s; the 24-qubit step
   is the second roofline entry);
+- the 28-qubit workload in the particle-number / S_z restricted state
+  vector (and a 32-qubit restricted reference energy);
 - ADAPT pool gradients (Sec. 3.2), PQE residuals (Sec. 3.3) and the QK
   Trotter basis with its S and H matrices (Sec. 3.7) at 20 qubits;
 - 256 batched instances in one persistent launch vs plain calls;
@@ -384,6 +386,73 @@ def pqe_leg(qf, qi, d, p, ws, reps=3):
     return out
 
 
+def sector_pairs(n_orb, na, nb, H, off):
+    """Sum over the groups kept by the sector of the sector determinants whose
+    partner under the group's flips is in the sector (exact counts)."""
+    from math import comb
+    tot = 0
+    for g in range(len(off) - 1):
+        x = int(H["x"][off[g]])
+        ka = bin(sum(((x >> (2 * j)) & 1) << j for j in range(n_orb))).count("1")
+        kb = bin(sum(((x >> (2 * j + 1)) & 1) << j for j in range(n_orb))).count("1")
+        if ka % 2 or kb % 2:
+            continue
+        fa = comb(ka, ka // 2) * comb(n_orb - ka, na - ka // 2)
+        fb = comb(kb, kb // 2) * comb(n_orb - kb, nb - kb // 2)
+        tot += fa * fb
+    return tot
+
+
+def sector_leg(qf, qi, s28, e28):
+    """The 28-qubit workload in the (7, 7) sector: reference, the 512
+    truncated-UCCD factors as determinant-pair rotations, the energy; and
+    the reference energy of a 32-qubit (8, 8) sector."""
+    import torch
+    w, h, g = qi.workload("28q")
+    n_d = len(qf.excitations("uccd", 14, 14))
+    t_all = qi.amplitudes(n_d, w["seed"], w["t_scale"])
+    _, _, kept = qf.build_paulis("uccd_top", 14, 14, t_rank=t_all, top_k=w["top_k"])
+    ops = qf.excitations("uccd_top", 14, 14, t_rank=t_all, top_k=w["top_k"])
+    S = qf.Sector(14, 7, 7, ops, s28["H"], s28["off"])
+    psi = torch.empty(S.dim, dtype=torch.complex128, device="cuda")
+    S.prepare(psi, s28["occ"])
+    S.apply(psi, t_all[kept])
+    S.energy(psi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.prepare(psi, s28["occ"])
+    S.apply(psi, t_all[kept])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e = S.energy(psi)
+    t2 = time.perf_counter()
+    pairs = sector_pairs(14, 7, 7, s28["H"], s28["off"])
+    ebytes = 16 * (S.dim + pairs)
+    out = {"dim": S.dim, "state_MiB": S.dim * 16 / 2 ** 20, "groups": S.groups, "excitations": len(ops),
+           "prepare_apply_ms": (t1 - t0) * 1e3, "energy_ms": (t2 - t1) * 1e3, "energy": e,
+           "abs_dE_vs_full_space": abs(e - e28), "energy_bytes": ebytes, "energy_GBps": ebytes / (t2 - t1) / 1e9}
+    del psi
+    S.close()
+    torch.cuda.empty_cache()
+    h, g = qi.integrals(16, 16, 1132)
+    H, off, _ = qf.build_paulis("hamiltonian", 16, 16, h, g)
+    S = qf.Sector(16, 8, 8, None, H, off)
+    psi = torch.empty(S.dim, dtype=torch.complex128, device="cuda")
+    S.prepare(psi, (1 << 16) - 1)
+    t0 = time.perf_counter()
+    e32 = S.energy(psi)
+    t1 = time.perf_counter()
+    pairs = sector_pairs(16, 8, 8, H, off)
+    out["sector_32q"] = {"dim": S.dim, "state_GiB": S.dim * 16 / 2 ** 30, "groups": S.groups,
+                         "energy_ms": (t1 - t0) * 1e3, "energy_reference": e32,
+                         "energy_GBps": 16 * (S.dim + pairs) / (t1 - t0) / 1e9}
+    del psi
+    S.close()
+    torch.cuda.empty_cache()
+    log(f"sector: {out}")
+    return out
+
+
 def qk_leg(qf, qi, name="20q", dt_=0.5, s_=3, r_=1):
     """QK basis (Sec. 3.7): s Trotter evolutions of r steps over H's strings,
     s + 1 sigma passes and the S, H inner products."""
@@ -421,6 +490,7 @@ def main():
     ap.add_argument("--no-20q", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sector", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving trace replayed (default: all 10 000)")
     ap.add_argument("--plain-requests", type=int, default=10000,
@@ -499,6 +569,7 @@ def main():
     log(f"untiled energy (one pass per group): {e0_ms:.1f} ms, E = {E0:.12f}")
     del psi
     torch.cuda.empty_cache()
+    sector = None if args.no_sector else sector_leg(qf, qi, s28, E)
 
     extra = {"energy_28q": E, "apply_ms": float(np.mean(t_apply)), "energy_ms": e_ms,
              "apply_passes": passes, "apply_runs": ainfo["runs"], "apply_block_bits": ainfo["block_bits"],
@@ -508,6 +579,8 @@ def main():
              "energy_untiled_ms": e0_ms, "energy_untiled_E": E0,
              "energy_untiled_GBps": G * S / (e0_ms * 1e-3) / 1e9,
              "energy_speedup_vs_untiled": e0_ms / e_ms}
+    if sector is not None:
+        extra["sector_28q"] = sector
 
     if not args.no_20q:
         eg = {}

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define QF_MAX_QUBITS 32
+#define QF_MAX_QUBITS 30 /* full-space states: 2^30 amplitudes = 16 GiB (tested) */
 
 typedef struct qf_term {
     uint64_t x; /* flip mask: qubits carrying X or Y */
@@ -145,7 +145,7 @@ int qf_energy(const void *psi, int n_qubits, const qf_term *H, const int64_t *gr
  * graph capture, tight serving loops, hosts that forbid hipMalloc): the
  * same result from the same kernels, with every device table and scratch
  * array carved from a 16 MiB static device array that the library holds on
- * each GPU until the process ends (Hamiltonians up to 32 qubits fit; larger
+ * each GPU until the process ends (Hamiltonians up to 30 qubits fit; larger
  * tables give QF_E_SIZE).  The call performs no hipMalloc, hipFree or other
  * allocating device call.  All calls on one GPU share that array and leave
  * it holding their tables: calls that overlap on one GPU (two host threads,

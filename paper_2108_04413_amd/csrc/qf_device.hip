@@ -1765,7 +1765,7 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
                int64_t G, int block_bits = -1, int energy_tile = -1)
 {
     if (n < 1 || n > QF_MAX_QUBITS)
-        raise(QF_E_RANGE, "n_qubits=" + std::to_string(n) + " out of range [1, 32]");
+        raise(QF_E_RANGE, "n_qubits=" + std::to_string(n) + " out of range [1, " + std::to_string(QF_MAX_QUBITS) + "]");
     if (K < 0 || G < 0)
         raise(QF_E_ARG, "negative term or group count");
     if ((K > 0 && !A) || (G > 0 && (!H || !goff)))
@@ -2593,7 +2593,7 @@ extern "C" int qf_prepare_state(void *psi, int n_qubits, uint64_t occ_mask, void
         if (!psi)
             return fail(QF_E_ARG, "qf_prepare_state: psi is NULL");
         if (n_qubits < 1 || n_qubits > QF_MAX_QUBITS)
-            return fail(QF_E_RANGE, "qf_prepare_state: n_qubits=%d out of range [1, 32]", n_qubits);
+            return fail(QF_E_RANGE, "qf_prepare_state: n_qubits=%d out of range [1, %d]", n_qubits, QF_MAX_QUBITS);
         if (occ_mask >> n_qubits)
             return fail(QF_E_RANGE, "qf_prepare_state: occ_mask has a bit >= n_qubits");
         launch_prepare((double2 *)psi, n_qubits, occ_mask, (hipStream_t)stream);

@@ -206,6 +206,7 @@ def test_device_calls_reject_bad_arguments_before_gpu(qf):
     assert lib.qf_prepare_state(None, 8, 3, None) == -1
     assert lib.qf_prepare_state(dummy, 0, 0, None) == -2
     assert lib.qf_prepare_state(dummy, 33, 0, None) == -2
+    assert lib.qf_prepare_state(dummy, 31, 0, None) == -2  # above the tested 30 qubits
     assert lib.qf_prepare_state(dummy, 8, 1 << 8, None) == -2
     assert lib.qf_apply_pauli_exp(dummy, 8, bad.ctypes.data, th.ctypes.data, 1, 0, None) == -2
     assert lib.qf_apply_pauli_exp(dummy, 8, bad.ctypes.data, th.ctypes.data, -1, 0, None) == -1

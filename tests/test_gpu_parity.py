@@ -328,6 +328,39 @@ def test_28q_hf_energy_closed_form(qf):
     torch.cuda.empty_cache()
 
 
+def test_30q_reference_energy_and_identity_ansatz(qf):
+    """30 qubits (16 GiB state, the largest the library accepts): the
+    closed-form Hartree-Fock energy through the streaming energy kernel, and
+    the blocked apply with all angles zero leaving the reference exactly."""
+    h, g = qi.integrals(15, 15, 1130)
+    H, off, _ = qf.build_paulis("hamiltonian", 15, 15, h, g)
+    A, aoff, _ = qf.build_paulis("uccd", 15, 15)
+    A = A[: int(aoff[64])]  # the first 64 doubles
+    n, occ = 30, (1 << 15) - 1
+    psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    plan = qf.Plan(n, A, H, off)
+    qf.prepare_state(psi, n, occ)
+    plan.apply(psi, np.zeros(len(A)))
+    # open shell: 8 alpha (orbitals 0..7), 7 beta (orbitals 0..6)
+    occ_a, occ_b = list(range(8)), list(range(7))
+    e_cf = sum(h[i, i] for i in occ_a) + sum(h[i, i] for i in occ_b)
+    for P in occ_a:
+        for Q in occ_a:
+            e_cf += 0.5 * (g[P, P, Q, Q] - g[P, Q, Q, P])
+    for P in occ_b:
+        for Q in occ_b:
+            e_cf += 0.5 * (g[P, P, Q, Q] - g[P, Q, Q, P])
+    for P in occ_a:
+        for Q in occ_b:
+            e_cf += g[P, P, Q, Q]
+    assert plan.energy(psi) == pytest.approx(e_cf, abs=E_TOL)
+    # the reference amplitude and a sample elsewhere are untouched
+    assert complex(psi[occ].item()) == 1.0
+    assert float(torch.max(torch.abs(psi[occ + 1: occ + 1 + (1 << 20)]))) == 0.0
+    del psi
+    torch.cuda.empty_cache()
+
+
 def test_28q_energy_vs_golden(qf):
     gold = _golden("28q")
     w, n, occ, H, off, A, aoff, th = _build_device_system(qf, "28q")
