@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -19,9 +20,20 @@
 
 namespace qf {
 
+// Fault injection for tests of the error paths: with the environment variable
+// QF_INJECT_ALLOC_FAIL=1 every device allocation of the library fails with
+// QF_E_NOMEM (read at each allocation, so a test can switch it on and off).
+inline bool alloc_failure_injected()
+{
+    const char *v = std::getenv("QF_INJECT_ALLOC_FAIL");
+    return v && v[0] == '1';
+}
+
 template <class T> T *dev_alloc(size_t count)
 {
     void *p = nullptr;
+    if (alloc_failure_injected())
+        raise(QF_E_NOMEM, "hipMalloc: failure injected by QF_INJECT_ALLOC_FAIL");
     if (count == 0)
         count = 1;
     hipError_t e = hipMalloc(&p, count * sizeof(T));

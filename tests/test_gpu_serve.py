@@ -184,3 +184,33 @@ def test_solo_lane_failure_and_invalid_request_are_isolated(qf, monkeypatch):
         e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
         assert r.E == pytest.approx(e_o, abs=1e-10)
         assert np.max(np.abs(r.grad - g_o)) < 1e-9
+
+
+def test_injected_allocation_failure_and_allocation_free_serving(qf, monkeypatch):
+    """QF_INJECT_ALLOC_FAIL=1 makes every device allocation of the library
+    fail: plan and batch creation report QF_E_NOMEM; the server, whose arena
+    and mailboxes exist before the replay, serves a mixed trace (batched
+    waves and the solo lane) without a single device allocation."""
+    from paper_2108_04413_amd import serve
+    tr = [(0.0, dict(n_orb=9, n_elec=9, seed=7200, t_scale=0.1))] + \
+         [(1e-4 * j, dict(n_orb=6, n_elec=6, seed=7201 + j, t_scale=0.1)) for j in range(6)]
+    reqs = serve.make_requests(qf, qi, tr)
+    r = reqs[1]
+    monkeypatch.setenv("QF_INJECT_ALLOC_FAIL", "1")
+    with pytest.raises(qf.QFError) as ei:
+        qf.Plan(r.n, r.A, r.H, r.off)
+    assert ei.value.status == -3 and "injected" in str(ei.value)
+    with pytest.raises(qf.QFError) as ei:
+        qf.Batch([dict(n=r.n, occ=r.occ, A=r.A, H=r.H, off=r.off)])
+    assert ei.value.status == -3
+    srv = serve.Server(arena_bytes=1 << 30, slots=2, max_wave=8, solo_qubits=18)
+    st = srv.serve(reqs)
+    srv.close()
+    assert st["completed"] == 7 and st["solo_requests"] == 1
+    monkeypatch.delenv("QF_INJECT_ALLOC_FAIL")
+    for r in (reqs[0], reqs[1]):
+        e_o, g_o = core.energy_grad(r.n, r.occ, r.A["x"], r.A["z"], r.theta, r.H["x"], r.H["z"], r.H["c"])
+        assert r.E == pytest.approx(e_o, abs=1e-10)
+        assert np.max(np.abs(r.grad - g_o)) < 1e-9
+    p = qf.Plan(r.n, r.A, r.H, r.off)  # allocation works again
+    p.close()
