@@ -405,7 +405,8 @@ def sector_pairs(n_orb, na, nb, H, off):
 
 def sector_leg(qf, qi, s28, e28):
     """The 28-qubit workload in the (7, 7) sector: reference, the 512
-    truncated-UCCD factors as determinant-pair rotations, the energy; and
+    truncated-UCCD factors as determinant-pair rotations, the energy; the
+    energy + dE/dt of the 24-qubit served request in its (6, 6) sector; and
     the reference energy of a 32-qubit (8, 8) sector."""
     import torch
     w, h, g = qi.workload("28q")
@@ -434,6 +435,23 @@ def sector_leg(qf, qi, s28, e28):
     del psi
     S.close()
     torch.cuda.empty_cache()
+    # energy + gradient (dE/dt per excitation) of the 24-qubit served request
+    r = mix_recipe(qi, 24)
+    d = instance_from_recipe(qf, qi, r)
+    ops = qf.excitations("uccsd", r["n_orb"], r["n_elec"])
+    t24 = qi.amplitudes(len(ops), r["seed"], r["t_scale"])
+    S = qf.Sector(r["n_orb"], (r["n_elec"] + 1) // 2, r["n_elec"] // 2, ops, d["H"], d["off"])
+    ws = torch.empty(2 * S.dim, dtype=torch.complex128, device="cuda")
+    S.energy_grad(d["occ"], t24, ws)
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        e24, g24 = S.energy_grad(d["occ"], t24, ws)
+        ts.append(time.perf_counter() - t0)
+    out["energy_grad_24q"] = {"dim": S.dim, "excitations": len(ops), "ms": float(np.median(ts)) * 1e3,
+                              "evals_per_s": 1.0 / float(np.median(ts)), "energy": e24}
+    del ws
+    S.close()
     h, g = qi.integrals(16, 16, 1132)
     H, off, _ = qf.build_paulis("hamiltonian", 16, 16, h, g)
     S = qf.Sector(16, 8, 8, None, H, off)

@@ -356,6 +356,12 @@ int qf_excitations(int kind, int n_orb, int n_elec, const double *t_rank, int64_
  *   D -> cos t D + s sin t D'.  t: host, one amplitude per excitation.
  * qf_sector_energy: <psi|H|psi> as the grouped Pauli sum of Eq. (17) over
  *   pairs of sector determinants (host E_out; the stream is synchronized).
+ * qf_sector_energy_grad: E(t) = <Phi|U^dagger H U|Phi> for Phi = |occ_mask>
+ *   and its gradient dE_dt[mu] = dE/dt_mu (Sec. 3.1, Eq. (16)), by
+ *   lambda = H psi in the sector and one reverse sweep over the factors:
+ *   dE/dt_mu = 2 Re <lambda_mu|kappa_mu|phi_mu>, then phi and lambda undo
+ *   factor mu.  workspace: 2 * dim complex128 device values (phi, lambda);
+ *   E_out and dE_dt (one value per excitation) are host memory.
  */
 typedef struct qf_sector qf_sector;
 int qf_sector_create(int n_orb, int n_alpha, int n_beta, const int32_t *exc, int64_t n_exc, const qf_term *H,
@@ -364,6 +370,8 @@ int qf_sector_info(const qf_sector *sector, int64_t *dim, int64_t *d_alpha, int6
 int qf_sector_prepare(qf_sector *sector, void *psi, uint64_t occ_mask, void *stream);
 int qf_sector_apply(qf_sector *sector, void *psi, const double *t, int inverse, void *stream);
 int qf_sector_energy(qf_sector *sector, const void *psi, double *E_out, void *stream);
+int qf_sector_energy_grad(qf_sector *sector, uint64_t occ_mask, const double *t, void *workspace, double *E_out,
+                          double *dE_dt, void *stream);
 int qf_sector_destroy(qf_sector *sector);
 
 /*

@@ -44,7 +44,7 @@ EXPORTS = ("qf_build_paulis", "qf_ansatz_angles", "qf_grad_t", "qf_prepare_state
            "qf_excited_determinants", "qf_mp_denominators", "qf_pqe_residuals", "qf_plan_pqe_residuals",
            "qf_plan_pqe_solve", "qf_plan_trotter", "qf_plan_qk_matrices",
            "qf_plan_grad_info", "qf_excitations", "qf_sector_create", "qf_sector_info", "qf_sector_prepare",
-           "qf_sector_apply", "qf_sector_energy", "qf_sector_destroy")
+           "qf_sector_apply", "qf_sector_energy", "qf_sector_destroy", "qf_sector_energy_grad")
 
 
 class QFError(RuntimeError):
@@ -93,6 +93,7 @@ _sig = {
     "qf_sector_prepare": [_vp, _vp, _u64, _vp],
     "qf_sector_apply": [_vp, _vp, _vp, _int, _vp],
     "qf_sector_energy": [_vp, _vp, _vp, _vp],
+    "qf_sector_energy_grad": [_vp, _u64, _vp, _vp, _vp, _vp, _vp],
     "qf_sector_destroy": [_vp],
     "qf_plan_qk_matrices": [_vp, _u64, _dbl, _int, _int, _vp, _vp, _vp, _vp],
     "qf_excited_determinants": [_int, _int, _int, _vp, _i64, _vp, _vp, _i64, _vp],

@@ -213,6 +213,19 @@ class Sector:
         check(lib.qf_sector_energy(self._h, ptr(psi), ctypes.byref(e), stream_handle(stream)), "qf_sector_energy")
         return e.value
 
+    def energy_grad(self, occ_mask: int, t, workspace=None, stream=None):
+        """qf_sector_energy_grad: (E, dE/dt) with one derivative per
+        excitation.  workspace: complex128 tensor of 2 * dim (allocated if None)."""
+        import torch
+        t = _f64(t)
+        if workspace is None:
+            workspace = torch.empty(2 * self.dim, dtype=torch.complex128, device="cuda")
+        e = ctypes.c_double()
+        g = np.zeros(0 if self._exc is None else len(self._exc), dtype=np.float64)
+        check(lib.qf_sector_energy_grad(self._h, int(occ_mask), ptr(t), ptr(workspace), ctypes.byref(e), ptr(g),
+                                        stream_handle(stream)), "qf_sector_energy_grad")
+        return e.value, g
+
 
 class PoolPlan:
     """qf_plan_create_pool: device tables of an ADAPT operator pool."""

@@ -21,6 +21,13 @@
 //                     stored y and group g with y ^ x_g stored,
 //                     conj(psi[y ^ x_g]) D_g(y) psi[y] (Eq. (17)); each
 //                     thread holds its amplitude and walks all groups.
+//   k_sector_sigma    lambda = H psi in the sector: lambda[y] = sum_g
+//                     D_g(y ^ x_g) psi[y ^ x_g] over stored partners, fused
+//                     with E = Re <psi|lambda>.
+//   k_sector_adjoint  one step of the reverse sweep for one dUCC factor:
+//                     dE/dt_mu = 2 Re <lambda|kappa_mu|phi> over its
+//                     determinant pairs, then phi and lambda rotated back by
+//                     -t_mu (the factor undone).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -205,6 +212,152 @@ __global__ __launch_bounds__(kSecT) void k_sector_energy(const double2 *__restri
     }
 }
 
+// Fixed-order block sum of one value, then the last block to arrive sums the
+// per-block partials in block order into *out.
+__device__ __forceinline__ void sector_reduce(double v, double *partials, unsigned *counter, double *out)
+{
+    __shared__ double lds[kSecT / 64];
+    __shared__ bool last;
+    __shared__ double red[kSecT];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if (lane == 0)
+        lds[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bsum = 0.0;
+        for (int w = 0; w < kSecT / 64; w++)
+            bsum += lds[w];
+        __hip_atomic_store(&partials[blockIdx.x], bsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last)
+        return;
+    __threadfence();
+    double p = 0.0;
+    for (unsigned k = threadIdx.x; k < gridDim.x; k += kSecT)
+        p += __hip_atomic_load(&partials[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    red[threadIdx.x] = p;
+    __syncthreads();
+    for (int w = kSecT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *out = red[0];
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(kSecT) void k_sector_sigma(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                        const uint32_t *__restrict__ strA,
+                                                        const uint32_t *__restrict__ strB,
+                                                        const uint32_t *__restrict__ rankA,
+                                                        const uint32_t *__restrict__ rankB, uint32_t DA,
+                                                        uint32_t DB, const SecGroup *__restrict__ groups, int G,
+                                                        const SecStr *__restrict__ strs, double *partials,
+                                                        unsigned *counter, double *out)
+{
+    double acc = 0.0;
+    const uint32_t nchunk = (DB + kSecT - 1) / kSecT;
+    const uint64_t ntiles = (uint64_t)DA * nchunk;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t ia = (uint32_t)(t / nchunk), ch = (uint32_t)(t % nchunk);
+        const uint32_t a = strA[ia];
+        const uint32_t ib = ch * kSecT + threadIdx.x;
+        const bool live = ib < DB;
+        const uint32_t b = live ? strB[ib] : 0u;
+        double lx = 0.0, ly = 0.0;
+        for (int g = 0; g < G; g++) {
+            const SecGroup gd = groups[g];
+            if ((uint32_t)__popc(a & gd.xA) != gd.halfA)
+                continue;
+            const uint32_t a2 = a ^ gd.xA;
+            const uint32_t ia2 = gd.xA ? rankA[a2] : ia;
+            const uint32_t b2 = b ^ gd.xB;
+            const uint32_t ib2 = gd.xB ? (live ? rankB[b2] : kNoRank) : ib;
+            if (!live || ib2 == kNoRank)
+                continue;
+            // D_g at the partner determinant (a2, b2)
+            double dr = 0.0, di = 0.0;
+            for (int k = gd.k0; k < gd.kre; k++) {
+                const SecStr z = strs[k];
+                dr += ((__popc(a2 & z.zA) + __popc(b2 & z.zB)) & 1u) ? -z.c : z.c;
+            }
+            for (int k = gd.kre; k < gd.k1; k++) {
+                const SecStr z = strs[k];
+                di += ((__popc(a2 & z.zA) + __popc(b2 & z.zB)) & 1u) ? -z.c : z.c;
+            }
+            const double2 w = psi[(uint64_t)ia2 * DB + ib2];
+            lx += dr * w.x - di * w.y;
+            ly += dr * w.y + di * w.x;
+        }
+        if (live) {
+            const uint64_t i = (uint64_t)ia * DB + ib;
+            lam[i] = make_double2(lx, ly);
+            const double2 v = psi[i];
+            acc += v.x * lx + v.y * ly;
+        }
+    }
+    sector_reduce(acc, partials, counter, out);
+}
+
+// grad_out = 2 Re <lam|kappa|phi> over the pairs (D, D' = tau D / s):
+// kappa D = s D', kappa D' = -s D, so the pair adds
+// s (conj(lam[D']) phi[D] - conj(lam[D]) phi[D']); then both states are
+// rotated by -t on the pair (D -> cos t D - s sin t D' ...).
+__global__ __launch_bounds__(kSecT) void k_sector_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam,
+                                                          const uint32_t *__restrict__ strA,
+                                                          const uint32_t *__restrict__ strB,
+                                                          const uint32_t *__restrict__ rankA,
+                                                          const uint32_t *__restrict__ rankB, uint32_t DA,
+                                                          uint32_t DB, SecExc e, double cs, double sn,
+                                                          double *partials, unsigned *counter, double *grad_out)
+{
+    double acc = 0.0;
+    const uint32_t nchunk = (DB + kSecT - 1) / kSecT;
+    const uint64_t ntiles = (uint64_t)DA * nchunk;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t ia = (uint32_t)(t / nchunk), ch = (uint32_t)(t % nchunk);
+        const uint32_t a = strA[ia];
+        if ((a & e.annA) != e.annA || (a & e.creA) != 0u)
+            continue;
+        const uint32_t ia2 = rankA[a ^ e.annA ^ e.creA];
+        const uint32_t ib = ch * kSecT + threadIdx.x;
+        if (ib >= DB)
+            continue;
+        const uint32_t b = strB[ib];
+        if ((b & e.annB) != e.annB || (b & e.creB) != 0u)
+            continue;
+        const uint32_t ib2 = rankB[b ^ e.annB ^ e.creB];
+        uint32_t ca = a, cb = b, par = 0u;
+        for (int k = 0; k < e.nops; k++) {
+            const int p = e.op[k];
+            par ^= below_parity(ca, cb, p);
+            if (p & 1)
+                cb ^= 1u << (p >> 1);
+            else
+                ca ^= 1u << (p >> 1);
+        }
+        const double sgn = par ? -1.0 : 1.0;
+        const uint64_t i1 = (uint64_t)ia * DB + ib, i2 = (uint64_t)ia2 * DB + ib2;
+        const double2 u = phi[i1], v = phi[i2], lu = lam[i1], lv = lam[i2];
+        // s (Re conj(lv) u - Re conj(lu) v)
+        acc += sgn * ((lv.x * u.x + lv.y * u.y) - (lu.x * v.x + lu.y * v.y));
+        // undo: rotation by -t (sn is sin t)
+        const double s = sgn * sn;
+        phi[i1] = make_double2(cs * u.x + s * v.x, cs * u.y + s * v.y);
+        phi[i2] = make_double2(cs * v.x - s * u.x, cs * v.y - s * u.y);
+        lam[i1] = make_double2(cs * lu.x + s * lv.x, cs * lu.y + s * lv.y);
+        lam[i2] = make_double2(cs * lv.x - s * lu.x, cs * lv.y - s * lu.y);
+    }
+    sector_reduce(2.0 * acc, partials, counter, grad_out);
+}
+
 uint32_t compact(uint64_t so, int spin, int n_orb)
 {
     uint32_t m = 0;
@@ -226,9 +379,11 @@ struct qf_sector {
     qf::SecStr *d_strs = nullptr;
     double *d_partials = nullptr, *d_result = nullptr;
     unsigned *d_counter = nullptr;
+    double *d_grad = nullptr;  // dE/dt of the last gradient call
+    size_t grad_cap = 0;
     ~qf_sector()
     {
-        void *bufs[] = {d_strA, d_strB, d_rankA, d_rankB, d_groups, d_strs, d_partials, d_result, d_counter};
+        void *bufs[] = {d_strA, d_strB, d_rankA, d_rankB, d_groups, d_strs, d_partials, d_result, d_counter, d_grad};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -459,6 +614,48 @@ extern "C" int qf_sector_energy(qf_sector *s, const void *psi, double *E_out, vo
                            s->d_partials, s->d_counter, s->d_result);
         QF_HIP(hipGetLastError());
         QF_HIP(hipMemcpyAsync(E_out, s->d_result, sizeof(double), hipMemcpyDeviceToHost, st));
+        QF_HIP(hipStreamSynchronize(st));
+        return QF_OK;
+    });
+}
+
+extern "C" int qf_sector_energy_grad(qf_sector *s, uint64_t occ_mask, const double *t, void *workspace,
+                                     double *E_out, double *dE_dt, void *stream)
+{
+    return guarded([&]() -> int {
+        if (!s || !workspace || !E_out || (!s->exc.empty() && (!t || !dE_dt)))
+            return fail(QF_E_ARG, "qf_sector_energy_grad: null argument");
+        if (s->G == 0)
+            return fail(QF_E_ARG, "qf_sector_energy_grad: the sector has no Hamiltonian");
+        hipStream_t st = (hipStream_t)stream;
+        double2 *phi = (double2 *)workspace;
+        double2 *lam = phi + (uint64_t)s->DA * s->DB;
+        int rc = qf_sector_prepare(s, phi, occ_mask, stream);
+        if (rc != QF_OK)
+            return rc;
+        rc = qf_sector_apply(s, phi, t, 0, stream);
+        if (rc != QF_OK)
+            return rc;
+        const unsigned grid = tile_grid(*s);
+        hipLaunchKernelGGL(k_sector_sigma, dim3(grid), dim3(kSecT), 0, st, (const double2 *)phi, lam, s->d_strA,
+                           s->d_strB, s->d_rankA, s->d_rankB, s->DA, s->DB, s->d_groups, s->G, s->d_strs,
+                           s->d_partials, s->d_counter, s->d_result);
+        const size_t E = s->exc.size();
+        if (E > s->grad_cap) {
+            if (s->d_grad)
+                QF_HIP(hipFree(s->d_grad));
+            s->d_grad = nullptr;
+            s->d_grad = dev_alloc<double>(E);
+            s->grad_cap = E;
+        }
+        for (size_t i = E; i-- > 0;)
+            hipLaunchKernelGGL(k_sector_adjoint, dim3(grid), dim3(kSecT), 0, st, phi, lam, s->d_strA, s->d_strB,
+                               s->d_rankA, s->d_rankB, s->DA, s->DB, s->exc[i], std::cos(t[i]), std::sin(t[i]),
+                               s->d_partials, s->d_counter, s->d_grad + i);
+        QF_HIP(hipGetLastError());
+        QF_HIP(hipMemcpyAsync(E_out, s->d_result, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (E)
+            QF_HIP(hipMemcpyAsync(dE_dt, s->d_grad, E * sizeof(double), hipMemcpyDeviceToHost, st));
         QF_HIP(hipStreamSynchronize(st));
         return QF_OK;
     });
