@@ -639,7 +639,7 @@ def main():
     if "energy_grad" in extra:
         r24 = extra["energy_grad"]["24q"]
         line["roofline_energy_grad"] = {
-            "bound": "hbm", "kernel": "energy + gradient step at 24 qubits (k_apply_block, k_sigma_tiled, "
+            "bound": "hbm", "kernel": "energy + gradient step at 24 qubits (k_apply_block, k_sigma_stream, "
                                       "k_adjoint_block, k_grad_reduce)",
             "achieved": r24["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r24["GBps"] / HBM_PEAK_GBS,
             "traffic": None, "bytes_per_step": r24["state_bytes"], "step_ms": r24["ms"]}

@@ -21,9 +21,11 @@
 //                    k_energy_tiled / k_energy_merged walk the same items
 //                    class by class (per string / merged), k_energy makes
 //                    one pass per group.
-//   k_sigma_tiled    lambda = H psi over the same classes (the partner tile
-//                    staged in LDS), fused with E = Re <psi|lambda>; k_sigma
-//                    gathers psi[y ^ x_g] per group below 12 qubits.
+//   k_sigma_stream   lambda = H psi over output tiles of 2^11: per class the
+//                    partner tile staged in LDS, strings merged per tile into
+//                    lo-terms with signs taken at the output index, fused
+//                    with E = Re <psi|lambda>; k_sigma gathers psi[y ^ x_g]
+//                    per group below 12 qubits.
 //   k_adjoint_block  reverse sweep over a segment on LDS sub-cubes of phi and
 //                    lambda: 2 Im <lambda|P_k|phi> for each string of a run,
 //                    then phi, lambda <- U_run^dagger; k_grad_reduce adds
@@ -871,18 +873,257 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
-// Class-tiled sigma (sigma_tiles): one workgroup per output tile at a time.
-__global__ __launch_bounds__(kSigNT) void k_sigma_tiled(const double2 *__restrict__ psi, double2 *__restrict__ lam,
-                                                        int n, const ClassDesc *__restrict__ classes, int ncls,
-                                                        const GroupDesc *__restrict__ groups, int G,
-                                                        const uint32_t *__restrict__ zs,
-                                                        const double *__restrict__ cs, double *partials,
+// ---------------------------------------------------------------- sigma, streamed
+// lambda = H psi with the signs evaluated at the output index.  For a string
+// of real phase omega(y ^ x) = omega(y), for one of imaginary phase
+// omega(y ^ x) = -omega(y), so lambda[y] = sum_g (dre_g(y) - i dim_g(y))
+// psi[y ^ x_g] with dre, dim the sums of the folded coefficients times
+// (-1)^popcount(y & z) (host tables carry the imaginary part negated).
+// Output tiles of 2^11: with y = t 2^11 | tid | i 2^8 (256 threads, items
+// i < 8) the sign splits into (-1)^popcount(t & z_hi), uniform over the
+// tile, (-1)^popcount(tid & z_lo) per thread and (-1)^popcount(i & p),
+// p = z_lo >> 8, fixed per item.  So strings of a group part with equal z_lo
+// merge per tile into one lo-term of coefficient C(t) = sum c (-1)^popcount(t & z_hi),
+// and lo-terms sorted by z_lo come in runs of equal p: a run sums
+// a = sum C (-1)^popcount(tid & z_lo) once and adds +-a psi[y_i ^ x] to
+// the eight outputs with compile-time signs (a uniform switch on p).
+//
+// A workgroup owns one output tile at a time and walks the sub-classes
+// (groups with the same flip bits above the tile, at most 256 groups and 256
+// lo-terms each).  For each it stages the partner tile t ^ xh in LDS, with
+// one lo-term per thread (C(t) computed from the tabled strings) and one
+// group word per thread; the next sub-class's tile, lo-term and group are in
+// flight in registers meanwhile.  Waves pull lo-terms and group words 64 at
+// a time from LDS into lanes and broadcast them with readlane.
+constexpr int kSsL = 11;
+constexpr int kSsNT = 256;
+constexpr int kSsWin = 256;           // groups / lo-terms per sub-class
+constexpr int kSsGrp = 64;            // lo-terms per group (larger groups are cut)
+constexpr uint32_t kSsFlush = 1u << 11;  // last lo-term of a run of equal p
+constexpr uint32_t kSsImag = 1u << 12;   // lo-term of the imaginary part
+constexpr uint32_t kSsOne = 1u << 14;    // group word: one run (pattern in bits 11..13)
+
+struct SsLo {
+    uint32_t zf;       // z_lo | kSsFlush | kSsImag
+    uint32_t zhi[3];   // z >> 11 of up to three strings, as tile-index masks
+    double c[3];       // their coefficients (0 where unused)
+    double pad;
+};
+
+struct SsCls {
+    uint32_t xh;       // partner tile t ^ xh
+    int32_t g0, l0;    // first group word / lo-term
+    int32_t ng, nl;    // counts, 1..kSsWin
+    int32_t pad[3];
+};
+
+// d_i += (-1)^popcount(i & p) a for the eight items: the item signs are
+// uniform (FMAs by +-1.0, exact)
+__device__ __forceinline__ void ss_run(double a, uint32_t p, double (&d)[8])
+{
+    const uint32_t m1 = p << 31, m2 = (p >> 1) << 31, m4 = (p >> 2) << 31;
+    const uint32_t sg[8] = {0u, m1, m2, m1 ^ m2, m4, m1 ^ m4, m2 ^ m4, m1 ^ m2 ^ m4};
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        d[i] = fma(pm_one(sg[i]), a, d[i]);
+}
+
+template <bool IMAG>
+__global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                        int n, const SsCls *__restrict__ cls, int ncls,
+                                                        const uint32_t *__restrict__ gwords,
+                                                        const SsLo *__restrict__ los, double *partials,
                                                         unsigned *counter, double *result)
 {
-    __shared__ double2 sp[2][1u << kSigL];
-    double vals[1] = {
-        sigma_tiles(psi, lam, blockIdx.x, gridDim.x, 1u << (n - kSigL), classes, ncls, groups, G, zs, cs, sp)};
-    reduce_finish<1, kSigNT>(vals, partials, counter, result, 1.0, 1);
+    constexpr uint32_t T = 1u << kSsL;
+    __shared__ double2 tile[T];
+    __shared__ uint4 wlo[kSsWin];    // z_lo | flags, 0, C (lo, hi word)
+    __shared__ uint32_t wgw[kSsWin]; // x & (T - 1) | lo-term count << 16
+    const uint32_t tid = threadIdx.x, tid16 = tid << 4;
+    const int lane = (int)(tid & 63u);
+    const uint32_t ntiles = 1u << (n - kSsL);
+    double acc = 0.0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        double2 l[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            l[i] = make_double2(0.0, 0.0);
+        // sub-class in flight: its tile, lo-term and group word (raw loads;
+        // named values: an array carried around the loop went to scratch)
+        double2 p0, p1, p2, p3, p4, p5, p6, p7;
+        uint32_t zfn, zh0, zh1, zh2, gwn;
+        double c0, c1, c2;
+        SsCls cn = cls[0];
+        auto fetch = [&]() __attribute__((always_inline)) {
+            const double2 *src = psi + ((size_t)(t ^ cn.xh) << kSsL) + tid;
+            p0 = src[0];
+            p1 = src[1u << 8];
+            p2 = src[2u << 8];
+            p3 = src[3u << 8];
+            p4 = src[4u << 8];
+            p5 = src[5u << 8];
+            p6 = src[6u << 8];
+            p7 = src[7u << 8];
+            const SsLo &r = los[cn.l0 + min((int)tid, cn.nl - 1)];
+            zfn = r.zf;
+            zh0 = r.zhi[0];
+            zh1 = r.zhi[1];
+            zh2 = r.zhi[2];
+            c0 = r.c[0];
+            c1 = r.c[1];
+            c2 = r.c[2];
+            gwn = gwords[cn.g0 + min((int)tid, cn.ng - 1)];
+        };
+        fetch();
+        for (int c = 0; c < ncls; c++) {
+            const int ng = cn.ng;
+            __syncthreads();  // the previous sub-class's LDS reads are done
+            tile[tid] = p0;
+            tile[tid + (1u << 8)] = p1;
+            tile[tid + (2u << 8)] = p2;
+            tile[tid + (3u << 8)] = p3;
+            tile[tid + (4u << 8)] = p4;
+            tile[tid + (5u << 8)] = p5;
+            tile[tid + (6u << 8)] = p6;
+            tile[tid + (7u << 8)] = p7;
+            {
+                const double C = flip(c0, par(t & zh0)) + flip(c1, par(t & zh1)) + flip(c2, par(t & zh2));
+                wlo[tid] = make_uint4(zfn, 0u, (uint32_t)__double2loint(C), (uint32_t)__double2hiint(C));
+                wgw[tid] = gwn;
+            }
+            __syncthreads();
+            cn = cls[c + 1 < ncls ? c + 1 : c];
+            fetch();  // unconditional: the last sub-class fetches itself again
+            int jw = 0;
+            uint4 lch = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t gch = 0u;
+            for (int g = 0; g < ng; g++) {
+                if ((g & 63) == 0)
+                    gch = wgw[g + lane];
+                const uint32_t gw = (uint32_t)__builtin_amdgcn_readlane((int)gch, g & 63);
+                const int nlo = (int)(gw >> 16);
+                // the group's lo-terms, one per lane (at most 64; lanes past
+                // them read entries that are not used)
+                lch = wlo[min(jw + lane, kSsWin - 1)];
+                jw += nlo;
+                const uint32_t base = tid16 ^ ((gw & (T - 1u)) << 4);
+                auto row = [&](int i) __attribute__((always_inline)) {
+                    return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tile) +
+                                                              (base ^ ((uint32_t)i << 12)));
+                };
+                double a = 0.0;
+                if constexpr (IMAG) {
+                    double2 b[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++)
+                        b[i] = row(i);
+                    // D at the eight outputs: dr + i di
+                    double dr[8], di[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        dr[i] = 0.0;
+                        di[i] = 0.0;
+                    }
+                    for (int k = 0; k < nlo; k++) {
+                        const uint32_t zf = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+                        const double C = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                                          __builtin_amdgcn_readlane((int)lch.z, k));
+                        a = fma(pm_one((uint32_t)__popc(tid & zf) << 31), C, a);
+                        if (zf & kSsFlush) {
+                            if (zf & kSsImag)
+                                ss_run(a, (zf >> 8) & 7u, di);
+                            else
+                                ss_run(a, (zf >> 8) & 7u, dr);
+                            a = 0.0;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        l[i].x = fma(dr[i], b[i].x, l[i].x);
+                        l[i].y = fma(dr[i], b[i].y, l[i].y);
+                        l[i].x = fma(-di[i], b[i].y, l[i].x);
+                        l[i].y = fma(di[i], b[i].x, l[i].y);
+                    }
+                } else {
+                    // partner rows of the first four items in flight during
+                    // the lo-terms; the other four are read after the first
+                    // four outputs are updated (fewer live registers)
+                    double2 b[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        b[i] = row(i);
+                    // D at the eight outputs; a group of one run (one phase
+                    // part, one item pattern) signs its one sum at the end
+                    double d[8];
+                    if (gw & kSsOne) {
+                        // lo-terms two at a time into two sums
+                        double a2 = 0.0;
+                        int k = 0;
+                        for (; k + 1 < nlo; k += 2) {
+                            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+                            const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k + 1);
+                            const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                                               __builtin_amdgcn_readlane((int)lch.z, k));
+                            const double C1 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k + 1),
+                                                               __builtin_amdgcn_readlane((int)lch.z, k + 1));
+                            a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
+                            a2 = fma(pm_one((uint32_t)__popc(tid & z1) << 31), C1, a2);
+                        }
+                        if (k < nlo) {
+                            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+                            const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                                               __builtin_amdgcn_readlane((int)lch.z, k));
+                            a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
+                        }
+                        a += a2;
+                        const uint32_t p = (gw >> 11) & 7u;
+                        const uint32_t m1 = p << 31, m2 = (p >> 1) << 31, m4 = (p >> 2) << 31;
+                        const uint32_t sg[8] = {0u, m1, m2, m1 ^ m2, m4, m1 ^ m4, m2 ^ m4, m1 ^ m2 ^ m4};
+#pragma unroll
+                        for (int i = 0; i < 8; i++)
+                            d[i] = pm_one(sg[i]) * a;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; i++)
+                            d[i] = 0.0;
+                        for (int k = 0; k < nlo; k++) {
+                            const uint32_t zf = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+                            const double C = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                                              __builtin_amdgcn_readlane((int)lch.z, k));
+                            a = fma(pm_one((uint32_t)__popc(tid & zf) << 31), C, a);
+                            if (zf & kSsFlush) {
+                                ss_run(a, (zf >> 8) & 7u, d);
+                                a = 0.0;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        l[i].x = fma(d[i], b[i].x, l[i].x);
+                        l[i].y = fma(d[i], b[i].y, l[i].y);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        b[i] = row(i + 4);
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        l[i + 4].x = fma(d[i + 4], b[i].x, l[i + 4].x);
+                        l[i + 4].y = fma(d[i + 4], b[i].y, l[i + 4].y);
+                    }
+                }
+            }
+        }
+        const size_t tb = (size_t)t << kSsL;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const size_t y = tb + tid + ((uint32_t)i << 8);
+            const double2 p = psi[y];
+            lam[y] = l[i];
+            acc += p.x * l[i].x + p.y * l[i].y;
+        }
+    }
+    double vals[1] = {acc};
+    reduce_finish<1, kSsNT>(vals, partials, counter, result, 1.0, 1);
 }
 
 // One reverse-sweep step over a run: grad[k0+k] = 2 Im <lam|P_k|phi>, then
@@ -1345,6 +1586,83 @@ void sigma_classes(std::vector<GroupDesc> &gd, std::vector<ClassDesc> &cls)
     }
 }
 
+// Tables of k_sigma_stream: groups in class order, each group part's strings
+// sorted by (z_lo, z_hi) and merged into lo-terms of equal z_lo (at most three
+// strings each; longer runs continue in the next lo-term), the imaginary
+// part's coefficients negated (signs taken at the output index), a flush
+// flag on the last lo-term of every run of equal item pattern z_lo >> 8.
+// A group of more than kSsGrp lo-terms is cut into groups of the same flip
+// mask; sub-classes hold at most kSsWin groups and kSsWin lo-terms.
+void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uint32_t> &zs,
+                         const std::vector<double> &cs, std::vector<SsCls> &cls, std::vector<uint32_t> &words,
+                         std::vector<SsLo> &los)
+{
+    constexpr uint32_t lomask = (1u << kSsL) - 1u;
+    std::vector<size_t> order(gd.size());
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return (gd[a].x >> kSsL) < (gd[b].x >> kSsL); });
+    cls.clear();
+    words.clear();
+    los.clear();
+    for (size_t gi : order) {
+        const GroupDesc &g = gd[gi];
+        std::vector<SsLo> lg;
+        const int32_t ranges[2][2] = {{g.k0, g.kre}, {g.kre, g.k1}};
+        for (int part = 0; part < 2; part++) {
+            std::vector<int32_t> ks;
+            for (int32_t k = ranges[part][0]; k < ranges[part][1]; k++)
+                ks.push_back(k);
+            std::stable_sort(ks.begin(), ks.end(), [&](int32_t a, int32_t b) {
+                const uint32_t la = zs[(size_t)a] & lomask, lb = zs[(size_t)b] & lomask;
+                return la != lb ? la < lb : (zs[(size_t)a] >> kSsL) < (zs[(size_t)b] >> kSsL);
+            });
+            const size_t first = lg.size();
+            int used = 3;
+            for (size_t i = 0; i < ks.size(); i++) {
+                const uint32_t z = zs[(size_t)ks[i]];
+                const uint32_t zlo = z & lomask;
+                if (used == 3 || (lg.back().zf & lomask) != zlo) {
+                    SsLo e;
+                    std::memset(&e, 0, sizeof e);
+                    e.zf = zlo | (part ? kSsImag : 0u);
+                    lg.push_back(e);
+                    used = 0;
+                }
+                lg.back().zhi[used] = z >> kSsL;
+                lg.back().c[used] = part ? -cs[(size_t)ks[i]] : cs[(size_t)ks[i]];
+                used++;
+            }
+            for (size_t j = first; j < lg.size(); j++)
+                if (j + 1 == lg.size() || ((lg[j + 1].zf & lomask) >> 8) != ((lg[j].zf & lomask) >> 8))
+                    lg[j].zf |= kSsFlush;
+        }
+        for (size_t p0 = 0; p0 < lg.size(); p0 += kSsGrp) {
+            const size_t p1 = std::min(lg.size(), p0 + (size_t)kSsGrp);
+            lg[p1 - 1].zf |= kSsFlush;
+            const uint32_t xh = g.x >> kSsL;
+            const int32_t nl = (int32_t)(p1 - p0);
+            if (cls.empty() || cls.back().xh != xh || cls.back().ng == kSsWin || cls.back().nl + nl > kSsWin) {
+                SsCls c;
+                std::memset(&c, 0, sizeof c);
+                c.xh = xh;
+                c.g0 = (int32_t)words.size();
+                c.l0 = (int32_t)los.size();
+                cls.push_back(c);
+            }
+            // one run: every lo-term of the piece is real with one item pattern
+            bool one = true;
+            for (size_t j = p0; j < p1; j++)
+                one = one && !(lg[j].zf & kSsImag) && ((lg[j].zf & lomask) >> 8) == ((lg[p0].zf & lomask) >> 8);
+            const uint32_t pat = one ? (((lg[p0].zf & lomask) >> 8) << 11) | kSsOne : 0u;
+            words.push_back((g.x & lomask) | pat | ((uint32_t)nl << 16));
+            los.insert(los.end(), lg.begin() + (ptrdiff_t)p0, lg.begin() + (ptrdiff_t)p1);
+            cls.back().ng++;
+            cls.back().nl += nl;
+        }
+    }
+}
+
 // Greedy segmentation of the run sequence for blocked application: extend a
 // segment while the union of its flip masks and the lowest q0 qubits has at
 // most B qubits; pad Q with the lowest free qubits to exactly B.  A run whose
@@ -1482,9 +1800,10 @@ struct qf_plan {
     qf::GroupDesc *d_groups = nullptr;
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
-    qf::ClassDesc *d_sclasses = nullptr;  // sigma classes over 2^11 tiles (n >= 12)
-    qf::GroupDesc *d_sgroups = nullptr;   // groups in class order (ranges into d_z / d_c)
-    int n_sclasses = 0;
+    qf::SsCls *d_ss_cls = nullptr;        // k_sigma_stream sub-classes, group words, lo-terms
+    uint32_t *d_ss_words = nullptr;
+    qf::SsLo *d_ss_los = nullptr;
+    int n_ss_cls = 0;
     double *d_partials = nullptr;
     unsigned *d_counter = nullptr;
     double *d_result = nullptr;
@@ -1553,8 +1872,8 @@ struct qf_plan {
         if (mem != kOwned)
             return;
         void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
-                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_sclasses, d_sgroups, d_pidx, d_pout,
-                        d_dots};
+                        d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_pidx, d_pout,
+                        d_dots, d_ss_cls, d_ss_words, d_ss_los};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -1812,14 +2131,17 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         P.hz = zs;
         P.hc = cs;
         if (n > kSigL && P.sigma_tables) {
-            std::vector<GroupDesc> sg(gd);
-            std::vector<ClassDesc> sc;
-            sigma_classes(sg, sc);
-            P.d_sclasses = P.dalloc<ClassDesc>(sc.size());
-            P.d_sgroups = P.dalloc<GroupDesc>(sg.size());
-            P.upload(P.d_sclasses, sc.data(), sc.size() * sizeof(ClassDesc));
-            P.upload(P.d_sgroups, sg.data(), sg.size() * sizeof(GroupDesc));
-            P.n_sclasses = (int)sc.size();
+            std::vector<SsCls> ssc;
+            std::vector<uint32_t> ssw;
+            std::vector<SsLo> ssl;
+            sigma_stream_tables(gd, zs, cs, ssc, ssw, ssl);
+            P.d_ss_cls = P.dalloc<SsCls>(ssc.size());
+            P.d_ss_words = P.dalloc<uint32_t>(ssw.size());
+            P.d_ss_los = P.dalloc<SsLo>(ssl.size());
+            P.upload(P.d_ss_cls, ssc.data(), ssc.size() * sizeof(SsCls));
+            P.upload(P.d_ss_words, ssw.data(), ssw.size() * sizeof(uint32_t));
+            P.upload(P.d_ss_los, ssl.data(), ssl.size() * sizeof(SsLo));
+            P.n_ss_cls = (int)ssc.size();
         }
         for (const GroupDesc &g : gd)
             if (g.k1 > g.kre)
@@ -2028,13 +2350,32 @@ void launch_energy(qf_plan &P, const double2 *psi, double *dev_out, hipStream_t 
     QF_HIP(hipGetLastError());
 }
 
+template <bool IMAG> unsigned sigma_stream_grid()
+{
+    static unsigned cached = 0;
+    if (!cached) {
+        int dev = 0, cus = 0, per = 0;
+        QF_HIP(hipGetDevice(&dev));
+        QF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        QF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, reinterpret_cast<const void *>(k_sigma_stream<IMAG>), kSsNT, 0));
+        cached = (unsigned)std::max(1, std::min(cus * std::max(per, 1), kMaxBlocks));
+    }
+    return cached;
+}
+
 void launch_sigma(qf_plan &P, const double2 *psi, double2 *lam, double *dev_out, hipStream_t s)
 {
-    if (P.n_sclasses) {
-        const unsigned ntiles = 1u << (P.n - kSigL);
-        const unsigned nb = std::min<unsigned>(ntiles, (unsigned)kMaxBlocks);
-        hipLaunchKernelGGL(k_sigma_tiled, dim3(nb), dim3(kSigNT), 0, s, psi, lam, P.n, P.d_sclasses,
-                           P.n_sclasses, P.d_sgroups, P.G, P.d_z, P.d_c, P.d_partials, P.d_counter, dev_out);
+    if (P.n_ss_cls) {
+        const unsigned ntiles = 1u << (P.n - kSsL);
+        if (P.has_imag)
+            hipLaunchKernelGGL(k_sigma_stream<true>, dim3(std::min(ntiles, sigma_stream_grid<true>())),
+                               dim3(kSsNT), 0, s, psi, lam, P.n, P.d_ss_cls, P.n_ss_cls, P.d_ss_words,
+                               P.d_ss_los, P.d_partials, P.d_counter, dev_out);
+        else
+            hipLaunchKernelGGL(k_sigma_stream<false>, dim3(std::min(ntiles, sigma_stream_grid<false>())),
+                               dim3(kSsNT), 0, s, psi, lam, P.n, P.d_ss_cls, P.n_ss_cls, P.d_ss_words,
+                               P.d_ss_los, P.d_partials, P.d_counter, dev_out);
         QF_HIP(hipGetLastError());
         return;
     }
@@ -2760,7 +3101,7 @@ extern "C" int qf_plan_grad_info(const qf_plan *P, int64_t *sigma_passes, int64_
     if (!P)
         return fail(QF_E_ARG, "qf_plan_grad_info: plan is NULL");
     if (sigma_passes)
-        *sigma_passes = P->G == 0 ? 0 : P->n_sclasses ? (int64_t)P->n_sclasses : (int64_t)P->G;
+        *sigma_passes = P->G == 0 ? 0 : P->n_ss_cls ? (int64_t)P->n_ss_cls : (int64_t)P->G;
     if (sweep_passes)
         *sweep_passes = P->adj_bits ? (int64_t)P->asegs.size() : (int64_t)P->runs.size();
     return QF_OK;

@@ -8,6 +8,7 @@ paper_2108_04413_amd.measure --op pool --qubits 20`).
     --op qk      QK basis by Trotterized evolution, S and H (Sec. 3.7),
                  dt 0.5, s 3, r 1
     --op sector  restricted state vector: reference, UCCSD factors, energy
+    --op sigma   lambda = H psi (Eq. (17) as a sigma) on the UCCSD state
 
 The instance is the autotuner's: n/2 spatial orbitals and n/2 electrons,
 seeded random integrals, all UCCSD excitations, amplitudes ~ U[-0.2, 0.2].
@@ -24,7 +25,7 @@ import time
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", default="eg", choices=("eg", "pool", "pqe", "qk", "sector"))
+    ap.add_argument("--op", default="eg", choices=("eg", "pool", "pqe", "qk", "sector", "sigma"))
     ap.add_argument("--qubits", type=int, default=24)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--seed", type=int, default=None)
@@ -70,6 +71,15 @@ def main():
         def call():
             S, Hm, _ = hp.qk_matrices(d["occ"], 0.5, 3, 1, states)
             return float(Hm[0, 0].real)
+    elif args.op == "sigma":
+        del ws
+        psi = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+        lam = torch.empty_like(psi)
+        qf.prepare_state(psi, n, d["occ"])
+        plan.apply(psi, d["theta"])
+
+        def call():
+            return plan.sigma(psi, lam)
     else:
         ops = qf.excitations("uccsd", no, no)
         t = qi.amplitudes(len(ops), seed, 0.2)

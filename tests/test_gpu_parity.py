@@ -524,6 +524,46 @@ def test_sigma_shared_pattern_groups_match_oracle(qf, n):
     assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
 
 
+@pytest.mark.parametrize("n", [13, 16])
+def test_sigma_merged_lo_terms_and_split_windows_match_oracle(qf, n):
+    """Sigma with strings merged per output tile: many strings of one group
+    part sharing their low 11 z bits (runs longer than one lo-term holds),
+    a diagonal group with more lo-terms than one window and one wave hold
+    (the group is cut), a class of more than 256 groups (the class is cut
+    into several windows over the same partner tile), and imaginary-phase
+    parts."""
+    rng = np.random.default_rng([n, 131])
+    xs, zs = [], []
+    # 800 diagonal strings over 40 distinct low parts: long equal-z_lo runs
+    lows = rng.integers(0, 1 << 11, 40)
+    for k in range(800):
+        xs.append(0)
+        zs.append(int(lows[k % 40]) | (int(rng.integers(0, 1 << (n - 11))) << 11))
+    # 330 groups with flips below bit 11 (all in the class of the own tile),
+    # each with a few strings sharing z_lo
+    for x in rng.choice(np.arange(1, 1 << 11), 330, replace=False):
+        zl = int(rng.integers(0, 1 << 11))
+        for _ in range(int(rng.integers(1, 6))):
+            xs.append(int(x))
+            zs.append(zl | (int(rng.integers(0, 1 << (n - 11))) << 11))
+    # groups with high flips and mixed parts
+    for _ in range(40):
+        x = int(rng.integers(1 << 11, 1 << n))
+        for _ in range(int(rng.integers(2, 12))):
+            xs.append(x)
+            zs.append(int(rng.integers(0, 1 << n)))
+    xs, zs = np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64)
+    cs = rng.normal(size=len(xs))
+    xs, zs, cs, off = grouped(xs, zs, cs)
+    psi0 = qi.random_state(n, 140 + n)
+    plan = qf.Plan(n, None, qf.terms_array(xs, zs, cs), off)
+    lam = torch.empty_like(dev(psi0))
+    e = plan.sigma(dev(psi0), lam)
+    want = core.sigma(psi0, n, xs, zs, cs)
+    assert np.max(np.abs(host(lam) - want)) < 1e-11
+    assert e == pytest.approx(core.energy(psi0, n, xs, zs, cs, off), abs=E_TOL)
+
+
 # ------------------------------------ largest batched and served instances
 
 def _mix_instance(qf, gold):
