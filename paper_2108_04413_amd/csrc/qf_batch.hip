@@ -8,7 +8,8 @@
 // tickets from one device counter; ticket t makes it member t - ticket0_e of
 // the team of the instance that owns t.  A team runs the instance's passes
 // (prepare and the run tables, each forward segment of runs on sub-cubes,
-// sigma = H psi over class tiles, each reverse segment) on disjoint parts of
+// sigma = H psi over output tiles by the streamed tile routine (512 threads of
+// four outputs), each reverse segment) on disjoint parts of
 // the state and meets at a team barrier after every pass:
 // W = 1 teams only need the workgroup barrier, so small states stay in the
 // CU's L2; larger teams use an agent-scope counter barrier with a bounded
@@ -57,7 +58,9 @@ struct BatchEntry {
     int32_t aseg0, naseg, alr0;  // forward segments (Segment, LocalRun offsets)
     int32_t dseg0, ndseg, dlr0;  // reverse-sweep segments
     int32_t Bapp, Badj;          // their sub-cube sizes (qubits)
-    int32_t cls0, ncls;          // sigma classes (ClassDesc; groups in class order), 0: untiled sigma
+    int32_t cls0, ncls;          // streamed sigma sub-classes (SsCls), 0: untiled sigma
+    int32_t word0, lo0;          // its group words and lo-terms
+    int32_t imag;                // some string has an imaginary phase
     int32_t tabs0;               // the runs' (cos, sin) tables in the launch's table array
     uint64_t state0; // phi offset in amplitudes; lambda = phi + 2^n
 };
@@ -161,12 +164,13 @@ __device__ __forceinline__ void team_sync(int W, TeamSync &ts, unsigned epoch, u
 
 // Workgroup shape of the batched kernel: 512 threads, and LDS for one
 // 2^12-amplitude sub-cube (blocked apply), one 2^11 sub-cube of each of phi
-// and lambda (blocked adjoint) or the two partner-tile buffers of the
-// class-tiled sigma, two workgroups per CU.
+// and lambda (blocked adjoint) or the partner tile and the lo-term and group
+// windows of the streamed sigma, two workgroups per CU.
 constexpr int kBT = 512;
 constexpr int kBW = kBT / 64;
 constexpr int kSub = 4096;
-static_assert(kSub >= (2 << kSigL) && kBT == kSigNT, "the sigma tile buffers fit the sub-cube image");
+static_assert(kBT == 512 && kSub >= (1 << kSsL) + kBT + kBT / 4,
+              "the sigma tile and its lo-term and group windows fit the sub-cube image");
 // pairs per thread in the common sub-cubes (2^12 forward, 2^11 reverse), which get unrolled variants
 constexpr int kApplyPairs = kSub / 2 / kBT, kAdjPairs = kSub / 4 / kBT;
 
@@ -645,7 +649,8 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                unsigned total_tickets, const RunDesc *__restrict__ runs,
                                                const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
                                                const GroupDesc *__restrict__ groups,
-                                               const ClassDesc *__restrict__ classes, double2 *__restrict__ tabs,
+                                               const SsCls *__restrict__ sscls, const uint32_t *__restrict__ sswords,
+                                               const SsLo *__restrict__ sslos, double2 *__restrict__ tabs,
                                                const uint32_t *__restrict__ zs,
                                                const double *__restrict__ cs, const double *__restrict__ theta,
                                                double2 *states, double *partials, unsigned *sync, unsigned *ticket,
@@ -737,11 +742,19 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
         {
             double v[1] = {0.0};
             if (en.ncls) {
-                // class tiles rank, rank + W, ... (a team has at most one member per tile);
-                // the two tile buffers are the sub-cube image
-                double2(*sp)[1u << kSigL] = reinterpret_cast<double2(*)[1u << kSigL]>(s_sub);
-                v[0] = sigma_tiles(phi, lam, (uint32_t)rank, (uint32_t)W, 1u << (n - kSigL), classes + en.cls0,
-                                   en.ncls, groups + en.group0, en.G, zs + en.term0, cs + en.term0, sp);
+                // output tiles rank, rank + W, ... (a team has at most one member
+                // per tile); the tile and its windows live in the sub-cube image
+                double2 *tile = s_sub;
+                uint4 *wlo = reinterpret_cast<uint4 *>(s_sub + (1u << kSsL));
+                uint32_t *wgw = reinterpret_cast<uint32_t *>(s_sub + (1u << kSsL) + kBT);
+                if (en.imag)
+                    v[0] = sigma_stream<kBT, true>(phi, lam, (uint32_t)rank, (uint32_t)W, 1u << (n - kSsL),
+                                                   sscls + en.cls0, en.ncls, sswords + en.word0, sslos + en.lo0,
+                                                   tile, wlo, wgw);
+                else
+                    v[0] = sigma_stream<kBT, false>(phi, lam, (uint32_t)rank, (uint32_t)W, 1u << (n - kSsL),
+                                                    sscls + en.cls0, en.ncls, sswords + en.word0, sslos + en.lo0,
+                                                    tile, wlo, wgw);
             } else {
                 member_slice(dim, W, rank, b, e);
                 v[0] = pass_sigma(phi, lam, groups + en.group0, en.G, zs + en.term0, cs + en.term0, b, e);
@@ -849,7 +862,9 @@ struct qf_batch {
     qf::Segment *d_segs = nullptr;
     qf::LocalRun *d_lruns = nullptr;
     qf::GroupDesc *d_groups = nullptr;
-    qf::ClassDesc *d_classes = nullptr;
+    qf::SsCls *d_sscls = nullptr;
+    uint32_t *d_sswords = nullptr;
+    qf::SsLo *d_sslos = nullptr;
     double2 *d_tabs = nullptr;  // (cos, sin) tables of every instance's runs, filled in the launch
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
@@ -925,7 +940,9 @@ struct BatchHost {
     std::vector<Segment> segs;
     std::vector<LocalRun> lruns;
     std::vector<GroupDesc> groups;
-    std::vector<ClassDesc> cls;
+    std::vector<SsCls> sscls;
+    std::vector<uint32_t> sswords;
+    std::vector<SsLo> sslos;
     std::vector<uint32_t> zs;
     std::vector<double> cs;
     uint64_t state_amps = 0;
@@ -1012,9 +1029,11 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::vector<uint32_t> z;
         std::vector<double> c;
         build_groups(n, H[i], group_off[i], n_groups[i], gd, z, c);
-        std::vector<ClassDesc> sc;
-        if (n > kSigL && !gd.empty())
-            sigma_classes(gd, sc);
+        std::vector<SsCls> ssc;
+        std::vector<uint32_t> ssw;
+        std::vector<SsLo> ssl;
+        if (n > kSsL && !gd.empty())
+            sigma_stream_tables(gd, z, c, kBT, ssc, ssw, ssl);
         // forward segments on 2^min(n,12) sub-cubes, reverse on 2^min(n,11)
         // (phi and lambda share the LDS image)
         const int Bapp = std::min(n, 12), Badj = std::min(n, 11);
@@ -1046,8 +1065,14 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         e.run0 = (int32_t)T.runs.size();
         e.group0 = (int32_t)T.groups.size();
         e.term0 = (int32_t)T.zs.size();
-        e.cls0 = (int32_t)T.cls.size();
-        e.ncls = (int32_t)sc.size();
+        e.cls0 = (int32_t)T.sscls.size();
+        e.ncls = (int32_t)ssc.size();
+        e.word0 = (int32_t)T.sswords.size();
+        e.lo0 = (int32_t)T.sslos.size();
+        e.imag = 0;
+        for (const GroupDesc &g : gd)
+            if (g.k1 > g.kre)
+                e.imag = 1;
         e.tabs0 = (int32_t)T.tabs;
         e.theta0 = (int32_t)B.koff[(size_t)i];
         e.ticket0 = (int32_t)T.tickets;
@@ -1058,7 +1083,9 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.ent.push_back(e);
         T.runs.insert(T.runs.end(), r.begin(), r.end());
         T.groups.insert(T.groups.end(), gd.begin(), gd.end());
-        T.cls.insert(T.cls.end(), sc.begin(), sc.end());
+        T.sscls.insert(T.sscls.end(), ssc.begin(), ssc.end());
+        T.sswords.insert(T.sswords.end(), ssw.begin(), ssw.end());
+        T.sslos.insert(T.sslos.end(), ssl.begin(), ssl.end());
         T.zs.insert(T.zs.end(), z.begin(), z.end());
         T.cs.insert(T.cs.end(), c.begin(), c.end());
         T.state_amps += 2ull << n;
@@ -1066,7 +1093,7 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.tickets += e.W;
         T.parts += (int64_t)e.W * e.K + e.W;
         if (T.zs.size() > (size_t)INT32_MAX || T.tickets > INT32_MAX || T.parts > INT32_MAX ||
-            T.lruns.size() > (size_t)INT32_MAX || T.tabs > INT32_MAX)
+            T.lruns.size() > (size_t)INT32_MAX || T.tabs > INT32_MAX || T.sslos.size() > (size_t)INT32_MAX)
             raise(QF_E_ARG, "batch too large");
     }
     B.nentries = (int)T.ent.size();
@@ -1081,13 +1108,13 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[17];
+    size_t off[19];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[17] = {
+    const size_t sizes[19] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
@@ -1095,10 +1122,11 @@ Layout batch_layout(const qf_batch &B, const BatchHost &T)
         T.ent.size() * sizeof(unsigned),
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
-        std::max<size_t>(T.cls.size(), 1) * sizeof(ClassDesc), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2)};
+        std::max<size_t>(T.sscls.size(), 1) * sizeof(SsCls), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2),
+        std::max<size_t>(T.sswords.size(), 1) * sizeof(uint32_t), std::max<size_t>(T.sslos.size(), 1) * sizeof(SsLo)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 17; i++) {
+    for (int i = 0; i < 19; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -1123,8 +1151,10 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_grad = (double *)(base + L.off[12]);
     B.d_segs = (Segment *)(base + L.off[13]);
     B.d_lruns = (LocalRun *)(base + L.off[14]);
-    B.d_classes = (ClassDesc *)(base + L.off[15]);
+    B.d_sscls = (SsCls *)(base + L.off[15]);
     B.d_tabs = (double2 *)(base + L.off[16]);
+    B.d_sswords = (uint32_t *)(base + L.off[17]);
+    B.d_sslos = (SsLo *)(base + L.off[18]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -1145,9 +1175,12 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
                               s));
     QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
                           s));
-    if (!T.cls.empty())
-        QF_HIP(hipMemcpyAsync(B.d_classes, T.cls.data(), T.cls.size() * sizeof(ClassDesc), hipMemcpyHostToDevice,
-                              s));
+    if (!T.sscls.empty()) {
+        QF_HIP(hipMemcpyAsync(B.d_sscls, T.sscls.data(), T.sscls.size() * sizeof(SsCls), hipMemcpyHostToDevice, s));
+        QF_HIP(hipMemcpyAsync(B.d_sswords, T.sswords.data(), T.sswords.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s));
+        QF_HIP(hipMemcpyAsync(B.d_sslos, T.sslos.data(), T.sslos.size() * sizeof(SsLo), hipMemcpyHostToDevice, s));
+    }
     QF_HIP(hipMemcpyAsync(B.d_z, T.zs.data(), T.zs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     QF_HIP(hipMemcpyAsync(B.d_c, T.cs.data(), T.cs.size() * sizeof(double), hipMemcpyHostToDevice, s));
     const int64_t ng = std::max<int64_t>(B.K_total, 1);
@@ -1162,7 +1195,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_classes, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_sscls, B.d_sswords, B.d_sslos, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }

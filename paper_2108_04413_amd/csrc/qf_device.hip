@@ -873,60 +873,9 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
     reduce_finish<1>(vals, partials, counter, result, 1.0, 1);
 }
 
-// ---------------------------------------------------------------- sigma, streamed
-// lambda = H psi with the signs evaluated at the output index.  For a string
-// of real phase omega(y ^ x) = omega(y), for one of imaginary phase
-// omega(y ^ x) = -omega(y), so lambda[y] = sum_g (dre_g(y) - i dim_g(y))
-// psi[y ^ x_g] with dre, dim the sums of the folded coefficients times
-// (-1)^popcount(y & z) (host tables carry the imaginary part negated).
-// Output tiles of 2^11: with y = t 2^11 | tid | i 2^8 (256 threads, items
-// i < 8) the sign splits into (-1)^popcount(t & z_hi), uniform over the
-// tile, (-1)^popcount(tid & z_lo) per thread and (-1)^popcount(i & p),
-// p = z_lo >> 8, fixed per item.  So strings of a group part with equal z_lo
-// merge per tile into one lo-term of coefficient C(t) = sum c (-1)^popcount(t & z_hi),
-// and lo-terms sorted by z_lo come in runs of equal p: a run sums
-// a = sum C (-1)^popcount(tid & z_lo) once and adds +-a psi[y_i ^ x] to
-// the eight outputs with compile-time signs (a uniform switch on p).
-//
-// A workgroup owns one output tile at a time and walks the sub-classes
-// (groups with the same flip bits above the tile, at most 256 groups and 256
-// lo-terms each).  For each it stages the partner tile t ^ xh in LDS, with
-// one lo-term per thread (C(t) computed from the tabled strings) and one
-// group word per thread; the next sub-class's tile, lo-term and group are in
-// flight in registers meanwhile.  Waves pull lo-terms and group words 64 at
-// a time from LDS into lanes and broadcast them with readlane.
-constexpr int kSsL = 11;
+// lambda = H psi by the streamed tile routine (sigma_stream): one output tile
+// of 2^11 per workgroup at a time, 256 threads of eight items.
 constexpr int kSsNT = 256;
-constexpr int kSsWin = 256;           // groups / lo-terms per sub-class
-constexpr int kSsGrp = 64;            // lo-terms per group (larger groups are cut)
-constexpr uint32_t kSsFlush = 1u << 11;  // last lo-term of a run of equal p
-constexpr uint32_t kSsImag = 1u << 12;   // lo-term of the imaginary part
-constexpr uint32_t kSsOne = 1u << 14;    // group word: one run (pattern in bits 11..13)
-
-struct SsLo {
-    uint32_t zf;       // z_lo | kSsFlush | kSsImag
-    uint32_t zhi[3];   // z >> 11 of up to three strings, as tile-index masks
-    double c[3];       // their coefficients (0 where unused)
-    double pad;
-};
-
-struct SsCls {
-    uint32_t xh;       // partner tile t ^ xh
-    int32_t g0, l0;    // first group word / lo-term
-    int32_t ng, nl;    // counts, 1..kSsWin
-    int32_t pad[3];
-};
-
-// d_i += (-1)^popcount(i & p) a for the eight items: the item signs are
-// uniform (FMAs by +-1.0, exact)
-__device__ __forceinline__ void ss_run(double a, uint32_t p, double (&d)[8])
-{
-    const uint32_t m1 = p << 31, m2 = (p >> 1) << 31, m4 = (p >> 2) << 31;
-    const uint32_t sg[8] = {0u, m1, m2, m1 ^ m2, m4, m1 ^ m4, m2 ^ m4, m1 ^ m2 ^ m4};
-#pragma unroll
-    for (int i = 0; i < 8; i++)
-        d[i] = fma(pm_one(sg[i]), a, d[i]);
-}
 
 template <bool IMAG>
 __global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restrict__ psi, double2 *__restrict__ lam,
@@ -935,194 +884,11 @@ __global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restric
                                                         const SsLo *__restrict__ los, double *partials,
                                                         unsigned *counter, double *result)
 {
-    constexpr uint32_t T = 1u << kSsL;
-    __shared__ double2 tile[T];
-    __shared__ uint4 wlo[kSsWin];    // z_lo | flags, 0, C (lo, hi word)
-    __shared__ uint32_t wgw[kSsWin]; // x & (T - 1) | lo-term count << 16
-    const uint32_t tid = threadIdx.x, tid16 = tid << 4;
-    const int lane = (int)(tid & 63u);
-    const uint32_t ntiles = 1u << (n - kSsL);
-    double acc = 0.0;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        double2 l[8];
-#pragma unroll
-        for (int i = 0; i < 8; i++)
-            l[i] = make_double2(0.0, 0.0);
-        // sub-class in flight: its tile, lo-term and group word (raw loads;
-        // named values: an array carried around the loop went to scratch)
-        double2 p0, p1, p2, p3, p4, p5, p6, p7;
-        uint32_t zfn, zh0, zh1, zh2, gwn;
-        double c0, c1, c2;
-        SsCls cn = cls[0];
-        auto fetch = [&]() __attribute__((always_inline)) {
-            const double2 *src = psi + ((size_t)(t ^ cn.xh) << kSsL) + tid;
-            p0 = src[0];
-            p1 = src[1u << 8];
-            p2 = src[2u << 8];
-            p3 = src[3u << 8];
-            p4 = src[4u << 8];
-            p5 = src[5u << 8];
-            p6 = src[6u << 8];
-            p7 = src[7u << 8];
-            const SsLo &r = los[cn.l0 + min((int)tid, cn.nl - 1)];
-            zfn = r.zf;
-            zh0 = r.zhi[0];
-            zh1 = r.zhi[1];
-            zh2 = r.zhi[2];
-            c0 = r.c[0];
-            c1 = r.c[1];
-            c2 = r.c[2];
-            gwn = gwords[cn.g0 + min((int)tid, cn.ng - 1)];
-        };
-        fetch();
-        for (int c = 0; c < ncls; c++) {
-            const int ng = cn.ng;
-            __syncthreads();  // the previous sub-class's LDS reads are done
-            tile[tid] = p0;
-            tile[tid + (1u << 8)] = p1;
-            tile[tid + (2u << 8)] = p2;
-            tile[tid + (3u << 8)] = p3;
-            tile[tid + (4u << 8)] = p4;
-            tile[tid + (5u << 8)] = p5;
-            tile[tid + (6u << 8)] = p6;
-            tile[tid + (7u << 8)] = p7;
-            {
-                const double C = flip(c0, par(t & zh0)) + flip(c1, par(t & zh1)) + flip(c2, par(t & zh2));
-                wlo[tid] = make_uint4(zfn, 0u, (uint32_t)__double2loint(C), (uint32_t)__double2hiint(C));
-                wgw[tid] = gwn;
-            }
-            __syncthreads();
-            cn = cls[c + 1 < ncls ? c + 1 : c];
-            fetch();  // unconditional: the last sub-class fetches itself again
-            int jw = 0;
-            uint4 lch = make_uint4(0u, 0u, 0u, 0u);
-            uint32_t gch = 0u;
-            for (int g = 0; g < ng; g++) {
-                if ((g & 63) == 0)
-                    gch = wgw[g + lane];
-                const uint32_t gw = (uint32_t)__builtin_amdgcn_readlane((int)gch, g & 63);
-                const int nlo = (int)(gw >> 16);
-                // the group's lo-terms, one per lane (at most 64; lanes past
-                // them read entries that are not used)
-                lch = wlo[min(jw + lane, kSsWin - 1)];
-                jw += nlo;
-                const uint32_t base = tid16 ^ ((gw & (T - 1u)) << 4);
-                auto row = [&](int i) __attribute__((always_inline)) {
-                    return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tile) +
-                                                              (base ^ ((uint32_t)i << 12)));
-                };
-                double a = 0.0;
-                if constexpr (IMAG) {
-                    double2 b[8];
-#pragma unroll
-                    for (int i = 0; i < 8; i++)
-                        b[i] = row(i);
-                    // D at the eight outputs: dr + i di
-                    double dr[8], di[8];
-#pragma unroll
-                    for (int i = 0; i < 8; i++) {
-                        dr[i] = 0.0;
-                        di[i] = 0.0;
-                    }
-                    for (int k = 0; k < nlo; k++) {
-                        const uint32_t zf = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
-                        const double C = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
-                                                          __builtin_amdgcn_readlane((int)lch.z, k));
-                        a = fma(pm_one((uint32_t)__popc(tid & zf) << 31), C, a);
-                        if (zf & kSsFlush) {
-                            if (zf & kSsImag)
-                                ss_run(a, (zf >> 8) & 7u, di);
-                            else
-                                ss_run(a, (zf >> 8) & 7u, dr);
-                            a = 0.0;
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 8; i++) {
-                        l[i].x = fma(dr[i], b[i].x, l[i].x);
-                        l[i].y = fma(dr[i], b[i].y, l[i].y);
-                        l[i].x = fma(-di[i], b[i].y, l[i].x);
-                        l[i].y = fma(di[i], b[i].x, l[i].y);
-                    }
-                } else {
-                    // partner rows of the first four items in flight during
-                    // the lo-terms; the other four are read after the first
-                    // four outputs are updated (fewer live registers)
-                    double2 b[4];
-#pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        b[i] = row(i);
-                    // D at the eight outputs; a group of one run (one phase
-                    // part, one item pattern) signs its one sum at the end
-                    double d[8];
-                    if (gw & kSsOne) {
-                        // lo-terms two at a time into two sums
-                        double a2 = 0.0;
-                        int k = 0;
-                        for (; k + 1 < nlo; k += 2) {
-                            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
-                            const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k + 1);
-                            const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
-                                                               __builtin_amdgcn_readlane((int)lch.z, k));
-                            const double C1 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k + 1),
-                                                               __builtin_amdgcn_readlane((int)lch.z, k + 1));
-                            a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
-                            a2 = fma(pm_one((uint32_t)__popc(tid & z1) << 31), C1, a2);
-                        }
-                        if (k < nlo) {
-                            const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
-                            const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
-                                                               __builtin_amdgcn_readlane((int)lch.z, k));
-                            a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
-                        }
-                        a += a2;
-                        const uint32_t p = (gw >> 11) & 7u;
-                        const uint32_t m1 = p << 31, m2 = (p >> 1) << 31, m4 = (p >> 2) << 31;
-                        const uint32_t sg[8] = {0u, m1, m2, m1 ^ m2, m4, m1 ^ m4, m2 ^ m4, m1 ^ m2 ^ m4};
-#pragma unroll
-                        for (int i = 0; i < 8; i++)
-                            d[i] = pm_one(sg[i]) * a;
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 8; i++)
-                            d[i] = 0.0;
-                        for (int k = 0; k < nlo; k++) {
-                            const uint32_t zf = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
-                            const double C = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
-                                                              __builtin_amdgcn_readlane((int)lch.z, k));
-                            a = fma(pm_one((uint32_t)__popc(tid & zf) << 31), C, a);
-                            if (zf & kSsFlush) {
-                                ss_run(a, (zf >> 8) & 7u, d);
-                                a = 0.0;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        l[i].x = fma(d[i], b[i].x, l[i].x);
-                        l[i].y = fma(d[i], b[i].y, l[i].y);
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        b[i] = row(i + 4);
-#pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        l[i + 4].x = fma(d[i + 4], b[i].x, l[i + 4].x);
-                        l[i + 4].y = fma(d[i + 4], b[i].y, l[i + 4].y);
-                    }
-                }
-            }
-        }
-        const size_t tb = (size_t)t << kSsL;
-#pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const size_t y = tb + tid + ((uint32_t)i << 8);
-            const double2 p = psi[y];
-            lam[y] = l[i];
-            acc += p.x * l[i].x + p.y * l[i].y;
-        }
-    }
-    double vals[1] = {acc};
+    __shared__ double2 tile[1u << kSsL];
+    __shared__ uint4 wlo[kSsNT];    // z_lo | flags, 0, C (lo, hi word)
+    __shared__ uint32_t wgw[kSsNT]; // x & (2^11 - 1) | one-run pattern | lo-term count << 16
+    double vals[1] = {sigma_stream<kSsNT, IMAG>(psi, lam, blockIdx.x, gridDim.x, 1u << (n - kSsL), cls, ncls,
+                                                gwords, los, tile, wlo, wgw)};
     reduce_finish<1, kSsNT>(vals, partials, counter, result, 1.0, 1);
 }
 
@@ -1568,35 +1334,22 @@ uint32_t pext32(uint32_t v, uint32_t mask)
 
 } // namespace
 
-void sigma_classes(std::vector<GroupDesc> &gd, std::vector<ClassDesc> &cls)
-{
-    std::stable_sort(gd.begin(), gd.end(),
-                     [](const GroupDesc &a, const GroupDesc &b) { return (a.x >> kSigL) < (b.x >> kSigL); });
-    cls.clear();
-    for (size_t g = 0; g < gd.size(); g++) {
-        const uint32_t xh = gd[g].x >> kSigL;
-        if (cls.empty() || cls.back().xh != xh) {
-            ClassDesc c;
-            c.xh = xh;
-            c.hb = hibit(xh);
-            c.g0 = c.g1 = (int32_t)g;
-            cls.push_back(c);
-        }
-        cls.back().g1 = (int32_t)g + 1;
-    }
-}
-
-// Tables of k_sigma_stream: groups in class order, each group part's strings
-// sorted by (z_lo, z_hi) and merged into lo-terms of equal z_lo (at most three
-// strings each; longer runs continue in the next lo-term), the imaginary
-// part's coefficients negated (signs taken at the output index), a flush
-// flag on the last lo-term of every run of equal item pattern z_lo >> 8.
-// A group of more than kSsGrp lo-terms is cut into groups of the same flip
-// mask; sub-classes hold at most kSsWin groups and kSsWin lo-terms.
+// Tables of the streamed sigma (sigma_stream) for workgroups of nt threads
+// (256 or 512; item pattern p = z_lo >> log2(nt)): groups in class order,
+// each group part's strings sorted by (z_lo, z_hi) and merged into lo-terms
+// of equal z_lo (at most three strings each; longer runs continue in the
+// next lo-term), the imaginary part's coefficients negated (signs taken at
+// the output index), a flush flag on the last lo-term of every run of equal
+// p.  A group of more than kSsGrp lo-terms is cut into groups of the same
+// flip mask; sub-classes hold at most nt groups and nt lo-terms.  Group
+// words: x & (2^11 - 1), the one-run flag and pattern, the lo-term count.
 void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uint32_t> &zs,
-                         const std::vector<double> &cs, std::vector<SsCls> &cls, std::vector<uint32_t> &words,
-                         std::vector<SsLo> &los)
+                         const std::vector<double> &cs, int nt, std::vector<SsCls> &cls,
+                         std::vector<uint32_t> &words, std::vector<SsLo> &los)
 {
+    if (nt != 256 && nt != 512)
+        raise(QF_E_ARG, "streamed sigma tables: 256 or 512 threads");
+    const int ps = nt == 256 ? 8 : 9;
     constexpr uint32_t lomask = (1u << kSsL) - 1u;
     std::vector<size_t> order(gd.size());
     std::iota(order.begin(), order.end(), (size_t)0);
@@ -1634,7 +1387,7 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
                 used++;
             }
             for (size_t j = first; j < lg.size(); j++)
-                if (j + 1 == lg.size() || ((lg[j + 1].zf & lomask) >> 8) != ((lg[j].zf & lomask) >> 8))
+                if (j + 1 == lg.size() || ((lg[j + 1].zf & lomask) >> ps) != ((lg[j].zf & lomask) >> ps))
                     lg[j].zf |= kSsFlush;
         }
         for (size_t p0 = 0; p0 < lg.size(); p0 += kSsGrp) {
@@ -1642,7 +1395,7 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
             lg[p1 - 1].zf |= kSsFlush;
             const uint32_t xh = g.x >> kSsL;
             const int32_t nl = (int32_t)(p1 - p0);
-            if (cls.empty() || cls.back().xh != xh || cls.back().ng == kSsWin || cls.back().nl + nl > kSsWin) {
+            if (cls.empty() || cls.back().xh != xh || cls.back().ng == nt || cls.back().nl + nl > nt) {
                 SsCls c;
                 std::memset(&c, 0, sizeof c);
                 c.xh = xh;
@@ -1653,8 +1406,8 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
             // one run: every lo-term of the piece is real with one item pattern
             bool one = true;
             for (size_t j = p0; j < p1; j++)
-                one = one && !(lg[j].zf & kSsImag) && ((lg[j].zf & lomask) >> 8) == ((lg[p0].zf & lomask) >> 8);
-            const uint32_t pat = one ? (((lg[p0].zf & lomask) >> 8) << 11) | kSsOne : 0u;
+                one = one && !(lg[j].zf & kSsImag) && ((lg[j].zf & lomask) >> ps) == ((lg[p0].zf & lomask) >> ps);
+            const uint32_t pat = one ? (((lg[p0].zf & lomask) >> ps) << 11) | kSsOne : 0u;
             words.push_back((g.x & lomask) | pat | ((uint32_t)nl << 16));
             los.insert(los.end(), lg.begin() + (ptrdiff_t)p0, lg.begin() + (ptrdiff_t)p1);
             cls.back().ng++;
@@ -2130,11 +1883,11 @@ void plan_init(qf_plan &P, int n, const qf_term *A, int64_t K, const qf_term *H,
         P.groups = gd;
         P.hz = zs;
         P.hc = cs;
-        if (n > kSigL && P.sigma_tables) {
+        if (n > kSsL && P.sigma_tables) {
             std::vector<SsCls> ssc;
             std::vector<uint32_t> ssw;
             std::vector<SsLo> ssl;
-            sigma_stream_tables(gd, zs, cs, ssc, ssw, ssl);
+            sigma_stream_tables(gd, zs, cs, kSsNT, ssc, ssw, ssl);
             P.d_ss_cls = P.dalloc<SsCls>(ssc.size());
             P.d_ss_words = P.dalloc<uint32_t>(ssw.size());
             P.d_ss_los = P.dalloc<SsLo>(ssl.size());

@@ -58,9 +58,11 @@ std::vector<RunDesc> make_runs(const qf_term *T, int64_t K, int &tab_entries);
 void build_groups(int n, const qf_term *H, const int64_t *goff, int64_t G, std::vector<GroupDesc> &gd,
                   std::vector<uint32_t> &zs, std::vector<double> &cs);
 
-// Sort groups (stably) by their flip bits above the sigma tile, bit kSigL
-// and up, and list the classes of equal bits as ranges of the sorted order.
-void sigma_classes(std::vector<GroupDesc> &gd, std::vector<ClassDesc> &cls);
+// Tables of the streamed sigma for workgroups of nt (256 or 512) threads:
+// sub-classes, group words and lo-terms (see qf_device.hip).
+void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uint32_t> &zs,
+                         const std::vector<double> &cs, int nt, std::vector<SsCls> &cls,
+                         std::vector<uint32_t> &words, std::vector<SsLo> &los);
 
 // Greedy split of a run sequence into segments whose flip masks fit one set
 // of B qubits containing qubits 0..q0-1 (see qf_device.hip); appends the

@@ -451,127 +451,250 @@ __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__r
     }
 }
 
-// Sigma over tiles of 2^kSigL outputs: groups whose flip masks agree above
-// bit kSigL form a class (ClassDesc, groups in class order), and for output
-// tile t every group of class c reads its partner amplitudes psi[y ^ x] from
-// the one tile t ^ xh_c.  That tile is staged in LDS once per class
-// (double-buffered: the next class's tile is in flight in registers while
-// this class is evaluated), so the state crosses HBM once per class instead
-// of being gathered once per group.  A thread of the kSigNT-thread workgroup
-// owns outputs tb | tid | 512 i (i < 4); D_g is evaluated at the partner
-// index.  The workgroup takes tiles t0, t0 + dt, ... below ntiles, writes
-// lam over them and returns the thread's share of <psi|lam> on them.  sp:
-// two LDS buffers of 2^kSigL amplitudes; each tile ends with a workgroup
-// barrier, after which sp may be reused.
-constexpr int kSigL = 11;
-constexpr int kSigNT = 512;
+// ---------------------------------------------------------------- sigma, streamed
+// lambda = H psi with the signs evaluated at the output index.  For a string
+// of real phase omega(y ^ x) = omega(y), for one of imaginary phase
+// omega(y ^ x) = -omega(y), so lambda[y] = sum_g (dre_g(y) - i dim_g(y))
+// psi[y ^ x_g] with dre, dim the sums of the folded coefficients times
+// (-1)^popcount(y & z) (host tables carry the imaginary part negated).
+// Output tiles of 2^11: with y = t 2^11 | tid | i NT (NT threads, NI = 2^11 /
+// NT items) the sign splits into (-1)^popcount(t & z_hi), uniform over the
+// tile, (-1)^popcount(tid & z_lo) per thread and (-1)^popcount(i & p),
+// p = z_lo >> log2(NT), fixed per item.  So strings of a group part with
+// equal z_lo merge per tile into one lo-term of coefficient
+// C(t) = sum c (-1)^popcount(t & z_hi), and lo-terms sorted by z_lo come in
+// runs of equal p: a run sums a = sum C (-1)^popcount(tid & z_lo) once and
+// adds +-a to the items' coefficients (uniform signs).
+//
+// The caller's workgroup owns one output tile at a time (t0, t0 + dt, ...)
+// and walks the sub-classes (groups with the same flip bits above the tile,
+// at most NT groups and NT lo-terms each).  For each it stages the partner
+// tile t ^ xh in LDS, with one lo-term per thread (C(t) computed from the
+// tabled strings) and one group word per thread; the next sub-class's tile,
+// lo-term and group word are in flight in registers meanwhile.  Waves pull a
+// group's lo-terms (at most 64) into lanes with one LDS read and broadcast
+// them by readlane.  LDS: tile (2^11 amplitudes), wlo (NT entries), wgw (NT
+// words); each sub-class ends with the workgroup at a barrier, after which
+// they may be reused.  Returns the thread's share of Re <psi|lambda>.
+constexpr int kSsL = 11;
+constexpr int kSsGrp = 64;               // lo-terms per group (larger groups are cut)
+constexpr uint32_t kSsFlush = 1u << 11;  // last lo-term of a run of equal p
+constexpr uint32_t kSsImag = 1u << 12;   // lo-term of the imaginary part
+constexpr uint32_t kSsOne = 1u << 14;    // group word: one run (pattern in bits 11..13)
 
-__device__ __forceinline__ double sigma_tiles(const double2 *__restrict__ psi, double2 *__restrict__ lam,
-                                              uint32_t t0, uint32_t dt, uint32_t ntiles,
-                                              const ClassDesc *__restrict__ classes, int ncls,
-                                              const GroupDesc *__restrict__ groups, int G,
-                                              const uint32_t *__restrict__ zs, const double *__restrict__ cs,
-                                              double2 (*__restrict__ sp)[1u << kSigL])
+struct SsLo {
+    uint32_t zf;       // z_lo | kSsFlush | kSsImag
+    uint32_t zhi[3];   // z >> 11 of up to three strings, as tile-index masks
+    double c[3];       // their coefficients (0 where unused)
+    double pad;
+};
+
+struct SsCls {
+    uint32_t xh;       // partner tile t ^ xh
+    int32_t g0, l0;    // first group word / lo-term
+    int32_t ng, nl;    // counts, 1..NT
+    int32_t pad[3];
+};
+
+// the NI item signs (-1)^popcount(i & p) as sign-bit words
+template <int NI>
+__device__ __forceinline__ void ss_signs(uint32_t p, uint32_t (&sg)[NI])
 {
-    constexpr uint32_t T = 1u << kSigL;
-    constexpr int IT = (int)(T / kSigNT);
-    static_assert(IT == 4 && kSigNT == kItemStride, "four outputs 512 apart per thread");
-    const uint32_t tid = threadIdx.x;
+    const uint32_t m1 = p << 31, m2 = (p >> 1) << 31, m4 = (p >> 2) << 31;
+    const uint32_t all[8] = {0u, m1, m2, m1 ^ m2, m4, m1 ^ m4, m2 ^ m4, m1 ^ m2 ^ m4};
+#pragma unroll
+    for (int i = 0; i < NI; i++)
+        sg[i] = all[i];
+}
+
+// a = sum over the group's lo-terms k0 <= k < k1 (lanes of lch) of
+// C (-1)^popcount(tid & z_lo), two at a time into two sums
+__device__ __forceinline__ double ss_sum(const uint4 &lch, int nlo, uint32_t tid)
+{
+    double a = 0.0, a2 = 0.0;
+    int k = 0;
+    for (; k + 1 < nlo; k += 2) {
+        const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+        const uint32_t z1 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k + 1);
+        const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                           __builtin_amdgcn_readlane((int)lch.z, k));
+        const double C1 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k + 1),
+                                           __builtin_amdgcn_readlane((int)lch.z, k + 1));
+        a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
+        a2 = fma(pm_one((uint32_t)__popc(tid & z1) << 31), C1, a2);
+    }
+    if (k < nlo) {
+        const uint32_t z0 = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+        const double C0 = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                           __builtin_amdgcn_readlane((int)lch.z, k));
+        a = fma(pm_one((uint32_t)__popc(tid & z0) << 31), C0, a);
+    }
+    return a + a2;
+}
+
+template <int NT, bool IMAG>
+__device__ __forceinline__ double sigma_stream(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                               uint32_t t0, uint32_t dt, uint32_t ntiles,
+                                               const SsCls *__restrict__ cls, int ncls,
+                                               const uint32_t *__restrict__ gwords, const SsLo *__restrict__ los,
+                                               double2 *__restrict__ tile, uint4 *__restrict__ wlo,
+                                               uint32_t *__restrict__ wgw)
+{
+    constexpr uint32_t T = 1u << kSsL;
+    constexpr int NI = (int)(T / NT);
+    constexpr int IS = NT == 256 ? 8 : 9;  // item i is bit IS and up of the tile index
+    static_assert((NT == 256 && NI == 8) || (NT == 512 && NI == 4), "2^11 outputs per tile");
+    // item rows read per step: all of them, or two halves of four (eight items:
+    // fewer live registers)
+    constexpr int NH = NI == 8 ? 4 : NI;
+    const uint32_t tid = threadIdx.x, tid16 = tid << 4;
     const int lane = (int)(tid & 63u);
     double acc = 0.0;
     for (uint32_t t = t0; t < ntiles; t += dt) {
-        const uint32_t tb = t << kSigL;
-        double2 l[IT];
+        double2 l[NI];
 #pragma unroll
-        for (int i = 0; i < IT; i++)
+        for (int i = 0; i < NI; i++)
             l[i] = make_double2(0.0, 0.0);
-        // the next partner tile, in flight in registers (four named values: an
-        // array carried around the class loop was put in scratch memory)
-        const uint32_t pb0 = (t ^ classes[0].xh) << kSigL;
-        double2 p0 = psi[pb0 | tid], p1 = psi[pb0 | (tid + kSigNT)], p2 = psi[pb0 | (tid + 2 * kSigNT)],
-                p3 = psi[pb0 | (tid + 3 * kSigNT)];
-        // Group descriptors reach the wave 64 at a time, one per lane (coalesced
-        // vector loads), and are broadcast by readlane: a scalar load per group
-        // from a table larger than the scalar cache left the pass latency-bound
-        // (~2500 clocks per group).  Strings are scalar loads (a readlane
-        // broadcast of them costs three VALU per string, which measured slower).
-        int gc = 0;
-        uint32_t gxv = 0;
-        int gk0v = 0, gkrev = 0, gk1v = 0, gpatv = 0;
-        auto load_groups = [&](int g) __attribute__((always_inline)) {
-            gc = g;
-            const GroupDesc d = groups[min(g + lane, G - 1)];
-            gxv = d.x;
-            gk0v = d.k0;
-            gkrev = d.kre;
-            gk1v = d.k1;
-            gpatv = d.pat;
-        };
-        load_groups(0);
-        for (int c = 0; c < ncls; c++) {
-            double2 *buf = sp[c & 1];
-            buf[tid] = p0;
-            buf[tid + kSigNT] = p1;
-            buf[tid + 2 * kSigNT] = p2;
-            buf[tid + 3 * kSigNT] = p3;
-            const ClassDesc cd = classes[c];
-            {
-                // unconditional: the last class fetches its own tile again
-                const uint32_t pb = (t ^ classes[c + 1 < ncls ? c + 1 : c].xh) << kSigL;
-                p0 = psi[pb | tid];
-                p1 = psi[pb | (tid + kSigNT)];
-                p2 = psi[pb | (tid + 2 * kSigNT)];
-                p3 = psi[pb | (tid + 3 * kSigNT)];
+        // sub-class in flight: its tile, lo-term and group word (raw loads;
+        // named values: an array carried around the loop went to scratch)
+        double2 p0, p1, p2, p3, p4, p5, p6, p7;
+        uint32_t zfn, zh0, zh1, zh2, gwn;
+        double c0, c1, c2;
+        SsCls cn = cls[0];
+        auto fetch = [&]() __attribute__((always_inline)) {
+            const double2 *src = psi + ((size_t)(t ^ cn.xh) << kSsL) + tid;
+            p0 = src[0];
+            p1 = src[1u << IS];
+            p2 = src[2u << IS];
+            p3 = src[3u << IS];
+            if constexpr (NI == 8) {
+                p4 = src[4u << IS];
+                p5 = src[5u << IS];
+                p6 = src[6u << IS];
+                p7 = src[7u << IS];
             }
-            // buf is complete; its previous readers (class c - 2) passed the
-            // barrier of class c - 1 before anyone writes it again
+            const SsLo &r = los[cn.l0 + min((int)tid, cn.nl - 1)];
+            zfn = r.zf;
+            zh0 = r.zhi[0];
+            zh1 = r.zhi[1];
+            zh2 = r.zhi[2];
+            c0 = r.c[0];
+            c1 = r.c[1];
+            c2 = r.c[2];
+            gwn = gwords[cn.g0 + min((int)tid, cn.ng - 1)];
+        };
+        fetch();
+        for (int c = 0; c < ncls; c++) {
+            const int ng = cn.ng;
+            __syncthreads();  // the previous sub-class's LDS reads are done
+            tile[tid] = p0;
+            tile[tid + (1u << IS)] = p1;
+            tile[tid + (2u << IS)] = p2;
+            tile[tid + (3u << IS)] = p3;
+            if constexpr (NI == 8) {
+                tile[tid + (4u << IS)] = p4;
+                tile[tid + (5u << IS)] = p5;
+                tile[tid + (6u << IS)] = p6;
+                tile[tid + (7u << IS)] = p7;
+            }
+            {
+                const double C = flip(c0, par(t & zh0)) + flip(c1, par(t & zh1)) + flip(c2, par(t & zh2));
+                wlo[tid] = make_uint4(zfn, 0u, (uint32_t)__double2loint(C), (uint32_t)__double2hiint(C));
+                wgw[tid] = gwn;
+            }
             __syncthreads();
-            for (int g = cd.g0; g < cd.g1; g++) {
-                if (g - gc >= 64)
-                    load_groups(g);
-                const int jg = g - gc;
-                const uint32_t gx = (uint32_t)__builtin_amdgcn_readlane((int)gxv, jg);
-                const int k0 = __builtin_amdgcn_readlane(gk0v, jg);
-                const int kre = __builtin_amdgcn_readlane(gkrev, jg);
-                const int k1 = __builtin_amdgcn_readlane(gk1v, jg);
-                const int pat = __builtin_amdgcn_readlane(gpatv, jg);
-                const uint32_t xl = gx & (T - 1u);
-                const uint32_t Y = (tb | tid) ^ gx;
-                double dre[IT], dimg[IT];
+            cn = cls[c + 1 < ncls ? c + 1 : c];
+            fetch();  // unconditional: the last sub-class fetches itself again
+            int jw = 0;
+            uint4 lch = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t gch = 0u;
+            for (int g = 0; g < ng; g++) {
+                if ((g & 63) == 0)
+                    gch = wgw[g + lane];
+                const uint32_t gw = (uint32_t)__builtin_amdgcn_readlane((int)gch, g & 63);
+                const int nlo = (int)(gw >> 16);
+                // the group's lo-terms, one per lane (lanes past them read
+                // entries that are not used)
+                lch = wlo[min(jw + lane, NT - 1)];
+                jw += nlo;
+                const uint32_t base = tid16 ^ ((gw & (T - 1u)) << 4);
+                auto row = [&](int i) __attribute__((always_inline)) {
+                    return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tile) +
+                                                              (base ^ ((uint32_t)i << (IS + 4))));
+                };
+                double2 b[NH];
 #pragma unroll
-                for (int i = 0; i < IT; i++) {
-                    dre[i] = 0.0;
-                    dimg[i] = 0.0;
-                }
-                static_assert(kSigL - 2 == kPatBit, "items 2^(kSigL - 2) apart");
-                group_d4_part_pat(k0, kre, pat & 15, zs, cs, Y, dre);
-                if (k1 > kre) {
-                    group_d4_part_pat(kre, k1, (pat >> 4) & 15, zs, cs, Y, dimg);
+                for (int i = 0; i < NH; i++)
+                    b[i] = row(i);
+                // the items' coefficients: dr + i di
+                double dr[NI], di[IMAG ? NI : 1];
+                if (!IMAG && (gw & kSsOne)) {
+                    // one run (one phase part, one item pattern): sign its sum
+                    const double a = ss_sum(lch, nlo, tid);
+                    uint32_t sg[NI];
+                    ss_signs<NI>((gw >> 11) & 7u, sg);
 #pragma unroll
-                    for (int i = 0; i < IT; i++) {
-                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                        l[i].x += dre[i] * b.x - dimg[i] * b.y;
-                        l[i].y += dre[i] * b.y + dimg[i] * b.x;
+                    for (int i = 0; i < NI; i++)
+                        dr[i] = pm_one(sg[i]) * a;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NI; i++) {
+                        dr[i] = 0.0;
+                        if (IMAG)
+                            di[IMAG ? i : 0] = 0.0;
                     }
-                } else {  // real phases only (every string of a real Hamiltonian)
+                    double a = 0.0;
+                    for (int k = 0; k < nlo; k++) {
+                        const uint32_t zf = (uint32_t)__builtin_amdgcn_readlane((int)lch.x, k);
+                        const double C = __hiloint2double(__builtin_amdgcn_readlane((int)lch.w, k),
+                                                          __builtin_amdgcn_readlane((int)lch.z, k));
+                        a = fma(pm_one((uint32_t)__popc(tid & zf) << 31), C, a);
+                        if (zf & kSsFlush) {
+                            uint32_t sg[NI];
+                            ss_signs<NI>((zf >> IS) & 7u, sg);
+                            if (IMAG && (zf & kSsImag)) {
 #pragma unroll
-                    for (int i = 0; i < IT; i++) {
-                        const double2 b = buf[(tid + (uint32_t)i * kSigNT) ^ xl];
-                        l[i].x += dre[i] * b.x;
-                        l[i].y += dre[i] * b.y;
+                                for (int i = 0; i < NI; i++)
+                                    di[IMAG ? i : 0] = fma(pm_one(sg[i]), a, di[IMAG ? i : 0]);
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < NI; i++)
+                                    dr[i] = fma(pm_one(sg[i]), a, dr[i]);
+                            }
+                            a = 0.0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < NI; h += NH) {
+                    if (h > 0) {
+#pragma unroll
+                        for (int i = 0; i < NH; i++)
+                            b[i] = row(h + i);
+                    }
+#pragma unroll
+                    for (int i = 0; i < NH; i++) {
+                        l[h + i].x = fma(dr[h + i], b[i].x, l[h + i].x);
+                        l[h + i].y = fma(dr[h + i], b[i].y, l[h + i].y);
+                        if (IMAG) {
+                            l[h + i].x = fma(-di[IMAG ? h + i : 0], b[i].y, l[h + i].x);
+                            l[h + i].y = fma(di[IMAG ? h + i : 0], b[i].x, l[h + i].y);
+                        }
                     }
                 }
             }
         }
+        const size_t tb = (size_t)t << kSsL;
 #pragma unroll
-        for (int i = 0; i < IT; i++) {
-            const uint32_t y = tb | (tid + (uint32_t)i * kSigNT);
-            lam[y] = l[i];
+        for (int i = 0; i < NI; i++) {
+            const size_t y = tb + tid + ((uint32_t)i << IS);
             const double2 p = psi[y];
+            lam[y] = l[i];
             acc += p.x * l[i].x + p.y * l[i].y;
         }
-        __syncthreads();  // the last class's buffer is read before sp is written again
     }
+    // the workgroup's last LDS reads are done before the caller reuses it
+    __syncthreads();
     return acc;
 }
 
