@@ -92,17 +92,15 @@ __global__ __launch_bounds__(kBlock) void k_sector_prepare(double2 *__restrict__
 __global__ __launch_bounds__(kSecT) void k_sector_rotate(double2 *__restrict__ psi, const uint32_t *__restrict__ strA,
                                                          const uint32_t *__restrict__ strB,
                                                          const uint32_t *__restrict__ rankA,
-                                                         const uint32_t *__restrict__ rankB, uint32_t DA,
-                                                         uint32_t DB, SecExc e, double cs, double sn)
+                                                         const uint32_t *__restrict__ rankB, const uint32_t *__restrict__ rows,
+                                                         uint32_t nrows, uint32_t DB, SecExc e, double cs, double sn)
 {
     const uint32_t nchunk = (DB + kSecT - 1) / kSecT;
-    const uint64_t ntiles = (uint64_t)DA * nchunk;
+    const uint64_t ntiles = (uint64_t)nrows * nchunk;
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t ia = (uint32_t)(t / nchunk), ch = (uint32_t)(t % nchunk);
+        // the alpha strings of the domain of tau (host list)
+        const uint32_t ia = rows[(uint32_t)(t / nchunk)], ch = (uint32_t)(t % nchunk);
         const uint32_t a = strA[ia];
-        // uniform: is this alpha string in the domain of tau?
-        if ((a & e.annA) != e.annA || (a & e.creA) != 0u)
-            continue;
         const uint32_t a2 = a ^ e.annA ^ e.creA;
         const uint32_t ia2 = rankA[a2];
         const uint32_t ib = ch * kSecT + threadIdx.x;
@@ -253,6 +251,25 @@ __device__ __forceinline__ void sector_reduce(double v, double *partials, unsign
     }
 }
 
+// Fixed-order block sum of one value into out (thread 0 stores it; no
+// cross-workgroup step: k_sector_grad_reduce adds the workgroups later).
+__device__ __forceinline__ void sector_block_sum(double v, double *out)
+{
+    __shared__ double lds[kSecT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if (lane == 0)
+        lds[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bsum = 0.0;
+        for (int w = 0; w < kSecT / 64; w++)
+            bsum += lds[w];
+        *out = bsum;
+    }
+}
+
 __global__ __launch_bounds__(kSecT) void k_sector_sigma(const double2 *__restrict__ psi, double2 *__restrict__ lam,
                                                         const uint32_t *__restrict__ strA,
                                                         const uint32_t *__restrict__ strB,
@@ -314,18 +331,17 @@ __global__ __launch_bounds__(kSecT) void k_sector_adjoint(double2 *__restrict__ 
                                                           const uint32_t *__restrict__ strA,
                                                           const uint32_t *__restrict__ strB,
                                                           const uint32_t *__restrict__ rankA,
-                                                          const uint32_t *__restrict__ rankB, uint32_t DA,
+                                                          const uint32_t *__restrict__ rankB,
+                                                          const uint32_t *__restrict__ rows, uint32_t nrows,
                                                           uint32_t DB, SecExc e, double cs, double sn,
-                                                          double *partials, unsigned *counter, double *grad_out)
+                                                          double *part)
 {
     double acc = 0.0;
     const uint32_t nchunk = (DB + kSecT - 1) / kSecT;
-    const uint64_t ntiles = (uint64_t)DA * nchunk;
+    const uint64_t ntiles = (uint64_t)nrows * nchunk;
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t ia = (uint32_t)(t / nchunk), ch = (uint32_t)(t % nchunk);
+        const uint32_t ia = rows[(uint32_t)(t / nchunk)], ch = (uint32_t)(t % nchunk);
         const uint32_t a = strA[ia];
-        if ((a & e.annA) != e.annA || (a & e.creA) != 0u)
-            continue;
         const uint32_t ia2 = rankA[a ^ e.annA ^ e.creA];
         const uint32_t ib = ch * kSecT + threadIdx.x;
         if (ib >= DB)
@@ -355,7 +371,22 @@ __global__ __launch_bounds__(kSecT) void k_sector_adjoint(double2 *__restrict__ 
         lam[i1] = make_double2(cs * lu.x + s * lv.x, cs * lu.y + s * lv.y);
         lam[i2] = make_double2(cs * lv.x - s * lu.x, cs * lv.y - s * lu.y);
     }
-    sector_reduce(2.0 * acc, partials, counter, grad_out);
+    sector_block_sum(2.0 * acc, part + blockIdx.x);
+}
+
+// dE/dt of every excitation: the sum of its workgroups' partials
+// part[part0[m] .. part0[m + 1]) in workgroup order
+__global__ __launch_bounds__(kSecT) void k_sector_grad_reduce(const double *__restrict__ part,
+                                                              const uint32_t *__restrict__ part0, int E,
+                                                              double *__restrict__ grad)
+{
+    const int m = blockIdx.x * kSecT + threadIdx.x;
+    if (m >= E)
+        return;
+    double v = 0.0;
+    for (uint32_t b = part0[m]; b < part0[m + 1]; b++)
+        v += part[b];
+    grad[m] = v;
 }
 
 uint32_t compact(uint64_t so, int spin, int n_orb)
@@ -381,9 +412,18 @@ struct qf_sector {
     unsigned *d_counter = nullptr;
     double *d_grad = nullptr;  // dE/dt of the last gradient call
     size_t grad_cap = 0;
+    // per excitation, the alpha strings of its domain (rows[row0[m] ..
+    // row0[m + 1]), alpha-string indices): launches cover those rows only
+    std::vector<uint32_t> row0;
+    uint32_t *d_rows = nullptr;
+    // per excitation, its adjoint workgroups' partial sums part[part0[m] ..]
+    std::vector<uint32_t> part0;
+    uint32_t *d_part0 = nullptr;
+    double *d_part = nullptr;
     ~qf_sector()
     {
-        void *bufs[] = {d_strA, d_strB, d_rankA, d_rankB, d_groups, d_strs, d_partials, d_result, d_counter, d_grad};
+        void *bufs[] = {d_strA, d_strB, d_rankA, d_rankB, d_groups, d_strs, d_partials, d_result, d_counter, d_grad,
+                        d_rows, d_part0, d_part};
         for (void *p : bufs)
             if (p)
                 (void)hipFree(p);
@@ -500,6 +540,27 @@ void sector_init(qf_sector &S, int n_orb, int na, int nb, const int32_t *exc, in
         S.d_groups = upload_new(gd);
         S.d_strs = upload_new(st);
     }
+    std::vector<uint32_t> rows;
+    S.row0.assign(1, 0u);
+    for (const SecExc &e : S.exc) {
+        for (uint32_t ia = 0; ia < S.DA; ia++) {
+            const uint32_t a = S.strA[ia];
+            if ((a & e.annA) == e.annA && (a & e.creA) == 0u)
+                rows.push_back(ia);
+        }
+        if (rows.size() > (size_t)UINT32_MAX)
+            raise(QF_E_SIZE, "sector: excitation domains too large");
+        S.row0.push_back((uint32_t)rows.size());
+    }
+    S.d_rows = upload_new(rows);
+    S.part0.assign(1, 0u);
+    const uint32_t nchunk = (S.DB + kSecT - 1) / kSecT;
+    for (size_t m = 0; m < S.exc.size(); m++) {
+        const uint64_t tiles = (uint64_t)(S.row0[m + 1] - S.row0[m]) * nchunk;
+        S.part0.push_back(S.part0.back() + (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(tiles, kSecGrid)));
+    }
+    S.d_part0 = upload_new(S.part0);
+    S.d_part = dev_alloc<double>(std::max<size_t>(S.part0.back(), 1));
     S.d_strA = upload_new(S.strA);
     S.d_strB = upload_new(S.strB);
     S.d_rankA = upload_new(S.rankA);
@@ -513,6 +574,13 @@ void sector_init(qf_sector &S, int n_orb, int na, int nb, const int32_t *exc, in
 unsigned tile_grid(const qf_sector &S)
 {
     const uint64_t tiles = (uint64_t)S.DA * ((S.DB + kSecT - 1) / kSecT);
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, kSecGrid));
+}
+
+// workgroups for excitation m's domain rows
+unsigned exc_grid(const qf_sector &S, size_t m)
+{
+    const uint64_t tiles = (uint64_t)(S.row0[m + 1] - S.row0[m]) * ((S.DB + kSecT - 1) / kSecT);
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(tiles, kSecGrid));
 }
 
@@ -590,9 +658,12 @@ extern "C" int qf_sector_apply(qf_sector *s, void *psi, const double *t, int inv
         for (size_t i = 0; i < E; i++) {
             const size_t m = inverse ? E - 1 - i : i;
             const double tm = inverse ? -t[m] : t[m];
-            hipLaunchKernelGGL(k_sector_rotate, dim3(tile_grid(*s)), dim3(kSecT), 0, (hipStream_t)stream,
-                               (double2 *)psi, s->d_strA, s->d_strB, s->d_rankA, s->d_rankB, s->DA, s->DB, s->exc[m],
-                               std::cos(tm), std::sin(tm));
+            const uint32_t nrows = s->row0[m + 1] - s->row0[m];
+            if (nrows == 0)
+                continue;  // no determinant of the sector is in the domain
+            hipLaunchKernelGGL(k_sector_rotate, dim3(exc_grid(*s, m)), dim3(kSecT), 0, (hipStream_t)stream,
+                               (double2 *)psi, s->d_strA, s->d_strB, s->d_rankA, s->d_rankB, s->d_rows + s->row0[m],
+                               nrows, s->DB, s->exc[m], std::cos(tm), std::sin(tm));
         }
         QF_HIP(hipGetLastError());
         return QF_OK;
@@ -649,9 +720,13 @@ extern "C" int qf_sector_energy_grad(qf_sector *s, uint64_t occ_mask, const doub
             s->grad_cap = E;
         }
         for (size_t i = E; i-- > 0;)
-            hipLaunchKernelGGL(k_sector_adjoint, dim3(grid), dim3(kSecT), 0, st, phi, lam, s->d_strA, s->d_strB,
-                               s->d_rankA, s->d_rankB, s->DA, s->DB, s->exc[i], std::cos(t[i]), std::sin(t[i]),
-                               s->d_partials, s->d_counter, s->d_grad + i);
+            hipLaunchKernelGGL(k_sector_adjoint, dim3(s->part0[i + 1] - s->part0[i]), dim3(kSecT), 0, st, phi, lam,
+                               s->d_strA, s->d_strB, s->d_rankA, s->d_rankB, s->d_rows + s->row0[i],
+                               s->row0[i + 1] - s->row0[i], s->DB, s->exc[i], std::cos(t[i]), std::sin(t[i]),
+                               s->d_part + s->part0[i]);
+        if (E)
+            hipLaunchKernelGGL(k_sector_grad_reduce, dim3((unsigned)((E + kSecT - 1) / kSecT)), dim3(kSecT), 0, st,
+                               s->d_part, s->d_part0, (int)E, s->d_grad);
         QF_HIP(hipGetLastError());
         QF_HIP(hipMemcpyAsync(E_out, s->d_result, sizeof(double), hipMemcpyDeviceToHost, st));
         if (E)

@@ -8,6 +8,7 @@ paper_2108_04413_amd.measure --op pool --qubits 20`).
     --op qk      QK basis by Trotterized evolution, S and H (Sec. 3.7),
                  dt 0.5, s 3, r 1
     --op sector  restricted state vector: reference, UCCSD factors, energy
+    --op sector_eg  restricted state vector: energy and dE/dt per excitation
     --op sigma   lambda = H psi (Eq. (17) as a sigma) on the UCCSD state
 
 The instance is the autotuner's: n/2 spatial orbitals and n/2 electrons,
@@ -25,7 +26,7 @@ import time
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--op", default="eg", choices=("eg", "pool", "pqe", "qk", "sector", "sigma"))
+    ap.add_argument("--op", default="eg", choices=("eg", "pool", "pqe", "qk", "sector", "sector_eg", "sigma"))
     ap.add_argument("--qubits", type=int, default=24)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--seed", type=int, default=None)
@@ -87,10 +88,17 @@ def main():
         psi = torch.empty(S.dim, dtype=torch.complex128, device="cuda")
         print(f"sector: dim {S.dim}, {S.groups} groups, {len(ops)} excitations", flush=True)
 
-        def call():
-            S.prepare(psi, d["occ"])
-            S.apply(psi, t)
-            return S.energy(psi)
+        if args.op == "sector_eg":
+            del psi
+            wsec = torch.empty(2 * S.dim, dtype=torch.complex128, device="cuda")
+
+            def call():
+                return S.energy_grad(d["occ"], t, wsec)[0]
+        else:
+            def call():
+                S.prepare(psi, d["occ"])
+                S.apply(psi, t)
+                return S.energy(psi)
     E = call()
     best = float("inf")
     for _ in range(args.reps):
