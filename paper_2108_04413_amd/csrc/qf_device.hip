@@ -731,25 +731,37 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(const double2 *__restr
                 r = rc + k + 1;
             };
 
-            // lo-terms of one phase part, up to record rend, into d[i]; the
-            // slot factor (-1)^popcount(i & zi) is a compile-time sign per case
+            // lo-terms of one phase part, up to record rend, into d[i].  Slot
+            // i's sign is (-1)^popcount(i & K), K = bits 8..10 of z_lo, and
+            // the lo-terms (sorted by z_lo) come in runs of equal K: a run
+            // sums a = sum s0 ce once, then adds (-1)^popcount(i & K) a to
+            // the eight slots (uniform signs from an XOR table of K's bits)
             auto part = [&](int rend, double(&d)[NI]) __attribute__((always_inline)) {
+                double a = 0.0;
+                uint32_t Kc = 8u;  // no run open
+                auto flush = [&]() __attribute__((always_inline)) {
+                    const uint32_t c1 = Kc << 31, c2 = (Kc >> 1) << 31, c4 = (Kc >> 2) << 31;
+                    const uint32_t sk[NI] = {0u, c1, c2, c1 ^ c2, c4, c1 ^ c4, c2 ^ c4, c1 ^ c2 ^ c4};
+#pragma unroll
+                    for (int i = 0; i < NI; i++)
+                        d[i] = fma(pm_one(sk[i]), a, d[i]);
+                };
                 while (r < rend) {
                     uint32_t z;
                     double ce;
                     next_lo(z, ce);
                     const uint32_t zl = z & (T - 1u);
-                    const double s0 = __hiloint2double((int)(0x3FF00000u | (__popc(tid & zl) << 31)), 0);
-                    // slot i's sign (-1)^popcount(i & K), K = bits 8..10 of
-                    // z_lo, from an XOR table of K's bits: uniform sign words
-                    // on the coefficient, no branch on K
                     const uint32_t K = zl >> 8;
-                    const uint32_t c1 = K << 31, c2 = (K >> 1) << 31, c4 = (K >> 2) << 31;
-                    const uint32_t sk[NI] = {0u, c1, c2, c1 ^ c2, c4, c1 ^ c4, c2 ^ c4, c1 ^ c2 ^ c4};
-#pragma unroll
-                    for (int i = 0; i < NI; i++)
-                        d[i] = fma(s0, flip31(ce, sk[i]), d[i]);
+                    if (K != Kc) {
+                        if (Kc < 8u)
+                            flush();
+                        a = 0.0;
+                        Kc = K;
+                    }
+                    a = fma(pm_one((uint32_t)__popc(tid & zl) << 31), ce, a);
                 }
+                if (Kc < 8u)
+                    flush();
             };
 
             double item = 0.0;
