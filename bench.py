@@ -176,6 +176,27 @@ def oracle_group_sample(qf, qi, n_threads, budget_s):
             "seconds": t_used, "GBps": (k - 1) * (1 << 24) * 16 / t_used / 1e9}
 
 
+def oracle_energy_grad_20q(qi, reps=3):
+    """The oracle's energy + adjoint gradient of the 20-qubit workload (C
+    core, all host threads): median wall time of reps evaluations."""
+    from oracle import ansatz as an, core, hamiltonian as ham
+    w, h, g = qi.workload("20q")
+    n = 2 * w["n_orb"]
+    x, z, c, _ = ham.group_by_flip_mask(ham.qubit_hamiltonian(h, g))
+    _, ax, az, ac, aoff, _ = an.build(w["n_orb"], w["n_elec"], "uccsd")
+    th = an.angles(ac, aoff, qi.amplitudes(len(aoff) - 1, w["seed"], w["t_scale"]))
+    occ = an.reference_mask(w["n_elec"])
+    ts = []
+    e = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        e, _g = core.energy_grad(n, occ, ax, az, th, x, z, c)
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    return {"threads": core.threads(), "workload": "20q energy + adjoint gradient (6700 ansatz, 14251 H strings)",
+            "seconds": ts, "seconds_median": med, "evals_per_s": 1.0 / med, "energy": e}
+
+
 def instance_from_recipe(qf, qi, r):
     h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
     H, off, _ = qf.build_paulis("hamiltonian", r["n_orb"], r["n_elec"], h, g)
@@ -650,7 +671,7 @@ def main():
         one = oracle_group_sample(qf, qi, 1, 5.0)
         allt = oracle_group_sample(qf, qi, core_threads(), 5.0)
         cb.update({"host_cpu": model, "host_threads": nthreads, "one_thread_24q": one, "all_threads_24q": allt,
-                   "host_triad_GBps_one_thread": triad_gbps()})
+                   "host_triad_GBps_one_thread": triad_gbps(), "oracle_energy_grad_20q": oracle_energy_grad_20q(qi)})
         log(f"cpu baseline: {cb}")
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)
