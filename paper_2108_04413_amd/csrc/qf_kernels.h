@@ -206,26 +206,25 @@ __device__ __forceinline__ void sub_parities(const LocalRun *__restrict__ lr, in
     }
 }
 
-// Wavefront sums of 8 values per lane with 10 exchanges instead of 48, all
-// of them register moves (DPP and the gfx950 lane swaps), none through the
-// LDS crossbar.  Three halving steps over lane bits 0, 1 and 4 (each lane
-// keeps half of its values and receives the other half from its partner)
-// leave lane l with value sum8_index(l) = 4 b0 + 2 b1 + b4 summed over the 8
-// lanes that share bits 2, 3 and 5; two rotations within each 16-lane row
-// add the lanes that differ in bits 2 and 3 (the rotation's direction does
-// not matter: ror 4 then ror 8 visits all four), and a swap of the two
-// 32-lane halves adds bit 5.  Lanes with bits 2, 3 and 5 clear
-// (sum8_writer) hold the 8 totals.  The order of additions is fixed.
-__device__ __forceinline__ int sum8_index(int lane)
-{
-    return 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 4) & 1);
-}
+// Wavefront sums of 8 values per lane, all exchanges register moves (the
+// gfx950 lane swaps and DPP), none through the LDS crossbar.  Two
+// transposing steps with the two-operand lane swaps halve the values per
+// lane with no selects: a permlane32 swap of values k and k + 4 leaves lanes
+// 0..31 with value k summed over lane bit 5 and lanes 32..63 with value
+// k + 4, then a permlane16 swap of k and k + 2 does the same over lane bit 4.
+// A row rotation by 8 (keep one value, send the other) takes bit 3, and
+// three in-row exchanges (quad_perm xor 1, xor 2, then the half-row mirror,
+// which pairs the two quads of each half-row) add bits 0, 1 and 2.  Lane l
+// then holds value sum8_index(l) = l >> 3 (its bits 5, 4, 3 = the value's
+// bits 2, 1, 0); lanes with bits 0..2 clear (sum8_writer) hand the 8 totals
+// on.  The order of additions is fixed.
+__device__ __forceinline__ int sum8_index(int lane) { return lane >> 3; }
 
-__device__ __forceinline__ bool sum8_writer(int lane) { return (lane & 0x2c) == 0; }
+__device__ __forceinline__ bool sum8_writer(int lane) { return (lane & 7) == 0; }
 
-// Every control used here (quad_perm, row_ror with all rows and banks
-// enabled) reads a lane inside the same row, so no lane falls back to the
-// old value and none needs to be supplied (bound_ctrl).
+// Every DPP control used here (quad_perm, row_ror, row_half_mirror, with
+// all rows and banks enabled) reads a lane inside the same row, so no lane
+// falls back to the old value and none needs to be supplied (bound_ctrl).
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
 {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
@@ -233,57 +232,48 @@ template <int CTRL> __device__ __forceinline__ double dpp_f64(double v)
     return __hiloint2double(hi, lo);
 }
 
-constexpr int kDppXor1 = 0xb1;  // quad_perm [1, 0, 3, 2]
-constexpr int kDppXor2 = 0x4e;  // quad_perm [2, 3, 0, 1]
-constexpr int kDppRor4 = 0x124; // row_ror:4
-constexpr int kDppRor8 = 0x128; // row_ror:8
+constexpr int kDppXor1 = 0xb1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4e;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppRor8 = 0x128;       // row_ror:8
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 
-// the value of lane l ^ 16 (lanes exchange 16-lane rows 0 <-> 1, 2 <-> 3)
-__device__ __forceinline__ double xor16_f64(double v)
+// lanes 0..31: a(l) + a(l + 32); lanes 32..63: b(l - 32) + b(l).  The
+// permlane32 swap trades the upper half of its first operand for the lower
+// half of its second, so the two results are (a lo | b lo) and (a hi | b hi).
+__device__ __forceinline__ double swap_add32(double a, double b)
 {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    // one result of each swap is this lane's own word, the other the
-    // partner's; where both are equal either is right
-    const bool first_is_own = (int)pl[0] == lo && (int)ph[0] == hi;
-    return __hiloint2double(first_is_own ? (int)ph[1] : (int)ph[0], first_is_own ? (int)pl[1] : (int)pl[0]);
+    const auto pl = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
 }
 
-// v(l) + v(l ^ 32): the swap leaves each lane one word of each half
-__device__ __forceinline__ double sum_xor32_f64(double v)
+// per pair of 16-lane rows (2j, 2j + 1): row 2j gets a(l) + a(l + 16), row
+// 2j + 1 gets b(l - 16) + b(l) (the permlane16 swap trades the odd rows of
+// its first operand for the even rows of its second)
+__device__ __forceinline__ double swap_add16(double a, double b)
 {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const auto pl = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
     return __hiloint2double((int)ph[0], (int)pl[0]) + __hiloint2double((int)ph[1], (int)pl[1]);
 }
 
 __device__ __forceinline__ double wave_sum8(const double (&v)[8], int lane)
 {
-    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b4 = (lane >> 4) & 1;
-    double h4[4], h2[2];
+    double w[4], x[2];
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const double send = b0 ? v[k] : v[k + 4];
-        const double keep = b0 ? v[k + 4] : v[k];
-        h4[k] = keep + dpp_f64<kDppXor1>(send);
-    }
+    for (int k = 0; k < 4; k++)
+        w[k] = swap_add32(v[k], v[k + 4]);
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-        const double send = b1 ? h4[k] : h4[k + 2];
-        const double keep = b1 ? h4[k + 2] : h4[k];
-        h2[k] = keep + dpp_f64<kDppXor2>(send);
-    }
-    double h;
-    {
-        const double send = b4 ? h2[0] : h2[1];
-        const double keep = b4 ? h2[1] : h2[0];
-        h = keep + xor16_f64(send);
-    }
-    h += dpp_f64<kDppRor4>(h);
-    h += dpp_f64<kDppRor8>(h);
-    return sum_xor32_f64(h);
+    for (int k = 0; k < 2; k++)
+        x[k] = swap_add16(w[k], w[k + 2]);
+    const bool b3 = (lane >> 3) & 1;
+    const double send = b3 ? x[0] : x[1];
+    const double keep = b3 ? x[1] : x[0];
+    double h = keep + dpp_f64<kDppRor8>(send);
+    h += dpp_f64<kDppXor1>(h);
+    h += dpp_f64<kDppXor2>(h);
+    h += dpp_f64<kDppHalfMirror>(h);
+    return h;
 }
 
 // One thread's share of one run in the 8 Walsh sums
