@@ -242,24 +242,41 @@ __device__ void seg_hoff(const Segment &sg, uint32_t *hoff)
 // items are t + k * kBT (kBT = kItemStride); table indices and Z-parities
 // split into the thread's part and the run's tabulated item parts, and the
 // phase of a flip run folds into signs (rot_pair).
-// NP > 0: exactly NP pairs per thread (NB = 2 NP kBT), unrolled so that
-// their LDS reads are in flight together; NP = 0: as many as NB holds.
+// NP > 0: exactly NP pairs per thread (NB = 2 NP kBT), all read before any
+// is written so that their LDS reads are in flight together (the pairs are
+// disjoint, which the compiler cannot tell); NP = 0: as many as NB holds.
 template <bool SW, int NP>
 __device__ __forceinline__ void sub_apply_pairs(double2 *st, const double2 *tb, const LocalRun &d, uint32_t NB,
                                                 uint32_t yt, uint32_t ut, uint32_t pt31, uint32_t px31)
 {
+    if constexpr (NP > 0) {
+        uint32_t y1[NP];
+        double2 a[NP], b[NP], cs[NP];
 #pragma unroll
-    for (int k = 0; NP ? k < NP : (uint32_t)k * kBT < NB / 2; k++) {
-        if (!NP && threadIdx.x + (uint32_t)k * kBT >= NB / 2)
-            break;
-        const uint32_t ik = item_part(item_table(d), k);
-        const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
-        const double2 cs = tb[ut ^ (ik & 63u)];
-        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31);
-        double2 a = st[y1], b = st[y2];
-        rot_pair<SW>(cs.x, flip31(cs.y, P1), flip31(cs.y, P1 ^ px31), a, b);
-        st[y1] = a;
-        st[y2] = b;
+        for (int k = 0; k < NP; k++) {
+            y1[k] = yt | insert0((uint32_t)k * kBT, d.hbit);
+            cs[k] = tb[ut ^ (item_part(item_table(d), k) & 63u)];
+            a[k] = st[y1[k]];
+            b[k] = st[y1[k] ^ d.x];
+        }
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const uint32_t P1 = pt31 ^ ((item_part(item_table(d), k) >> 6) << 31);
+            rot_pair<SW>(cs[k].x, flip31(cs[k].y, P1), flip31(cs[k].y, P1 ^ px31), a[k], b[k]);
+            st[y1[k]] = a[k];
+            st[y1[k] ^ d.x] = b[k];
+        }
+    } else {
+        for (uint32_t j = threadIdx.x, k = 0; j < NB / 2; j += kBT, k++) {
+            const uint32_t ik = item_part(item_table(d), (int)k);
+            const uint32_t y1 = yt | insert0(k * kBT, d.hbit), y2 = y1 ^ d.x;
+            const double2 cs = tb[ut ^ (ik & 63u)];
+            const uint32_t P1 = pt31 ^ ((ik >> 6) << 31);
+            double2 a = st[y1], b = st[y2];
+            rot_pair<SW>(cs.x, flip31(cs.y, P1), flip31(cs.y, P1 ^ px31), a, b);
+            st[y1] = a;
+            st[y2] = b;
+        }
     }
 }
 
@@ -329,37 +346,62 @@ __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, cons
     const uint32_t i0 = item_part(item_table(d), 0) & 63u;
     uint32_t du[NP ? NP : 1];
     double qs[NP ? NP : 1];
+    if constexpr (NP > 0) {
+        // every item read before any is written, as in sub_apply_pairs
+        uint32_t y1s[NP];
+        double2 as[NP], bs[NP], las[NP], lbs[NP], css[NP];
 #pragma unroll
-    for (int k = 0; NP ? k < NP : (uint32_t)k * kBT < NB / 2; k++) {
-        if (!NP && threadIdx.x + (uint32_t)k * kBT >= NB / 2)
-            break;
-        const uint32_t ik = item_part(item_table(d), k);
-        const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit), y2 = y1 ^ d.x;
-        const uint32_t u = ut ^ (ik & 63u);
-        const double2 cs = tb[u];
-        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
-        double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
-        const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
-        const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
-        const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
-        const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
-        rot_pair<SW>(cs.x, s1, s2, a, b);
-        rot_pair<SW>(cs.x, s1, s2, la, lb);
-        sp[y1] = a;
-        sp[y2] = b;
-        sl[y1] = la;
-        sl[y2] = lb;
-        if constexpr (NP > 0) {
+        for (int k = 0; k < NP; k++) {
+            const uint32_t y1 = yt | insert0((uint32_t)k * kBT, d.hbit);
+            y1s[k] = y1;
+            css[k] = tb[ut ^ (item_part(item_table(d), k) & 63u)];
+            as[k] = sp[y1];
+            bs[k] = sp[y1 ^ d.x];
+            las[k] = sl[y1];
+            lbs[k] = sl[y1 ^ d.x];
+        }
+#pragma unroll
+        for (int k = 0; k < NP; k++) {
+            const uint32_t ik = item_part(item_table(d), k);
+            const uint32_t y1 = y1s[k], y2 = y1 ^ d.x;
+            const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
+            double2 a = as[k], b = bs[k], la = las[k], lb = lbs[k];
+            const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+            const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+            qs[k] = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
             du[k] = i0 ^ (ik & 63u);
-            qs[k] = q;
-        } else {
+            const double s1 = flip31(css[k].y, P1), s2 = flip31(css[k].y, P2);
+            rot_pair<SW>(css[k].x, s1, s2, a, b);
+            rot_pair<SW>(css[k].x, s1, s2, la, lb);
+            sp[y1] = a;
+            sp[y2] = b;
+            sl[y1] = la;
+            sl[y2] = lb;
+        }
+        accumulate(ut ^ i0, du, qs);
+    } else {
+        for (uint32_t j = threadIdx.x, k = 0; j < NB / 2; j += kBT, k++) {
+            const uint32_t ik = item_part(item_table(d), (int)k);
+            const uint32_t y1 = yt | insert0(k * kBT, d.hbit), y2 = y1 ^ d.x;
+            const uint32_t u = ut ^ (ik & 63u);
+            const double2 cs = tb[u];
+            const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
+            double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+            const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+            const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+            const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
+            const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+            rot_pair<SW>(cs.x, s1, s2, a, b);
+            rot_pair<SW>(cs.x, s1, s2, la, lb);
+            sp[y1] = a;
+            sp[y2] = b;
+            sl[y1] = la;
+            sl[y2] = lb;
             const uint32_t d1[1] = {0u};
             const double q1[1] = {q};
             accumulate(u, d1, q1);
         }
     }
-    if constexpr (NP > 0)
-        accumulate(ut ^ i0, du, qs);
 }
 
 // Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and

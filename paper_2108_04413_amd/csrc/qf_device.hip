@@ -216,6 +216,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_run(double2 *__restrict__ psi,
 // Z-parity split into the thread's part (ut, pt31) and item k's part (the
 // run's item table).  pt31 carries, in bit 31, the Z-parity of y_t plus the
 // constant signs of the rotation; px31 the parity of x & z0.
+// All items are read before any is written: the pairs are disjoint, but the
+// compiler cannot tell, and item by item it would wait out one LDS round
+// trip per item.
 template <bool SW, uint32_t NB, int NT>
 __device__ __forceinline__ void apply_pairs(double2 *st, const double2 *tb, const LocalRun &d, uint32_t yt,
                                             uint32_t ut, uint32_t pt31, uint32_t px31)
@@ -223,16 +226,22 @@ __device__ __forceinline__ void apply_pairs(double2 *st, const double2 *tb, cons
     constexpr int NP = NB / 2 >= (uint32_t)NT ? (int)(NB / 2 / NT) : 1;
     if (NB / 2 < (uint32_t)NT && threadIdx.x >= NB / 2)
         return;
+    uint32_t y1[NP];
+    double2 a[NP], b[NP], cs[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         const uint32_t ik = item_part(item_table(d), k);
-        const uint32_t y1 = yt | insert0((uint32_t)k * NT, d.hbit), y2 = y1 ^ d.x;
-        const double2 cs = tb[ut ^ (ik & 63u)];
-        const uint32_t P1 = pt31 ^ ((ik >> 6) << 31);
-        double2 a = st[y1], b = st[y2];
-        rot_pair<SW>(cs.x, flip31(cs.y, P1), flip31(cs.y, P1 ^ px31), a, b);
-        st[y1] = a;
-        st[y2] = b;
+        y1[k] = yt | insert0((uint32_t)k * NT, d.hbit);
+        cs[k] = tb[ut ^ (ik & 63u)];
+        a[k] = st[y1[k]];
+        b[k] = st[y1[k] ^ d.x];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const uint32_t P1 = pt31 ^ ((item_part(item_table(d), k) >> 6) << 31);
+        rot_pair<SW>(cs[k].x, flip31(cs[k].y, P1), flip31(cs[k].y, P1 ^ px31), a[k], b[k]);
+        st[y1[k]] = a[k];
+        st[y1[k] ^ d.x] = b[k];
     }
 }
 
@@ -296,13 +305,16 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, S
                 apply_pairs<false, NB, NT>(st, tb, d, yt, ut, pt31, px31);
         } else {
             const uint32_t ut = (pbz & 63u) ^ gf2_coords(threadIdx.x, d.b, d.r);
+            double2 cs[PER], v[PER];
 #pragma unroll
             for (int k = 0; k < PER; k++) {
-                const uint32_t y = threadIdx.x + (uint32_t)k * NT;
-                const double2 cs = tb[ut ^ item_part(item_table(d), k)];
-                const double c = cs.x, s = sgn * cs.y;
-                const double2 v = st[y];
-                st[y] = make_double2(c * v.x + s * v.y, c * v.y - s * v.x);
+                cs[k] = tb[ut ^ item_part(item_table(d), k)];
+                v[k] = st[threadIdx.x + (uint32_t)k * NT];
+            }
+#pragma unroll
+            for (int k = 0; k < PER; k++) {
+                const double c = cs[k].x, s = sgn * cs[k].y;
+                st[threadIdx.x + (uint32_t)k * NT] = make_double2(c * v[k].x + s * v[k].y, c * v[k].y - s * v[k].x);
             }
         }
     }
@@ -1013,21 +1025,35 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
     if (NB / 2 < (uint32_t)NT && threadIdx.x >= NB / 2)
         return;
     const uint32_t i0 = item_part(item_table(d), 0) & 63u;
-    uint32_t du[NP];
+    uint32_t du[NP], y1s[NP];
     double qs[NP];
+    double2 as[NP], bs[NP], las[NP], lbs[NP], css[NP];
+    // every item is read before any is written (the pairs are disjoint; item
+    // by item the compiler would wait out one LDS round trip per item)
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         const uint32_t ik = item_part(item_table(d), k);
         const uint32_t y1 = yt | insert0((uint32_t)k * NT, d.hbit), y2 = y1 ^ d.x;
-        const uint32_t u = ut ^ (ik & 63u);
+        y1s[k] = y1;
+        if constexpr (UNDO)
+            css[k] = tb[ut ^ (ik & 63u)];
+        as[k] = sp[y1];
+        bs[k] = sp[y2];
+        las[k] = sl[y1];
+        lbs[k] = sl[y2];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const uint32_t ik = item_part(item_table(d), k);
+        const uint32_t y1 = y1s[k], y2 = y1 ^ d.x;
         du[k] = i0 ^ (ik & 63u);
-        const double2 cs = tb[u];
         const uint32_t P1 = pt31 ^ ((ik >> 6) << 31), P2 = P1 ^ px31;
-        double2 a = sp[y1], b = sp[y2], la = sl[y1], lb = sl[y2];
+        double2 a = as[k], b = bs[k], la = las[k], lb = lbs[k];
         const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
         const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
         const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
         if constexpr (UNDO) {
+            const double2 cs = css[k];
             const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
             rot_pair<SW>(cs.x, s1, s2, a, b);
             rot_pair<SW>(cs.x, s1, s2, la, lb);
@@ -1136,16 +1162,23 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
                 const uint32_t i0 = item_part(item_table(d), 0);
                 uint32_t du[PER];
                 double qs[PER];
+                double2 as[PER], las[PER], css[PER];
 #pragma unroll
                 for (int kk = 0; kk < PER; kk++) {
                     const uint32_t y = tid + (uint32_t)kk * NT;
-                    const uint32_t u = ut ^ item_part(item_table(d), kk);
+                    if constexpr (UNDO)
+                        css[kk] = tb[ut ^ item_part(item_table(d), kk)];
+                    as[kk] = sp[y];
+                    las[kk] = sl[y];
+                }
+#pragma unroll
+                for (int kk = 0; kk < PER; kk++) {
+                    const uint32_t y = tid + (uint32_t)kk * NT;
                     du[kk] = i0 ^ item_part(item_table(d), kk);
-                    const double2 cs = tb[u];
-                    const double c = cs.x, s = cs.y;
-                    const double2 a = sp[y], la = sl[y];
+                    const double2 a = as[kk], la = las[kk];
                     qs[kk] = la.x * a.y - la.y * a.x;
                     if constexpr (UNDO) {
+                        const double c = css[kk].x, s = css[kk].y;
                         sp[y] = make_double2(c * a.x - s * a.y, c * a.y + s * a.x);
                         sl[y] = make_double2(c * la.x - s * la.y, c * la.y + s * la.x);
                     }
