@@ -1067,11 +1067,120 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
     accumulate(ut ^ i0, du, qs);
 }
 
+// One flip-run pair of the reverse sweep on registers: q of the pair (a, b)
+// (phi) and (la, lb) (lambda) as in adjoint_pairs, then the pair undone.
+template <bool SW>
+__device__ __forceinline__ double adjoint_one_pair(double2 &a, double2 &b, double2 &la, double2 &lb, double2 cs,
+                                                   uint32_t P1, uint32_t px31, uint32_t dq31)
+{
+    const uint32_t P2 = P1 ^ px31;
+    const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+    const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+    const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
+    const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+    rot_pair<SW>(cs.x, s1, s2, a, b);
+    rot_pair<SW>(cs.x, s1, s2, la, lb);
+    return q;
+}
+
+// The 3 GF(2) coordinates of y against a rank <= 3 run's masks.
+__device__ __forceinline__ uint32_t gf2_coords3(uint32_t y, const LocalRun &d)
+{
+    return par(y & d.b[0]) | (par(y & d.b[1]) << 1) | (par(y & d.b[2]) << 2);
+}
+
+// Whether runs A (undone first) and B (the run before it) go through one
+// LDS pass: both flip runs of rank <= 3 with different flip masks, so that
+// span(xA, xB) has dimension 2, and both with i^a0 imaginary (a0 odd: the
+// undo factor i^(a0 + 1) is real, the non-swapping rot_pair form).  Strings
+// with an odd number of Y factors, i.e. every string of a real-amplitude
+// excitation operator, have a0 odd; other runs take the one-run path.
+__device__ __forceinline__ bool adjoint_pairable(const LocalRun &A, const LocalRun &B)
+{
+    return A.x != 0u && B.x != 0u && A.x != B.x && A.r <= 3 && B.r <= 3 && (A.a0 & B.a0 & 1u);
+}
+
+// Two consecutive runs undone in one LDS pass.  The sub-cube splits into the
+// 2^(B-2) cosets {c0, c0 ^ xA, c0 ^ xB, c0 ^ xA ^ xB} of span(xA, xB); thread
+// t holds coset t (c0: zeros opened at the highest bit of xA and at the
+// highest bit of xB reduced by xA) in registers, so both runs' pairs are its
+// own and no barrier separates them.  Run A's pairs are (c0, c0 ^ xA) and
+// (c2, c2 ^ xA) with c2 = c0 ^ xB, run B's (c0, c2) and (c1, c1 ^ xB) with
+// c1 = c0 ^ xA.  Table index and Z-parity are affine in y, so each second
+// pair differs from the first by uniform offsets (the coordinates and parity
+// of xB for run A, of xA for run B).  Both runs' Walsh sums reach red
+// (columns 0..7: A, 8..15: B).
+__device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const double2 *tbA, const double2 *tbB,
+                                            const LocalRun &dA, const LocalRun &dB, uint32_t pbzA, uint32_t pbzB,
+                                            uint32_t tid, int lane, double *red_w)
+{
+    const uint32_t xA = dA.x, xB = dB.x;
+    const uint32_t p1 = dA.hbit;
+    const uint32_t xr = ((xB >> p1) & 1u) ? xB ^ xA : xB;
+    const uint32_t p2 = 31u - (uint32_t)__clz(xr);
+    const uint32_t c0 = insert0(insert0(tid, p1 < p2 ? p1 : p2), p1 < p2 ? p2 : p1);
+    const uint32_t c1 = c0 ^ xA, c2 = c0 ^ xB, c3 = c2 ^ xA;
+    const uint32_t mA = (dA.a0 + 1u) & 3u, mB = (dB.a0 + 1u) & 3u;
+    const uint32_t uA0 = (pbzA & 63u) ^ gf2_coords3(c0, dA), uA1 = uA0 ^ gf2_coords3(xB, dA);
+    const uint32_t uB0 = (pbzB & 63u) ^ gf2_coords3(c0, dB), uB1 = uB0 ^ gf2_coords3(xA, dB);
+    const double2 csA0 = tbA[uA0], csA1 = tbA[uA1], csB0 = tbB[uB0], csB1 = tbB[uB1];
+    double2 a0 = sp[c0], a1 = sp[c1], a2 = sp[c2], a3 = sp[c3];
+    double2 l0 = sl[c0], l1 = sl[c1], l2 = sl[c2], l3 = sl[c3];
+    const uint32_t PA0 = (par(c0 & dA.z0) ^ (pbzA >> 6) ^ (mA >> 1)) << 31;
+    const uint32_t PA1 = PA0 ^ (par(xB & dA.z0) << 31);
+    const uint32_t PB0 = (par(c0 & dB.z0) ^ (pbzB >> 6) ^ (mB >> 1)) << 31;
+    const uint32_t PB1 = PB0 ^ (par(xA & dB.z0) << 31);
+    // Run A, then run B one pair at a time, each B pair stored as soon as it
+    // is final; the Walsh sums and wave reductions follow with only the four
+    // q values live.  (Scheduling fences between the steps: interleaved, the
+    // steps hold more than the 128 registers of four waves per SIMD.)
+    double qA[2], qB[2];
+    {
+        const uint32_t px = par(xA & dA.z0) << 31, dq = ((dA.a0 >> 1) ^ (mA >> 1)) << 31;
+        qA[0] = adjoint_one_pair<false>(a0, a1, l0, l1, csA0, PA0, px, dq);
+        __builtin_amdgcn_sched_barrier(0);
+        qA[1] = adjoint_one_pair<false>(a2, a3, l2, l3, csA1, PA1, px, dq);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const uint32_t px = par(xB & dB.z0) << 31, dq = ((dB.a0 >> 1) ^ (mB >> 1)) << 31;
+        qB[0] = adjoint_one_pair<false>(a0, a2, l0, l2, csB0, PB0, px, dq);
+        sp[c0] = a0;
+        sp[c2] = a2;
+        sl[c0] = l0;
+        sl[c2] = l2;
+        __builtin_amdgcn_sched_barrier(0);
+        qB[1] = adjoint_one_pair<false>(a1, a3, l1, l3, csB1, PB1, px, dq);
+        sp[c1] = a1;
+        sp[c3] = a3;
+        sl[c1] = l1;
+        sl[c3] = l3;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // (no branch before both sums: a branch lets the compiler sink run B's
+    // q past it and keep all eight amplitudes live through the first sum)
+    double w[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        double acc[kMaxRun];
+#pragma unroll
+        for (int k = 0; k < kMaxRun; k++)
+            acc[k] = -0.0;
+        const uint32_t du[2] = {0u, h ? uB0 ^ uB1 : uA0 ^ uA1};
+        walsh_add<2>(acc, h ? uB0 : uA0, du, h ? qB : qA);
+        w[h] = wave_sum8(acc, lane);
+    }
+    if (sum8_writer(lane)) {
+        red_w[sum8_index(lane)] = w[0];
+        red_w[kMaxRun + sum8_index(lane)] = w[1];
+    }
+}
+
 // UNDO = false: the same string sums 2 Im <lambda|P_k|phi> with phi and
 // lambda left as they are (read-only sub-cubes, no write-back): the ADAPT
 // pool gradients of Sec. 3.2 on a fixed state.
 template <int B, int NT, bool UNDO = true>
-__global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
                                                       Segment sg, const LocalRun *__restrict__ lruns,
                                                       const double2 *__restrict__ tab, int sk0, int nstr,
                                                       double *__restrict__ part, int K)
@@ -1084,9 +1193,11 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
     __shared__ uint32_t hoff[64];
     __shared__ double2 stab[kSegTab];
     __shared__ double lacc[kSegStr];
-    __shared__ double red[NW][kMaxRun];
+    __shared__ double red[NW][2 * kMaxRun];
     __shared__ uint32_t spbz[kSegRuns];
     static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
+    // two runs per pass need a coset of 4 amplitudes per thread
+    constexpr bool kTwo = UNDO && NB == 4u * (uint32_t)NT;
     const uint32_t tid = threadIdx.x;
     const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
     const uint32_t lomask = (1u << sg.q0) - 1u;
@@ -1118,6 +1229,40 @@ __global__ __launch_bounds__(NT) void k_adjoint_block(double2 *__restrict__ phi,
             sl[l] = lam[y];
         }
         for (int ri = nr - 1; ri >= 0; ri--) {
+            if constexpr (kTwo) {
+                if (ri > 0 && adjoint_pairable(lruns[sg.r0 + ri], lruns[sg.r0 + ri - 1])) {
+                    const LocalRun &dA = lruns[sg.r0 + ri], &dB = lruns[sg.r0 + ri - 1];
+                    const double2 *tbA = stab + (dA.tab - sg.tab0), *tbB = stab + (dB.tab - sg.tab0);
+                    const uint32_t pbzA = spbz[ri], pbzB = spbz[ri - 1];
+                    __syncthreads();  // the previous run's updates are visible
+                    adjoint_two(sp, sl, tbA, tbB, dA, dB, pbzA, pbzB, tid, lane, red[wave]);
+                    __syncthreads();
+                    if (tid < 2u * kMaxRun) {
+                        // lanes 0..7: run A's strings, 8..15: run B's (Walsh
+                        // column e_k, sign s_k, as in the one-run case)
+                        const bool hiB = tid >= (uint32_t)kMaxRun;
+                        const int k = (int)(tid & (kMaxRun - 1));
+                        uint64_t eA, sA, eB, sB;
+                        __builtin_memcpy(&eA, dA.e, sizeof eA);
+                        __builtin_memcpy(&sA, dA.s, sizeof sA);
+                        __builtin_memcpy(&eB, dB.e, sizeof eB);
+                        __builtin_memcpy(&sB, dB.s, sizeof sB);
+                        const uint64_t ep = hiB ? eB : eA, spk = ((hiB ? sB : sA) >> 7) & 0x0101010101010101ull;
+                        if (k < (hiB ? dB.m : dA.m)) {
+                            const int col = (hiB ? kMaxRun : 0) + (int)((ep >> (8 * k)) & 0xffu);
+                            double v = 0.0;
+#pragma unroll
+                            for (int w = 0; w < NW; w++)
+                                v += red[w][col];
+                            if ((spk >> (8 * k)) & 1u)
+                                v = -v;
+                            lacc[(hiB ? dB.k0 : dA.k0) - sk0 + k] += v;
+                        }
+                    }
+                    ri--;
+                    continue;
+                }
+            }
             // (the descriptors stay in the scalar cache over the sub-cubes of
             // a segment; reading them a run ahead cost ~60 register copies per run)
             const LocalRun d = lruns[sg.r0 + ri];
