@@ -1083,67 +1083,47 @@ __device__ __forceinline__ double adjoint_one_pair(double2 &a, double2 &b, doubl
     return q;
 }
 
-// The 3 GF(2) coordinates of y against a rank <= 3 run's masks.
-__device__ __forceinline__ uint32_t gf2_coords3(uint32_t y, const LocalRun &d)
-{
-    return par(y & d.b[0]) | (par(y & d.b[1]) << 1) | (par(y & d.b[2]) << 2);
-}
-
-// Whether runs A (undone first) and B (the run before it) go through one
-// LDS pass: both flip runs of rank <= 3 with different flip masks, so that
-// span(xA, xB) has dimension 2, and both with i^a0 imaginary (a0 odd: the
-// undo factor i^(a0 + 1) is real, the non-swapping rot_pair form).  Strings
-// with an odd number of Y factors, i.e. every string of a real-amplitude
-// excitation operator, have a0 odd; other runs take the one-run path.
-__device__ __forceinline__ bool adjoint_pairable(const LocalRun &A, const LocalRun &B)
-{
-    return A.x != 0u && B.x != 0u && A.x != B.x && A.r <= 3 && B.r <= 3 && (A.a0 & B.a0 & 1u);
-}
-
-// Two consecutive runs undone in one LDS pass.  The sub-cube splits into the
-// 2^(B-2) cosets {c0, c0 ^ xA, c0 ^ xB, c0 ^ xA ^ xB} of span(xA, xB); thread
-// t holds coset t (c0: zeros opened at the highest bit of xA and at the
-// highest bit of xB reduced by xA) in registers, so both runs' pairs are its
-// own and no barrier separates them.  Run A's pairs are (c0, c0 ^ xA) and
+// Two consecutive runs undone in one LDS pass (an AdjPair).  The sub-cube
+// splits into the 2^(B-2) cosets {c0, c0 ^ xA, c0 ^ xB, c0 ^ xA ^ xB} of
+// span(xA, xB); thread t holds coset t (c0: zeros opened at the pair's two
+// pivot bits) of phi and lambda in registers, so both runs' pairs are its own
+// and no barrier separates them.  Run A's pairs are (c0, c0 ^ xA) and
 // (c2, c2 ^ xA) with c2 = c0 ^ xB, run B's (c0, c2) and (c1, c1 ^ xB) with
 // c1 = c0 ^ xA.  Table index and Z-parity are affine in y, so each second
-// pair differs from the first by uniform offsets (the coordinates and parity
-// of xB for run A, of xA for run B).  Both runs' Walsh sums reach red
-// (columns 0..7: A, 8..15: B).
-__device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const double2 *tbA, const double2 *tbB,
-                                            const LocalRun &dA, const LocalRun &dB, uint32_t pbzA, uint32_t pbzB,
-                                            uint32_t tid, int lane, double *red_w)
+// pair differs from the first by the tabulated uniform offsets.  Both runs'
+// Walsh sums reach red_w (columns 0..7: A, 8..15: B).
+__device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const double2 *stab, const AdjPair &pr,
+                                            uint32_t pbzA, uint32_t pbzB, uint32_t tid, int lane, double *red_w)
 {
-    const uint32_t xA = dA.x, xB = dB.x;
-    const uint32_t p1 = dA.hbit;
-    const uint32_t xr = ((xB >> p1) & 1u) ? xB ^ xA : xB;
-    const uint32_t p2 = 31u - (uint32_t)__clz(xr);
-    const uint32_t c0 = insert0(insert0(tid, p1 < p2 ? p1 : p2), p1 < p2 ? p2 : p1);
-    const uint32_t c1 = c0 ^ xA, c2 = c0 ^ xB, c3 = c2 ^ xA;
-    const uint32_t mA = (dA.a0 + 1u) & 3u, mB = (dB.a0 + 1u) & 3u;
-    const uint32_t uA0 = (pbzA & 63u) ^ gf2_coords3(c0, dA), uA1 = uA0 ^ gf2_coords3(xB, dA);
-    const uint32_t uB0 = (pbzB & 63u) ^ gf2_coords3(c0, dB), uB1 = uB0 ^ gf2_coords3(xA, dB);
+    const uint32_t plo = (pr.w0 >> 8) & 31u, phi = (pr.w0 >> 16) & 31u;
+    const uint32_t c0 = insert0(insert0(tid, plo), phi);
+    const uint32_t c1 = c0 ^ pr.xA, c2 = c0 ^ pr.xB, c3 = c2 ^ pr.xA;
+    const uint32_t bA = pr.bits & 0xffu, bB = (pr.bits >> 8) & 0xffu;
+    const double2 *tbA = stab + (pr.tabs & 0xffffu), *tbB = stab + (pr.tabs >> 16);
+    const uint32_t uA0 = (pbzA & 63u) ^ par(c0 & pr.bA[0]) ^ (par(c0 & pr.bA[1]) << 1) ^ (par(c0 & pr.bA[2]) << 2);
+    const uint32_t uB0 = (pbzB & 63u) ^ par(c0 & pr.bB[0]) ^ (par(c0 & pr.bB[1]) << 1) ^ (par(c0 & pr.bB[2]) << 2);
+    const uint32_t uA1 = uA0 ^ (bA & 7u), uB1 = uB0 ^ (bB & 7u);
     const double2 csA0 = tbA[uA0], csA1 = tbA[uA1], csB0 = tbB[uB0], csB1 = tbB[uB1];
     double2 a0 = sp[c0], a1 = sp[c1], a2 = sp[c2], a3 = sp[c3];
     double2 l0 = sl[c0], l1 = sl[c1], l2 = sl[c2], l3 = sl[c3];
-    const uint32_t PA0 = (par(c0 & dA.z0) ^ (pbzA >> 6) ^ (mA >> 1)) << 31;
-    const uint32_t PA1 = PA0 ^ (par(xB & dA.z0) << 31);
-    const uint32_t PB0 = (par(c0 & dB.z0) ^ (pbzB >> 6) ^ (mB >> 1)) << 31;
-    const uint32_t PB1 = PB0 ^ (par(xA & dB.z0) << 31);
+    const uint32_t PA0 = (par(c0 & pr.z0A) ^ (pbzA >> 6) ^ (bA >> 5)) << 31;
+    const uint32_t PA1 = PA0 ^ ((bA >> 3) << 31);
+    const uint32_t PB0 = (par(c0 & pr.z0B) ^ (pbzB >> 6) ^ (bB >> 5)) << 31;
+    const uint32_t PB1 = PB0 ^ ((bB >> 3) << 31);
     // Run A, then run B one pair at a time, each B pair stored as soon as it
     // is final; the Walsh sums and wave reductions follow with only the four
     // q values live.  (Scheduling fences between the steps: interleaved, the
     // steps hold more than the 128 registers of four waves per SIMD.)
     double qA[2], qB[2];
     {
-        const uint32_t px = par(xA & dA.z0) << 31, dq = ((dA.a0 >> 1) ^ (mA >> 1)) << 31;
+        const uint32_t px = (bA >> 4) << 31, dq = (bA >> 6) << 31;
         qA[0] = adjoint_one_pair<false>(a0, a1, l0, l1, csA0, PA0, px, dq);
         __builtin_amdgcn_sched_barrier(0);
         qA[1] = adjoint_one_pair<false>(a2, a3, l2, l3, csA1, PA1, px, dq);
     }
     __builtin_amdgcn_sched_barrier(0);
     {
-        const uint32_t px = par(xB & dB.z0) << 31, dq = ((dB.a0 >> 1) ^ (mB >> 1)) << 31;
+        const uint32_t px = (bB >> 4) << 31, dq = (bB >> 6) << 31;
         qB[0] = adjoint_one_pair<false>(a0, a2, l0, l2, csB0, PB0, px, dq);
         sp[c0] = a0;
         sp[c2] = a2;
@@ -1182,6 +1162,7 @@ __device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const doub
 template <int B, int NT, bool UNDO = true>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
                                                       Segment sg, const LocalRun *__restrict__ lruns,
+                                                      const AdjPair *__restrict__ apairs,
                                                       const double2 *__restrict__ tab, int sk0, int nstr,
                                                       double *__restrict__ part, int K)
 {
@@ -1196,7 +1177,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ double red[NW][2 * kMaxRun];
     __shared__ uint32_t spbz[kSegRuns];
     static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
-    // two runs per pass need a coset of 4 amplitudes per thread
+    // two runs per pass need a coset of 4 amplitudes per thread (apairs is
+    // read only then)
     constexpr bool kTwo = UNDO && NB == 4u * (uint32_t)NT;
     const uint32_t tid = threadIdx.x;
     const int lane = (int)(tid & 63u), wave = (int)(tid >> 6);
@@ -1230,14 +1212,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         for (int ri = nr - 1; ri >= 0; ri--) {
             if constexpr (kTwo) {
-                if (ri > 0 && adjoint_pairable(lruns[sg.r0 + ri], lruns[sg.r0 + ri - 1])) {
-                    const LocalRun &dA = lruns[sg.r0 + ri], &dB = lruns[sg.r0 + ri - 1];
-                    const double2 *tbA = stab + (dA.tab - sg.tab0), *tbB = stab + (dB.tab - sg.tab0);
+                const AdjPair pr = apairs[sg.r0 + ri];
+                if (pr.w0 & 1u) {
                     const uint32_t pbzA = spbz[ri], pbzB = spbz[ri - 1];
                     __syncthreads();  // the previous run's updates are visible
-                    adjoint_two(sp, sl, tbA, tbB, dA, dB, pbzA, pbzB, tid, lane, red[wave]);
+                    adjoint_two(sp, sl, stab, pr, pbzA, pbzB, tid, lane, red[wave]);
                     __syncthreads();
                     if (tid < 2u * kMaxRun) {
+                        const LocalRun &dA = lruns[sg.r0 + ri], &dB = lruns[sg.r0 + ri - 1];
                         // lanes 0..7: run A's strings, 8..15: run B's (Walsh
                         // column e_k, sign s_k, as in the one-run case)
                         const bool hiB = tid >= (uint32_t)kMaxRun;
@@ -1726,6 +1708,55 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
     }
 }
 
+// Two-run passes of the blocked reverse sweep (AdjPair): walking each
+// segment's runs from the last, as the kernel does, run r and run r - 1 form
+// a pair when both are flip runs of rank <= 3 with different flip masks and
+// a0 odd; a run that does not pair is undone on its own.
+std::vector<AdjPair> adjoint_pairs(const std::vector<Segment> &segs, const std::vector<LocalRun> &lr)
+{
+    std::vector<AdjPair> ap(lr.size());
+    std::memset(ap.data(), 0, ap.size() * sizeof(AdjPair));
+    auto par = [](uint32_t v) { return (uint32_t)__builtin_popcount(v) & 1u; };
+    auto coords3 = [&](uint32_t y, const LocalRun &d) {
+        return par(y & d.b[0]) | (par(y & d.b[1]) << 1) | (par(y & d.b[2]) << 2);
+    };
+    // bits 0..6 of one run: second-pair table offset, its parity offset,
+    // par(x & z0), m >> 1 and the q sign (see AdjPair)
+    auto run_bits = [&](const LocalRun &d, uint32_t other) {
+        const uint32_t m = (d.a0 + 1u) & 3u;
+        return coords3(other, d) | par(other & d.z0) << 3 | par(d.x & d.z0) << 4 | (m >> 1) << 5 |
+               (((d.a0 >> 1) ^ (m >> 1)) & 1u) << 6;
+    };
+    for (const Segment &sg : segs) {
+        if (!sg.Q)
+            continue;
+        for (int ri = sg.r1 - 1; ri >= sg.r0; ri--) {
+            if (ri == sg.r0)
+                break;
+            const LocalRun &A = lr[(size_t)ri], &B = lr[(size_t)ri - 1];
+            if (!(A.x && B.x && A.x != B.x && A.r <= 3 && B.r <= 3 && (A.a0 & B.a0 & 1u)))
+                continue;
+            const uint32_t p1 = A.hbit;
+            const uint32_t xr = ((B.x >> p1) & 1u) ? B.x ^ A.x : B.x;
+            const uint32_t p2 = 31u - (uint32_t)__builtin_clz(xr);
+            AdjPair &P = ap[(size_t)ri];
+            P.w0 = 1u | std::min(p1, p2) << 8 | std::max(p1, p2) << 16;
+            P.xA = A.x;
+            P.xB = B.x;
+            for (int q = 0; q < 3; q++) {
+                P.bA[q] = A.b[q];
+                P.bB[q] = B.b[q];
+            }
+            P.z0A = A.z0;
+            P.z0B = B.z0;
+            P.bits = run_bits(A, B.x) | run_bits(B, A.x) << 8;
+            P.tabs = (uint32_t)(A.tab - sg.tab0) | (uint32_t)(B.tab - sg.tab0) << 16;
+            ri--;  // B is taken
+        }
+    }
+    return ap;
+}
+
 } // namespace qf
 
 struct qf_plan {
@@ -1741,6 +1772,7 @@ struct qf_plan {
     std::vector<qf::Segment> asegs;     // segments of the blocked adjoint
     std::vector<int> aseg_k0, aseg_nstr; // their strings (contiguous: runs are in string order)
     qf::LocalRun *d_alruns = nullptr;
+    qf::AdjPair *d_apairs = nullptr;    // two-run passes of the blocked adjoint, per LocalRun
     double *d_apart = nullptr;          // per-block string sums of the blocked adjoint [adj_grid][K]
     uint8_t *d_ablocked = nullptr;      // 1 for strings of blocked adjoint segments
     unsigned adj_grid = 0;
@@ -1838,7 +1870,7 @@ struct qf_plan {
             (void)hipHostFree(h_theta);
         if (mem != kOwned)
             return;
-        void *bufs[] = {d_runs, d_lruns, d_alruns, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+        void *bufs[] = {d_runs, d_lruns, d_alruns, d_apairs, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_pidx, d_pout,
                         d_dots, d_ss_cls, d_ss_words, d_ss_los};
         for (void *p : bufs)
@@ -2009,11 +2041,12 @@ void set_block_bits(qf_plan &P, int B)
 {
     if (B != 0 && (B < 6 || B > 12 || B > P.n))
         raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
-    void *old[] = {P.d_lruns, P.d_alruns, P.d_apart, P.d_ablocked};
+    void *old[] = {P.d_lruns, P.d_alruns, P.d_apairs, P.d_apart, P.d_ablocked};
     for (void *p : old)
         P.release(p);
     P.d_lruns = nullptr;
     P.d_alruns = nullptr;
+    P.d_apairs = nullptr;
     P.d_apart = nullptr;
     P.d_ablocked = nullptr;
     P.adj_grid = 0;
@@ -2041,6 +2074,12 @@ void set_block_bits(qf_plan &P, int B)
         P.d_alruns = P.dalloc<LocalRun>(lr.size());
         if (!lr.empty())
             P.upload(P.d_alruns, lr.data(), lr.size() * sizeof(LocalRun));
+        if (P.adj_bits == 11) {
+            const std::vector<AdjPair> ap = adjoint_pairs(P.asegs, lr);
+            P.d_apairs = P.dalloc<AdjPair>(ap.size());
+            if (!ap.empty())
+                P.upload(P.d_apairs, ap.data(), ap.size() * sizeof(AdjPair));
+        }
         std::vector<uint8_t> blocked((size_t)P.K, 0);
         for (size_t i = 0; i < P.asegs.size(); i++)
             for (int t = 0; t < P.aseg_nstr[i]; t++)
@@ -2382,10 +2421,12 @@ void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
             const int sk0 = P.aseg_k0[i], nstr = P.aseg_nstr[i];
             if (P.adj_bits == 10)
                 hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10)>), dim3(P.adj_grid), dim3(adj_threads(10)),
-                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_tab, sk0, nstr, P.d_apart, (int)P.K);
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_tab, sk0, nstr, P.d_apart,
+                                   (int)P.K);
             else
                 hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11)>), dim3(P.adj_grid), dim3(adj_threads(11)),
-                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_tab, sk0, nstr, P.d_apart, (int)P.K);
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_tab, sk0, nstr, P.d_apart,
+                                   (int)P.K);
         }
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((P.K + 63) / 64)), dim3(kBlock), 0, s, P.d_apart,
                            (int)P.adj_grid, (int)P.K, P.d_ablocked, P.d_grad);
@@ -2412,12 +2453,12 @@ void launch_pool_sweep(qf_plan &Q, double2 *phi, double2 *lam, hipStream_t s)
             const int sk0 = Q.aseg_k0[i], nstr = Q.aseg_nstr[i];
             if (Q.adj_bits == 10)
                 hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10), false>), dim3(Q.adj_grid),
-                                   dim3(adj_threads(10)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, Q.d_tab, sk0, nstr,
-                                   Q.d_apart, (int)Q.K);
+                                   dim3(adj_threads(10)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_tab,
+                                   sk0, nstr, Q.d_apart, (int)Q.K);
             else
                 hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11), false>), dim3(Q.adj_grid),
-                                   dim3(adj_threads(11)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, Q.d_tab, sk0, nstr,
-                                   Q.d_apart, (int)Q.K);
+                                   dim3(adj_threads(11)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_tab,
+                                   sk0, nstr, Q.d_apart, (int)Q.K);
         }
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((Q.K + 63) / 64)), dim3(kBlock), 0, s, Q.d_apart,
                            (int)Q.adj_grid, (int)Q.K, Q.d_ablocked, Q.d_grad);

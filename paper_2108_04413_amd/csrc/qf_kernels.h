@@ -76,6 +76,27 @@ struct LocalRun {
 };
 static_assert(kMaxRun == 8, "e and s of a LocalRun fill one 64-bit word each");
 
+// Reverse sweep, two runs per LDS pass: run A (LocalRun r) and run B (r - 1)
+// of one segment, both flip runs of rank <= 3 with different flip masks and
+// a0 odd.  Set on A's index (w0 bit 0); the kernel walks a segment's runs
+// from the last and takes a pair wherever its run carries the flag.  Every
+// uniform quantity of the pass is precomputed:
+//   w0:   1 | plo << 8 | phi << 16, the two bits opened in the thread index
+//         (the highest bit of xA and of xB reduced by xA);
+//   bits: run A in bits 0..7, run B in bits 8..15: the table-index offset of
+//         the second pair (3 bits: coordinates of xB for A, of xA for B), its
+//         Z-parity offset (bit 3), par(x & z0) (bit 4), m >> 1 with m = a0 + 1
+//         (bit 5) and the sign of q against the rotation's (bit 6);
+//   tabs: the two runs' table offsets in the segment's table (A low half).
+struct AdjPair {
+    uint32_t w0, xA, xB;
+    uint32_t bA[3], bB[3];
+    uint32_t z0A, z0B;
+    uint32_t bits, tabs;
+    uint32_t pad[3];
+};
+static_assert(sizeof(AdjPair) == 64, "one scalar load of 16 dwords");
+
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
 // are fixed, so the factor (-1)^popcount(y_hi & z_hi) of every string is a
 // per-item constant: strings of a group that share (phase, z_lo) merge into
