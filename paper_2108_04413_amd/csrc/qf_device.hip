@@ -245,15 +245,76 @@ __device__ __forceinline__ void apply_pairs(double2 *st, const double2 *tb, cons
     }
 }
 
+// One run of an ApplyTriple on the thread's coset held in v (v[i] is
+// c0 ^ (i & 1) x0 ^ (i >> 1 & 1) x1 ^ (i >> 2) x2): run J's pairs are
+// (v[i], v[i | 2^J]) for the four i with bit J clear; each pair's table index
+// and Z-parity differ from those of c0 by the tabulated offsets of its
+// partner-run coordinates.  u0, p0: table index and rotation sign bit at c0.
+template <int J>
+__device__ __forceinline__ void triple_run(double2 (&v)[8], const double2 *tb, uint32_t u0, uint32_t p0,
+                                           uint32_t bits)
+{
+    constexpr int K1 = J == 0 ? 1 : 0, K2 = J == 2 ? 1 : 2;
+    const uint32_t d1 = bits & 7u, d2 = (bits >> 3) & 7u, px = ((bits >> 8) & 1u) << 31;
+    double2 cs[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        cs[t] = tb[u0 ^ ((t & 1) ? d1 : 0u) ^ ((t & 2) ? d2 : 0u)];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int i = ((t & 1) << K1) | ((t >> 1) << K2);
+        const uint32_t P1 = (p0 ^ ((t & 1) ? bits >> 6 : 0u) ^ ((t & 2) ? bits >> 7 : 0u)) << 31;
+        rot_pair<false>(cs[t].x, flip31(cs[t].y, P1), flip31(cs[t].y, P1 ^ px), v[i], v[i | (1 << J)]);
+    }
+}
+
+// Three consecutive runs applied in one LDS pass (ApplyTriple), in order
+// (FWD) or as their inverses in reverse order; pbz: the three runs' entries
+// of the sub-cube's fixed-bit parities.
+template <bool FWD>
+__device__ __forceinline__ void apply_three(double2 *st, const double2 *stab, const ApplyTriple &T,
+                                            const uint32_t *pbz, uint32_t tid)
+{
+    const uint32_t c0 = insert0(insert0(insert0(tid, (T.w0 >> 8) & 31u), (T.w0 >> 16) & 31u), T.w0 >> 24);
+    // (the addresses are formed again for the stores: 8 fewer live registers)
+    auto yi = [&](int i) { return c0 ^ ((i & 1) ? T.x[0] : 0u) ^ ((i & 2) ? T.x[1] : 0u) ^ ((i & 4) ? T.x[2] : 0u); };
+    double2 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        v[i] = st[yi(i)];
+    uint32_t u0[3], p0[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const uint32_t pb = pbz[j];
+        u0[j] = (pb & 63u) ^ par(c0 & T.b[j][0]) ^ (par(c0 & T.b[j][1]) << 1) ^ (par(c0 & T.b[j][2]) << 2);
+        // the inverse negates the angle: one more sign on every pair
+        p0[j] = par(c0 & T.z0[j]) ^ (pb >> 6) ^ (T.bits[j] >> 9) ^ (FWD ? 0u : 1u);
+    }
+    const double2 *tb0 = stab + (T.tabs & 1023u), *tb1 = stab + ((T.tabs >> 10) & 1023u),
+                  *tb2 = stab + (T.tabs >> 20);
+    if (FWD) {
+        triple_run<0>(v, tb0, u0[0], p0[0], T.bits[0]);
+        triple_run<1>(v, tb1, u0[1], p0[1], T.bits[1]);
+        triple_run<2>(v, tb2, u0[2], p0[2], T.bits[2]);
+    } else {
+        triple_run<2>(v, tb2, u0[2], p0[2], T.bits[2]);
+        triple_run<1>(v, tb1, u0[1], p0[1], T.bits[1]);
+        triple_run<0>(v, tb0, u0[0], p0[0], T.bits[0]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        st[yi(i)] = v[i];
+}
+
 // Blocked apply: one workgroup per sub-cube of 2^B amplitudes.  Runs of the
 // segment are applied in order (or reversed, with sgn = -1, for U^dagger);
 // the pairs (y, y ^ x) of a run never leave the sub-cube because x is in Q.
 // The segment's (cos, sin) tables are staged in LDS with the sub-cube, and
 // so are the parities of the sub-cube's fixed bits against every run.
 template <int B, int NT>
-__global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, Segment sg,
-                                                        const LocalRun *__restrict__ lruns,
-                                                        const double2 *__restrict__ tab, double sgn)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_block(
+    double2 *__restrict__ psi, Segment sg, const LocalRun *__restrict__ lruns,
+    const ApplyTriple *__restrict__ trip, const double2 *__restrict__ tab, double sgn)
 {
     constexpr uint32_t NB = 1u << B;
     static_assert(NT <= (int)NB && NB % NT == 0, "the workgroup must tile the sub-cube");
@@ -285,9 +346,26 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, S
         st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
     }
     const uint32_t sneg = sgn < 0 ? 1u : 0u;
+    // three runs per pass need a coset of 8 amplitudes per thread (trip is
+    // read only then)
+    constexpr bool kThree = NB == 8u * (uint32_t)NT;
     for (int ri = 0; ri < nr; ri++) {
         const int rr = sgn > 0 ? ri : nr - 1 - ri;
         const LocalRun d = lruns[sg.r0 + rr];
+        if constexpr (kThree) {
+            // a flip run's itm[1] is free: it carries the triple flags
+            if (d.x && (d.itm[1] & (sneg ? 2u : 1u))) {
+                const int r0 = sneg ? rr - 2 : rr;
+                const ApplyTriple T = trip[sg.r0 + r0];
+                __syncthreads();
+                if (sneg)
+                    apply_three<false>(st, stab, T, spbz + r0, threadIdx.x);
+                else
+                    apply_three<true>(st, stab, T, spbz + r0, threadIdx.x);
+                ri += 2;
+                continue;
+            }
+        }
         const double2 *tb = stab + (d.tab - sg.tab0);
         const uint32_t pbz = spbz[rr];
         __syncthreads();
@@ -321,7 +399,11 @@ __global__ __launch_bounds__(NT) void k_apply_block(double2 *__restrict__ psi, S
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; i++) {
-        const uint32_t l = threadIdx.x + (uint32_t)i * NT;
+        uint32_t l = threadIdx.x + (uint32_t)i * NT;
+        // (an empty register barrier: the write-back forms its addresses
+        // again instead of keeping those of the loads live through the run
+        // loop, where they would spill)
+        asm volatile("" : "+v"(l));
         psi[base | (l & lomask) | hoff[l >> sg.q0]] = st[l];
     }
 }
@@ -1757,6 +1839,70 @@ std::vector<AdjPair> adjoint_pairs(const std::vector<Segment> &segs, const std::
     return ap;
 }
 
+// Three-run passes of the blocked apply (ApplyTriple), grouped greedily from
+// each segment's first run.
+std::vector<ApplyTriple> apply_triples(const std::vector<Segment> &segs, const std::vector<LocalRun> &lr)
+{
+    std::vector<ApplyTriple> at(lr.size());
+    std::memset(at.data(), 0, at.size() * sizeof(ApplyTriple));
+    auto par = [](uint32_t v) { return (uint32_t)__builtin_popcount(v) & 1u; };
+    auto hib = [](uint32_t v) { return 31u - (uint32_t)__builtin_clz(v); };
+    auto coords3 = [&](uint32_t y, const LocalRun &d) {
+        return par(y & d.b[0]) | (par(y & d.b[1]) << 1) | (par(y & d.b[2]) << 2);
+    };
+    for (const Segment &sg : segs) {
+        if (!sg.Q)
+            continue;
+        for (int ri = sg.r0; ri + 2 < sg.r1;) {
+            const LocalRun *R[3] = {&lr[(size_t)ri], &lr[(size_t)ri + 1], &lr[(size_t)ri + 2]};
+            bool ok = true;
+            for (const LocalRun *d : R)
+                ok = ok && d->x && d->r <= 3 && (d->a0 & 1u);
+            uint32_t v0 = 0, v1 = 0, v2 = 0, p0 = 0, p1 = 0;
+            if (ok) {
+                v0 = R[0]->x;
+                p0 = hib(v0);
+                v1 = R[1]->x;
+                if ((v1 >> p0) & 1u)
+                    v1 ^= v0;
+                ok = v1 != 0;
+            }
+            if (ok) {
+                p1 = hib(v1);
+                v2 = R[2]->x;
+                if ((v2 >> p0) & 1u)
+                    v2 ^= v0;
+                if ((v2 >> p1) & 1u)
+                    v2 ^= v1;
+                ok = v2 != 0;
+            }
+            if (!ok) {
+                ri++;
+                continue;
+            }
+            uint32_t piv[3] = {p0, p1, hib(v2)};
+            std::sort(piv, piv + 3);
+            ApplyTriple &T = at[(size_t)ri];
+            T.w0 = 1u | piv[0] << 8 | piv[1] << 16 | piv[2] << 24;
+            for (int j = 0; j < 3; j++) {
+                const LocalRun &d = *R[j];
+                const int k1 = j == 0 ? 1 : 0, k2 = j == 2 ? 1 : 2;
+                const uint32_t x1 = R[k1]->x, x2 = R[k2]->x;
+                T.x[j] = d.x;
+                for (int q = 0; q < 3; q++)
+                    T.b[j][q] = d.b[q];
+                T.z0[j] = d.z0;
+                T.bits[j] = coords3(x1, d) | coords3(x2, d) << 3 | par(x1 & d.z0) << 6 | par(x2 & d.z0) << 7 |
+                            par(d.x & d.z0) << 8 | (((d.a0 + 3u) & 3u) >> 1) << 9;
+                T.tabs |= (uint32_t)(d.tab - sg.tab0) << (10 * j);
+            }
+            at[(size_t)ri + 2].w0 = 2u;
+            ri += 3;
+        }
+    }
+    return at;
+}
+
 } // namespace qf
 
 struct qf_plan {
@@ -1768,6 +1914,7 @@ struct qf_plan {
     int block_bits = 0;                 // sub-cube size of blocked apply (0: per-run passes)
     std::vector<qf::Segment> segs;      // Q == 0: a run applied on its own (index r0)
     qf::LocalRun *d_lruns = nullptr;
+    qf::ApplyTriple *d_atrip = nullptr;  // three-run passes of the blocked apply (2^12 sub-cubes), per LocalRun
     int adj_bits = 0;                   // sub-cube size of the blocked adjoint (0: per-run passes)
     std::vector<qf::Segment> asegs;     // segments of the blocked adjoint
     std::vector<int> aseg_k0, aseg_nstr; // their strings (contiguous: runs are in string order)
@@ -1870,7 +2017,7 @@ struct qf_plan {
             (void)hipHostFree(h_theta);
         if (mem != kOwned)
             return;
-        void *bufs[] = {d_runs, d_lruns, d_alruns, d_apairs, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+        void *bufs[] = {d_runs, d_lruns, d_atrip, d_alruns, d_apairs, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_pidx, d_pout,
                         d_dots, d_ss_cls, d_ss_words, d_ss_los};
         for (void *p : bufs)
@@ -2041,10 +2188,11 @@ void set_block_bits(qf_plan &P, int B)
 {
     if (B != 0 && (B < 6 || B > 12 || B > P.n))
         raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
-    void *old[] = {P.d_lruns, P.d_alruns, P.d_apairs, P.d_apart, P.d_ablocked};
+    void *old[] = {P.d_lruns, P.d_atrip, P.d_alruns, P.d_apairs, P.d_apart, P.d_ablocked};
     for (void *p : old)
         P.release(p);
     P.d_lruns = nullptr;
+    P.d_atrip = nullptr;
     P.d_alruns = nullptr;
     P.d_apairs = nullptr;
     P.d_apart = nullptr;
@@ -2061,6 +2209,17 @@ void set_block_bits(qf_plan &P, int B)
         return;
     std::vector<LocalRun> lr;
     build_segments(P.runs, P.n, B, std::min(6, B), P.segs, lr);
+    if (B == 12) {
+        // triple flags in the flip runs' free itm[1] (the kernel tests them on
+        // the descriptor it loads anyway)
+        const std::vector<ApplyTriple> at = apply_triples(P.segs, lr);
+        for (size_t i = 0; i < lr.size(); i++)
+            if (lr[i].x)
+                lr[i].itm[1] = at[i].w0 & 3u;
+        P.d_atrip = P.dalloc<ApplyTriple>(at.size());
+        if (!at.empty())
+            P.upload(P.d_atrip, at.data(), at.size() * sizeof(ApplyTriple));
+    }
     P.d_lruns = P.dalloc<LocalRun>(lr.size());
     if (!lr.empty())
         P.upload(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun));
@@ -2224,7 +2383,7 @@ template <int B> void launch_block(qf_plan &P, double2 *psi, const Segment &sg, 
     // 2^11..2^12 elements while the LDS image still admits two workgroups.
     constexpr int NT = (1 << B) < 512 ? (1 << B) : 512;
     hipLaunchKernelGGL((k_apply_block<B, NT>), dim3((unsigned)(1ull << (P.n - B))), dim3(NT), 0, s, psi, sg,
-                       P.d_lruns, P.d_tab, sgn);
+                       P.d_lruns, P.d_atrip, P.d_tab, sgn);
 }
 
 void launch_runs(qf_plan &P, double2 *psi, bool inverse, hipStream_t s)

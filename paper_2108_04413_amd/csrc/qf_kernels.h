@@ -72,7 +72,9 @@ struct LocalRun {
     int32_t k0, m;                  // the run's strings (as in RunDesc)
     uint8_t e[kMaxRun];
     int8_t s[kMaxRun];
-    uint32_t itm[2];                // per-item table-index and parity parts
+    uint32_t itm[2];                // per-item table-index and parity parts; a flip run
+                                    // uses itm[0] only, and the blocked apply's runs
+                                    // carry their ApplyTriple flags in itm[1]
 };
 static_assert(kMaxRun == 8, "e and s of a LocalRun fill one 64-bit word each");
 
@@ -96,6 +98,32 @@ struct AdjPair {
     uint32_t pad[3];
 };
 static_assert(sizeof(AdjPair) == 64, "one scalar load of 16 dwords");
+
+// Blocked apply, three runs per LDS pass (sub-cubes of 2^12 with 512
+// threads: 8 amplitudes per thread, one coset of span(x0, x1, x2)).  Runs
+// r, r + 1, r + 2 of a segment, flip runs of rank <= 3 with a0 odd and
+// linearly independent flip masks.  The record sits on the first run
+// (w0 bit 0, read by the forward walk); the last run carries w0 = 2 (read by
+// the inverse walk, which then reads the record two runs back).  The same two
+// flags are copied into the runs' LocalRun::itm[1], where the kernel tests
+// them.
+//   w0:   1 | s0 << 8 | s1 << 16 | s2 << 24, the three bits opened in the
+//         thread index (the pivots of the echelon form of x0, x1, x2);
+//   bits[j]: for run j and its two partner runs k1 < k2: the coordinates of
+//         x_k1 (bits 0..2) and x_k2 (3..5), par(x_k1 & z0_j) (6),
+//         par(x_k2 & z0_j) (7), par(x_j & z0_j) (8) and m >> 1 with
+//         m = a0 + 3 (9);
+//   tabs: the three runs' table offsets in the segment's table (10 bits each).
+struct ApplyTriple {
+    uint32_t w0;
+    uint32_t x[3];
+    uint32_t b[3][3];
+    uint32_t z0[3];
+    uint32_t bits[3];
+    uint32_t tabs;
+    uint32_t pad[12];
+};
+static_assert(sizeof(ApplyTriple) == 128, "scalar loads of whole records");
 
 // Tiled energy, merged form.  Inside a tile pair the bits of y above the tile
 // are fixed, so the factor (-1)^popcount(y_hi & z_hi) of every string is a
