@@ -1149,6 +1149,14 @@ __device__ __forceinline__ void adjoint_pairs(double2 *sp, double2 *sl, const do
     accumulate(ut ^ i0, du, qs);
 }
 
+// *p += v for an LDS word that only this lane adds to: the LDS add returns
+// nothing, so the lane does not wait for the old value (the order of the
+// additions is the lane's program order)
+__device__ __forceinline__ void wave_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // One flip-run pair of the reverse sweep on registers: q of the pair (a, b)
 // (phi) and (la, lb) (lambda) as in adjoint_pairs, then the pair undone.
 template <bool SW>
@@ -1173,9 +1181,10 @@ __device__ __forceinline__ double adjoint_one_pair(double2 &a, double2 &b, doubl
 // (c2, c2 ^ xA) with c2 = c0 ^ xB, run B's (c0, c2) and (c1, c1 ^ xB) with
 // c1 = c0 ^ xA.  Table index and Z-parity are affine in y, so each second
 // pair differs from the first by the tabulated uniform offsets.  Both runs'
-// Walsh sums reach red_w (columns 0..7: A, 8..15: B).
+// Walsh sums of the wave are added to sumA and sumB (their 8 entries).
 __device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const double2 *stab, const AdjPair &pr,
-                                            uint32_t pbzA, uint32_t pbzB, uint32_t tid, int lane, double *red_w)
+                                            uint32_t pbzA, uint32_t pbzB, uint32_t tid, int lane, double *sumA,
+                                            double *sumB)
 {
     const uint32_t plo = (pr.w0 >> 8) & 31u, phi = (pr.w0 >> 16) & 31u;
     const uint32_t c0 = insert0(insert0(tid, plo), phi);
@@ -1233,8 +1242,8 @@ __device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const doub
         w[h] = wave_sum8(acc, lane);
     }
     if (sum8_writer(lane)) {
-        red_w[sum8_index(lane)] = w[0];
-        red_w[kMaxRun + sum8_index(lane)] = w[1];
+        wave_add(&sumA[sum8_index(lane)], w[0]);
+        wave_add(&sumB[sum8_index(lane)], w[1]);
     }
 }
 
@@ -1245,6 +1254,7 @@ template <int B, int NT, bool UNDO = true>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint_block(double2 *__restrict__ phi, double2 *__restrict__ lam, int n,
                                                       Segment sg, const LocalRun *__restrict__ lruns,
                                                       const AdjPair *__restrict__ apairs,
+                                                      const uint32_t *__restrict__ smap,
                                                       const double2 *__restrict__ tab, int sk0, int nstr,
                                                       double *__restrict__ part, int K)
 {
@@ -1254,10 +1264,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr int NW = NT / 64;
     __shared__ double2 sp[NB], sl[NB];
     __shared__ uint32_t hoff[64];
-    __shared__ double2 stab[kSegTab];
-    __shared__ double lacc[kSegStr];
-    __shared__ double red[NW][2 * kMaxRun];
-    __shared__ uint32_t spbz[kSegRuns];
+    __shared__ double2 stab[kAdjTab];
+    // per wave and run, the run's 8 sums over this workgroup's sub-cubes so
+    // far (each wave adds to its own: no barrier, no cross-wave step per run)
+    __shared__ double wred[NW][kAdjRuns][kMaxRun];
+    __shared__ uint32_t spbz[kAdjRuns];
     static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
     // two runs per pass need a coset of 4 amplitudes per thread (apairs is
     // read only then)
@@ -1276,8 +1287,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if constexpr (UNDO)
         for (int t = (int)tid; t < sg.ntab; t += NT)
             stab[t] = tab[sg.tab0 + t];
-    for (int t = (int)tid; t < nstr; t += NT)
-        lacc[t] = 0.0;
+    for (int t = (int)tid; t < NW * kAdjRuns * kMaxRun; t += NT)
+        (&wred[0][0][0])[t] = 0.0;
     const uint32_t nsub = 1u << (n - B);
     const int nr = sg.r1 - sg.r0;
     for (uint32_t sc = blockIdx.x; sc < nsub; sc += gridDim.x) {
@@ -1298,31 +1309,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 if (pr.w0 & 1u) {
                     const uint32_t pbzA = spbz[ri], pbzB = spbz[ri - 1];
                     __syncthreads();  // the previous run's updates are visible
-                    adjoint_two(sp, sl, stab, pr, pbzA, pbzB, tid, lane, red[wave]);
-                    __syncthreads();
-                    if (tid < 2u * kMaxRun) {
-                        const LocalRun &dA = lruns[sg.r0 + ri], &dB = lruns[sg.r0 + ri - 1];
-                        // lanes 0..7: run A's strings, 8..15: run B's (Walsh
-                        // column e_k, sign s_k, as in the one-run case)
-                        const bool hiB = tid >= (uint32_t)kMaxRun;
-                        const int k = (int)(tid & (kMaxRun - 1));
-                        uint64_t eA, sA, eB, sB;
-                        __builtin_memcpy(&eA, dA.e, sizeof eA);
-                        __builtin_memcpy(&sA, dA.s, sizeof sA);
-                        __builtin_memcpy(&eB, dB.e, sizeof eB);
-                        __builtin_memcpy(&sB, dB.s, sizeof sB);
-                        const uint64_t ep = hiB ? eB : eA, spk = ((hiB ? sB : sA) >> 7) & 0x0101010101010101ull;
-                        if (k < (hiB ? dB.m : dA.m)) {
-                            const int col = (hiB ? kMaxRun : 0) + (int)((ep >> (8 * k)) & 0xffu);
-                            double v = 0.0;
-#pragma unroll
-                            for (int w = 0; w < NW; w++)
-                                v += red[w][col];
-                            if ((spk >> (8 * k)) & 1u)
-                                v = -v;
-                            lacc[(hiB ? dB.k0 : dA.k0) - sk0 + k] += v;
-                        }
-                    }
+                    adjoint_two(sp, sl, stab, pr, pbzA, pbzB, tid, lane, wred[wave][ri], wred[wave][ri - 1]);
                     ri--;
                     continue;
                 }
@@ -1397,26 +1384,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             {
                 const double h = wave_sum8(acc, lane);
                 if (sum8_writer(lane))
-                    red[wave][sum8_index(lane)] = h;
-            }
-            __syncthreads();
-            if (tid < (uint32_t)d.m) {
-                // lane k's string fields from the uniform descriptor, packed
-                // into 64-bit words (indexing its register copy by lane would
-                // go through scratch memory)
-                // (byte k of e and s is string k's; the sign bit of s_k moves to bit 0)
-                uint64_t epk, spk;
-                __builtin_memcpy(&epk, d.e, sizeof epk);
-                __builtin_memcpy(&spk, d.s, sizeof spk);
-                spk = (spk >> 7) & 0x0101010101010101ull;
-                const int col = walsh ? (int)((epk >> (8 * tid)) & 0xffu) : (int)tid;
-                double v = 0.0;
-#pragma unroll
-                for (int w = 0; w < NW; w++)
-                    v += red[w][col];
-                if (walsh && ((spk >> (8 * tid)) & 1u))
-                    v = -v;
-                lacc[d.k0 - sk0 + (int)tid] += v;
+                    wave_add(&wred[wave][ri][sum8_index(lane)], h);
             }
         }
         __syncthreads();
@@ -1430,12 +1398,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
         }
     }
-    // this workgroup's sums; k_grad_reduce adds the workgroups after the
-    // sweep (no cross-workgroup fence here: on a multi-XCD device a release
-    // at agent scope writes back the whole L2, sub-cube stores included)
+    // this workgroup's string sums, the waves added in order: string k of
+    // run r takes s_k times Walsh sum e_k (rank <= 3) or sum k.  k_grad_reduce
+    // adds the workgroups after the sweep (no cross-workgroup fence here: on
+    // a multi-XCD device a release at agent scope writes back the whole L2,
+    // sub-cube stores included)
+    // (smap: the run, column and sign of each string, per string of the plan)
     __syncthreads();
-    for (int t = (int)tid; t < nstr; t += NT)
-        part[(size_t)blockIdx.x * K + sk0 + t] = lacc[t];
+    for (int t = (int)tid; t < nstr; t += NT) {
+        const uint32_t e = smap[sk0 + t];
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+            v += wred[w][e >> 4][e & 7u];
+        part[(size_t)blockIdx.x * K + sk0 + t] = (e & 8u) ? -v : v;
+    }
 }
 
 // grad[k] = 2 sum_b part[b][k] in workgroup order, for the strings of
@@ -1696,10 +1673,12 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
 
 // Greedy segmentation of the run sequence for blocked application: extend a
 // segment while the union of its flip masks and the lowest q0 qubits has at
-// most B qubits; pad Q with the lowest free qubits to exactly B.  A run whose
-// mask alone does not fit becomes a segment with Q = 0 (applied by itself).
+// most B qubits, it has at most max_runs runs (max_runs > 0) and its tables
+// at most max_tab entries; pad Q with the lowest free qubits to exactly B.  A
+// run whose mask alone does not fit becomes a segment with Q = 0 (applied by
+// itself).
 void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std::vector<Segment> &segs,
-                    std::vector<LocalRun> &lr)
+                    std::vector<LocalRun> &lr, int max_runs, int max_tab)
 {
     segs.clear();
     lr.clear();
@@ -1710,8 +1689,8 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
         size_t j = i;
         int ntab = 0;
         int nstr = 0;
-        while (j < runs.size() && __builtin_popcount(cur | runs[j].x) <= B && ntab + (1 << runs[j].r) <= kSegTab &&
-               nstr + runs[j].m <= kSegStr) {
+        while (j < runs.size() && __builtin_popcount(cur | runs[j].x) <= B && ntab + (1 << runs[j].r) <= max_tab &&
+               nstr + runs[j].m <= kSegStr && (max_runs == 0 || (int)(j - i) < max_runs)) {
             cur |= runs[j].x;
             ntab += 1 << runs[j].r;
             nstr += runs[j].m;
@@ -1920,6 +1899,7 @@ struct qf_plan {
     std::vector<int> aseg_k0, aseg_nstr; // their strings (contiguous: runs are in string order)
     qf::LocalRun *d_alruns = nullptr;
     qf::AdjPair *d_apairs = nullptr;    // two-run passes of the blocked adjoint, per LocalRun
+    uint32_t *d_asmap = nullptr;        // per string of a blocked adjoint segment: run, Walsh column, sign
     double *d_apart = nullptr;          // per-block string sums of the blocked adjoint [adj_grid][K]
     uint8_t *d_ablocked = nullptr;      // 1 for strings of blocked adjoint segments
     unsigned adj_grid = 0;
@@ -2017,7 +1997,7 @@ struct qf_plan {
             (void)hipHostFree(h_theta);
         if (mem != kOwned)
             return;
-        void *bufs[] = {d_runs, d_lruns, d_atrip, d_alruns, d_apairs, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
+        void *bufs[] = {d_runs, d_lruns, d_atrip, d_alruns, d_apairs, d_asmap, d_apart, d_ablocked, d_theta, d_tab, d_grad, d_groups, d_z, d_c, d_partials, d_counter, d_result,
                         d_classes, d_work_off, d_tgroups, d_recs, d_vcls, d_pidx, d_pout,
                         d_dots, d_ss_cls, d_ss_words, d_ss_los};
         for (void *p : bufs)
@@ -2188,11 +2168,12 @@ void set_block_bits(qf_plan &P, int B)
 {
     if (B != 0 && (B < 6 || B > 12 || B > P.n))
         raise(QF_E_ARG, "blocked apply needs 6 <= block bits <= min(12, n_qubits), or 0");
-    void *old[] = {P.d_lruns, P.d_atrip, P.d_alruns, P.d_apairs, P.d_apart, P.d_ablocked};
+    void *old[] = {P.d_lruns, P.d_atrip, P.d_alruns, P.d_apairs, P.d_asmap, P.d_apart, P.d_ablocked};
     for (void *p : old)
         P.release(p);
     P.d_lruns = nullptr;
     P.d_atrip = nullptr;
+    P.d_asmap = nullptr;
     P.d_alruns = nullptr;
     P.d_apairs = nullptr;
     P.d_apart = nullptr;
@@ -2224,7 +2205,7 @@ void set_block_bits(qf_plan &P, int B)
     if (!lr.empty())
         P.upload(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun));
     if (P.adj_bits) {
-        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr);
+        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr, kAdjRuns, kAdjTab);
         for (const Segment &sg : P.asegs) {
             const int k0 = sg.Q ? lr[(size_t)sg.r0].k0 : 0;
             P.aseg_k0.push_back(k0);
@@ -2239,6 +2220,21 @@ void set_block_bits(qf_plan &P, int B)
             if (!ap.empty())
                 P.upload(P.d_apairs, ap.data(), ap.size() * sizeof(AdjPair));
         }
+        // string k of local run r: Walsh column e_k (rank <= 3) or k, the sign of s_k
+        std::vector<uint32_t> smap((size_t)P.K, 0u);
+        for (const Segment &sg : P.asegs) {
+            if (!sg.Q)
+                continue;
+            for (int r = sg.r0; r < sg.r1; r++) {
+                const LocalRun &L = lr[(size_t)r];
+                const bool walsh = L.r <= 3;
+                for (int k = 0; k < L.m; k++)
+                    smap[(size_t)(L.k0 + k)] = (uint32_t)(walsh ? L.e[k] : k) | (walsh && L.s[k] < 0 ? 8u : 0u) |
+                                               (uint32_t)(r - sg.r0) << 4;
+            }
+        }
+        P.d_asmap = P.dalloc<uint32_t>((size_t)P.K);
+        P.upload(P.d_asmap, smap.data(), smap.size() * sizeof(uint32_t));
         std::vector<uint8_t> blocked((size_t)P.K, 0);
         for (size_t i = 0; i < P.asegs.size(); i++)
             for (int t = 0; t < P.aseg_nstr[i]; t++)
@@ -2580,11 +2576,11 @@ void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
             const int sk0 = P.aseg_k0[i], nstr = P.aseg_nstr[i];
             if (P.adj_bits == 10)
                 hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10)>), dim3(P.adj_grid), dim3(adj_threads(10)),
-                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_tab, sk0, nstr, P.d_apart,
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_asmap, P.d_tab, sk0, nstr, P.d_apart,
                                    (int)P.K);
             else
                 hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11)>), dim3(P.adj_grid), dim3(adj_threads(11)),
-                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_tab, sk0, nstr, P.d_apart,
+                                   0, s, phi, lam, P.n, sg, P.d_alruns, P.d_apairs, P.d_asmap, P.d_tab, sk0, nstr, P.d_apart,
                                    (int)P.K);
         }
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((P.K + 63) / 64)), dim3(kBlock), 0, s, P.d_apart,
@@ -2612,11 +2608,11 @@ void launch_pool_sweep(qf_plan &Q, double2 *phi, double2 *lam, hipStream_t s)
             const int sk0 = Q.aseg_k0[i], nstr = Q.aseg_nstr[i];
             if (Q.adj_bits == 10)
                 hipLaunchKernelGGL((k_adjoint_block<10, adj_threads(10), false>), dim3(Q.adj_grid),
-                                   dim3(adj_threads(10)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_tab,
+                                   dim3(adj_threads(10)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_asmap, Q.d_tab,
                                    sk0, nstr, Q.d_apart, (int)Q.K);
             else
                 hipLaunchKernelGGL((k_adjoint_block<11, adj_threads(11), false>), dim3(Q.adj_grid),
-                                   dim3(adj_threads(11)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_tab,
+                                   dim3(adj_threads(11)), 0, s, phi, lam, Q.n, sg, Q.d_alruns, nullptr, Q.d_asmap, Q.d_tab,
                                    sk0, nstr, Q.d_apart, (int)Q.K);
         }
         hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((Q.K + 63) / 64)), dim3(kBlock), 0, s, Q.d_apart,

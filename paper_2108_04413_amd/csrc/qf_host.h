@@ -65,10 +65,11 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
                          std::vector<uint32_t> &words, std::vector<SsLo> &los);
 
 // Greedy split of a run sequence into segments whose flip masks fit one set
-// of B qubits containing qubits 0..q0-1 (see qf_device.hip); appends the
+// of B qubits containing qubits 0..q0-1 (see qf_device.hip), at most
+// max_runs runs (0: no limit) and max_tab table entries each; appends the
 // segments' LocalRuns to lr (cleared first).  A Segment with Q == 0 holds
 // one run too wide for a sub-cube; its r0 indexes `runs`.
 void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std::vector<Segment> &segs,
-                    std::vector<LocalRun> &lr);
+                    std::vector<LocalRun> &lr, int max_runs = 0, int max_tab = kSegTab);
 
 } // namespace qf
