@@ -1008,11 +1008,10 @@ __global__ __launch_bounds__(kBlock) void k_sigma(const double2 *__restrict__ ps
 constexpr int kSsNT = 256;
 
 template <bool IMAG>
-__global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restrict__ psi, double2 *__restrict__ lam,
-                                                        int n, const SsCls *__restrict__ cls, int ncls,
-                                                        const uint32_t *__restrict__ gwords,
-                                                        const SsLo *__restrict__ los, double *partials,
-                                                        unsigned *counter, double *result)
+__device__ __forceinline__ void sigma_stream_kernel(const double2 *__restrict__ psi, double2 *__restrict__ lam, int n,
+                                                    const SsCls *__restrict__ cls, int ncls,
+                                                    const uint32_t *__restrict__ gwords, const SsLo *__restrict__ los,
+                                                    double *partials, unsigned *counter, double *result)
 {
     __shared__ double2 tile[1u << kSsL];
     __shared__ uint4 wlo[kSsNT];    // z_lo | flags, 0, C (lo, hi word)
@@ -1020,6 +1019,28 @@ __global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restric
     double vals[1] = {sigma_stream<kSsNT, IMAG>(psi, lam, blockIdx.x, gridDim.x, 1u << (n - kSsL), cls, ncls,
                                                 gwords, los, tile, wlo, wgw)};
     reduce_finish<1, kSsNT>(vals, partials, counter, result, 1.0, 1);
+}
+
+template <bool IMAG>
+__global__ __launch_bounds__(kSsNT) void k_sigma_stream(const double2 *__restrict__ psi, double2 *__restrict__ lam,
+                                                        int n, const SsCls *__restrict__ cls, int ncls,
+                                                        const uint32_t *__restrict__ gwords,
+                                                        const SsLo *__restrict__ los, double *partials,
+                                                        unsigned *counter, double *result)
+{
+    sigma_stream_kernel<IMAG>(psi, lam, n, cls, ncls, gwords, los, partials, counter, result);
+}
+
+// Real phases only: held to 128 registers, four waves per SIMD (the LDS
+// image admits four workgroups per CU; at 132 registers only three fit; the
+// bound spills one 8-byte value per tile, outside the group loop).
+template <>
+__global__ __launch_bounds__(kSsNT) __attribute__((amdgpu_waves_per_eu(4))) void k_sigma_stream<false>(
+    const double2 *__restrict__ psi, double2 *__restrict__ lam, int n, const SsCls *__restrict__ cls, int ncls,
+    const uint32_t *__restrict__ gwords, const SsLo *__restrict__ los, double *partials, unsigned *counter,
+    double *result)
+{
+    sigma_stream_kernel<false>(psi, lam, n, cls, ncls, gwords, los, partials, counter, result);
 }
 
 // One reverse-sweep step over a run: grad[k0+k] = 2 Im <lam|P_k|phi>, then
@@ -1291,10 +1312,26 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         (&wred[0][0][0])[t] = 0.0;
     const uint32_t nsub = 1u << (n - B);
     const int nr = sg.r1 - sg.r0;
+    // thread r < nr keeps run r's full-space masks (z0f, bf) in registers for
+    // the per-sub-cube parities (nr <= kAdjRuns < NT)
+    uint32_t pm[kMaxRank + 1] = {};
+    if (tid < (uint32_t)nr) {
+        const LocalRun &d = lruns[sg.r0 + (int)tid];
+        pm[kMaxRank] = d.z0f;
+#pragma unroll
+        for (int q = 0; q < kMaxRank; q++)
+            pm[q] = d.bf[q];
+    }
     for (uint32_t sc = blockIdx.x; sc < nsub; sc += gridDim.x) {
         const uint32_t base = subcube_base(sc, sg);
         // (the previous sub-cube's runs have all read spbz: barrier before its write-back)
-        sub_parities(lruns, sg.r0, nr, base, spbz, (int)tid, NT);
+        if (tid < (uint32_t)nr) {
+            uint32_t v = par(base & pm[kMaxRank]) << 6;
+#pragma unroll
+            for (int q = 0; q < kMaxRank; q++)
+                v |= par(base & pm[q]) << q;
+            spbz[tid] = v;
+        }
         __syncthreads();  // tables staged; the previous sub-cube is written back
 #pragma unroll
         for (int i = 0; i < PER; i++) {
