@@ -173,6 +173,9 @@ static_assert(kBT == 512 && kSub >= (1 << kSsL) + kBT + kBT / 4,
               "the sigma tile and its lo-term and group windows fit the sub-cube image");
 // pairs per thread in the common sub-cubes (2^12 forward, 2^11 reverse), which get unrolled variants
 constexpr int kApplyPairs = kSub / 2 / kBT, kAdjPairs = kSub / 4 / kBT;
+// runs of one segment (their fixed-bit parities in LDS; with the two-run
+// reduction array this keeps the LDS image within two workgroups per CU)
+constexpr int kBatchSegRuns = 256;
 
 // member's slice [b, e) of `units`, in whole tiles of kBT * kItems
 __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
@@ -284,8 +287,8 @@ __device__ __forceinline__ void sub_apply_pairs(double2 *st, const double2 *tb, 
 // 0 for 2^B
 template <uint32_t FIXNB>
 __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const Segment &sg,
-                          const LocalRun *__restrict__ lr, const double2 *tab, const uint32_t *hoff, double2 *st,
-                          uint32_t *pbzs)
+                          const LocalRun *__restrict__ lr, const ApplyTriple *__restrict__ trip, const double2 *tab,
+                          const uint32_t *hoff, double2 *st, uint32_t *pbzs)
 {
     const uint32_t NB = FIXNB ? FIXNB : 1u << B, lomask = (1u << sg.q0) - 1u;
     // (the previous sub-cube's runs have all read pbzs: barrier before its write-back)
@@ -295,6 +298,16 @@ __device__ void sub_apply(double2 *__restrict__ psi, int B, uint32_t base, const
         st[l] = psi[base | (l & lomask) | hoff[l >> sg.q0]];
     for (int ri = sg.r0; ri < sg.r1; ri++) {
         const LocalRun d = lr[ri];
+        if constexpr (FIXNB == 8u * kBT) {
+            // three runs per pass (ApplyTriple; flags in the flip runs' itm[1])
+            if (d.x && (d.itm[1] & 1u)) {
+                const ApplyTriple T = trip[ri];
+                __syncthreads();
+                apply_three<true>(st, tab, T, pbzs + (ri - sg.r0), threadIdx.x);
+                ri += 2;
+                continue;
+            }
+        }
         const double2 *tb = tab + (d.tab - sg.tab0);
         const uint32_t pbz = pbzs[ri - sg.r0];
         __syncthreads();
@@ -410,9 +423,9 @@ __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, cons
 // FIXNB: the sub-cube size when it is the common 2^11, 0 for 2^B
 template <uint32_t FIXNB>
 __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, int B, uint32_t base,
-                            const Segment &sg, const LocalRun *__restrict__ lr, const double2 *tab,
-                            const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc, double (*red)[kMaxRun],
-                            int sk0, uint32_t *pbzs)
+                            const Segment &sg, const LocalRun *__restrict__ lr, const AdjPair *__restrict__ apairs,
+                            const double2 *tab, const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc,
+                            double (*red)[2 * kMaxRun], int sk0, uint32_t *pbzs)
 {
     const uint32_t NB = FIXNB ? FIXNB : 1u << B, lomask = (1u << sg.q0) - 1u;
     const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
@@ -424,6 +437,36 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         sl[l] = lam[y];
     }
     for (int ri = sg.r1 - 1; ri >= sg.r0; ri--) {
+        if constexpr (FIXNB == 4u * kBT) {
+            // two runs per pass (AdjPair), the sums reduced per pass as below
+            const AdjPair pr = apairs[ri];
+            if (pr.w0 & 1u) {
+                const uint32_t pbzA = pbzs[ri - sg.r0], pbzB = pbzs[ri - 1 - sg.r0];
+                __syncthreads();  // the previous run's updates are visible
+                adjoint_two<false>(sp, sl, tab, pr, pbzA, pbzB, threadIdx.x, lane, red[wave], red[wave] + kMaxRun);
+                __syncthreads();
+                if (threadIdx.x < 2u * kMaxRun) {
+                    // lanes 0..7: run A's strings, 8..15: run B's
+                    const LocalRun &dA = lr[ri], &dB = lr[ri - 1];
+                    const bool hiB = threadIdx.x >= (uint32_t)kMaxRun;
+                    const int k = (int)(threadIdx.x & (kMaxRun - 1));
+                    const LocalRun &d = hiB ? dB : dA;
+                    if (k < d.m) {
+                        const bool walsh = d.r <= 3;
+                        const int col = (hiB ? kMaxRun : 0) + (walsh ? (int)d.e[k] : k);
+                        double v = 0.0;
+#pragma unroll
+                        for (int w = 0; w < kBW; w++)
+                            v += red[w][col];
+                        if (walsh && d.s[k] < 0)
+                            v = -v;
+                        lacc[d.k0 - sk0 + k] += v;
+                    }
+                }
+                ri--;
+                continue;
+            }
+        }
         const LocalRun d = lr[ri];
         const double2 *tb = tab + (d.tab - sg.tab0);
         const uint32_t pbz = pbzs[ri - sg.r0];
@@ -690,6 +733,8 @@ __global__ void k_batch_reset(unsigned *sync, int nentries, unsigned *ticket, un
 __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const BatchEntry *__restrict__ entries, int nentries,
                                                unsigned total_tickets, const RunDesc *__restrict__ runs,
                                                const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
+                                               const ApplyTriple *__restrict__ atrip,
+                                               const AdjPair *__restrict__ apairs,
                                                const GroupDesc *__restrict__ groups,
                                                const SsCls *__restrict__ sscls, const uint32_t *__restrict__ sswords,
                                                const SsLo *__restrict__ sslos, double2 *__restrict__ tabs,
@@ -704,9 +749,9 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double2 s_tab[kSegTab];
     __shared__ uint32_t s_hoff[64];
     __shared__ double s_lacc[kSegStr];
-    __shared__ double s_red[kBW][kMaxRun];
+    __shared__ double s_red[kBW][2 * kMaxRun];
     __shared__ double s_part[kMaxRun];
-    __shared__ uint32_t s_pbz[kSegRuns];
+    __shared__ uint32_t s_pbz[kBatchSegRuns];
     for (;;) {
         if (threadIdx.x == 0) {
             const unsigned t = atomicAdd(ticket, 1u);
@@ -773,9 +818,10 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
                     const uint32_t base = subcube_base(sc, sg);
                     if (en.Bapp == 12)
-                        sub_apply<(uint32_t)kSub>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
+                        sub_apply<(uint32_t)kSub>(phi, en.Bapp, base, sg, lr, atrip + en.alr0, s_tab, s_hoff, s_sub,
+                                                  s_pbz);
                     else
-                        sub_apply<0>(phi, en.Bapp, base, sg, lr, s_tab, s_hoff, s_sub, s_pbz);
+                        sub_apply<0>(phi, en.Bapp, base, sg, lr, atrip + en.alr0, s_tab, s_hoff, s_sub, s_pbz);
                 }
             }
             team_sync(W, ts, ++epoch, spin_limit, ierr);
@@ -835,11 +881,12 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
                     const uint32_t base = subcube_base(sc, sg);
                     if (en.Badj == 11)
-                        sub_adjoint<(uint32_t)kSub / 2>(phi, lam, en.Badj, base, sg, lr, s_tab, s_hoff, s_sub,
-                                                        s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
+                        sub_adjoint<(uint32_t)kSub / 2>(phi, lam, en.Badj, base, sg, lr, apairs + en.dlr0, s_tab,
+                                                        s_hoff, s_sub, s_sub + (kSub / 2), s_lacc, s_red, sk0,
+                                                        s_pbz);
                     else
-                        sub_adjoint<0>(phi, lam, en.Badj, base, sg, lr, s_tab, s_hoff, s_sub, s_sub + (kSub / 2),
-                                       s_lacc, s_red, sk0, s_pbz);
+                        sub_adjoint<0>(phi, lam, en.Badj, base, sg, lr, apairs + en.dlr0, s_tab, s_hoff, s_sub,
+                                       s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
                 }
                 __syncthreads();
                 for (int t = (int)threadIdx.x; t < nstr; t += kBT)
@@ -907,6 +954,8 @@ struct qf_batch {
     qf::SsCls *d_sscls = nullptr;
     uint32_t *d_sswords = nullptr;
     qf::SsLo *d_sslos = nullptr;
+    qf::ApplyTriple *d_atrip = nullptr;
+    qf::AdjPair *d_apairs = nullptr;
     double2 *d_tabs = nullptr;  // (cos, sin) tables of every instance's runs, filled in the launch
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
@@ -981,6 +1030,8 @@ struct BatchHost {
     std::vector<RunDesc> runs;
     std::vector<Segment> segs;
     std::vector<LocalRun> lruns;
+    std::vector<ApplyTriple> atrip;  // parallel to lruns: forward three-run passes
+    std::vector<AdjPair> apairs;     // parallel to lruns: reverse two-run passes
     std::vector<GroupDesc> groups;
     std::vector<SsCls> sscls;
     std::vector<uint32_t> sswords;
@@ -1082,9 +1133,23 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::vector<Segment> sa, sd;
         std::vector<LocalRun> la, ld;
         if (!r.empty()) {
-            build_segments(r, n, Bapp, std::min(6, Bapp), sa, la);
-            build_segments(r, n, Badj, std::min(6, Badj), sd, ld);
+            build_segments(r, n, Bapp, std::min(6, Bapp), sa, la, kBatchSegRuns);
+            build_segments(r, n, Badj, std::min(6, Badj), sd, ld, kBatchSegRuns);
         }
+        // multi-run passes on the full-size sub-cubes: three runs forward
+        // (flags in the flip runs' itm[1]), two runs in the reverse sweep
+        std::vector<ApplyTriple> at(la.size());
+        std::memset(at.data(), 0, at.size() * sizeof(ApplyTriple));
+        if (Bapp == 12 && !la.empty()) {
+            at = apply_triples(sa, la);
+            for (size_t j = 0; j < la.size(); j++)
+                if (la[j].x)
+                    la[j].itm[1] = at[j].w0 & 3u;
+        }
+        std::vector<AdjPair> ap(ld.size());
+        std::memset(ap.data(), 0, ap.size() * sizeof(AdjPair));
+        if (Badj == 11 && !ld.empty())
+            ap = adjoint_pairs(sd, ld);
         BatchEntry e;
         std::memset(&e, 0, sizeof e);
         e.n = n;
@@ -1100,6 +1165,10 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         T.segs.insert(T.segs.end(), sd.begin(), sd.end());
         T.lruns.insert(T.lruns.end(), la.begin(), la.end());
         T.lruns.insert(T.lruns.end(), ld.begin(), ld.end());
+        T.atrip.insert(T.atrip.end(), at.begin(), at.end());
+        T.atrip.resize(T.lruns.size());
+        T.apairs.resize(T.lruns.size() - ld.size());
+        T.apairs.insert(T.apairs.end(), ap.begin(), ap.end());
         e.W = B.W[(size_t)i];
         e.nruns = (int32_t)r.size();
         e.G = (int32_t)gd.size();
@@ -1150,13 +1219,13 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[19];
+    size_t off[21];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[19] = {
+    const size_t sizes[21] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
@@ -1165,10 +1234,11 @@ Layout batch_layout(const qf_batch &B, const BatchHost &T)
         (size_t)B.count * sizeof(double), (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double),
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
         std::max<size_t>(T.sscls.size(), 1) * sizeof(SsCls), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2),
-        std::max<size_t>(T.sswords.size(), 1) * sizeof(uint32_t), std::max<size_t>(T.sslos.size(), 1) * sizeof(SsLo)};
+        std::max<size_t>(T.sswords.size(), 1) * sizeof(uint32_t), std::max<size_t>(T.sslos.size(), 1) * sizeof(SsLo),
+        std::max<size_t>(T.lruns.size(), 1) * sizeof(ApplyTriple), std::max<size_t>(T.lruns.size(), 1) * sizeof(AdjPair)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 19; i++) {
+    for (int i = 0; i < 21; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -1197,6 +1267,8 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_tabs = (double2 *)(base + L.off[16]);
     B.d_sswords = (uint32_t *)(base + L.off[17]);
     B.d_sslos = (SsLo *)(base + L.off[18]);
+    B.d_atrip = (ApplyTriple *)(base + L.off[19]);
+    B.d_apairs = (AdjPair *)(base + L.off[20]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -1212,9 +1284,14 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
         QF_HIP(hipMemcpyAsync(B.d_runs, T.runs.data(), T.runs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, s));
     if (!T.segs.empty())
         QF_HIP(hipMemcpyAsync(B.d_segs, T.segs.data(), T.segs.size() * sizeof(Segment), hipMemcpyHostToDevice, s));
-    if (!T.lruns.empty())
+    if (!T.lruns.empty()) {
         QF_HIP(hipMemcpyAsync(B.d_lruns, T.lruns.data(), T.lruns.size() * sizeof(LocalRun), hipMemcpyHostToDevice,
                               s));
+        QF_HIP(hipMemcpyAsync(B.d_atrip, T.atrip.data(), T.atrip.size() * sizeof(ApplyTriple), hipMemcpyHostToDevice,
+                              s));
+        QF_HIP(hipMemcpyAsync(B.d_apairs, T.apairs.data(), T.apairs.size() * sizeof(AdjPair), hipMemcpyHostToDevice,
+                              s));
+    }
     QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
                           s));
     if (!T.sscls.empty()) {
@@ -1237,7 +1314,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_segs, B.d_lruns, B.d_groups, B.d_sscls, B.d_sswords, B.d_sslos, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_atrip, B.d_apairs, B.d_groups, B.d_sscls, B.d_sswords, B.d_sslos, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }

@@ -72,4 +72,12 @@ void sigma_stream_tables(const std::vector<GroupDesc> &gd, const std::vector<uin
 void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std::vector<Segment> &segs,
                     std::vector<LocalRun> &lr, int max_runs = 0, int max_tab = kSegTab);
 
+// Two-run passes of a blocked reverse sweep over (segs, lr): one AdjPair per
+// LocalRun, set on the first run undone of each pair (see qf_kernels.h).
+std::vector<AdjPair> adjoint_pairs(const std::vector<Segment> &segs, const std::vector<LocalRun> &lr);
+
+// Three-run passes of a blocked apply on 2^12 sub-cubes: one ApplyTriple per
+// LocalRun (the caller copies the w0 flags into the flip runs' itm[1]).
+std::vector<ApplyTriple> apply_triples(const std::vector<Segment> &segs, const std::vector<LocalRun> &lr);
+
 } // namespace qf

@@ -492,6 +492,173 @@ __device__ __forceinline__ void group_d4(const GroupDesc &g, const uint32_t *__r
     }
 }
 
+// ---------------------------------------------------------------- multi-run passes
+// One run of an ApplyTriple on the thread's coset held in v (v[i] is
+// c0 ^ (i & 1) x0 ^ (i >> 1 & 1) x1 ^ (i >> 2) x2): run J's pairs are
+// (v[i], v[i | 2^J]) for the four i with bit J clear; each pair's table index
+// and Z-parity differ from those of c0 by the tabulated offsets of its
+// partner-run coordinates.  u0, p0: table index and rotation sign bit at c0.
+template <int J>
+__device__ __forceinline__ void triple_run(double2 (&v)[8], const double2 *tb, uint32_t u0, uint32_t p0,
+                                           uint32_t bits)
+{
+    constexpr int K1 = J == 0 ? 1 : 0, K2 = J == 2 ? 1 : 2;
+    const uint32_t d1 = bits & 7u, d2 = (bits >> 3) & 7u, px = ((bits >> 8) & 1u) << 31;
+    double2 cs[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        cs[t] = tb[u0 ^ ((t & 1) ? d1 : 0u) ^ ((t & 2) ? d2 : 0u)];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int i = ((t & 1) << K1) | ((t >> 1) << K2);
+        const uint32_t P1 = (p0 ^ ((t & 1) ? bits >> 6 : 0u) ^ ((t & 2) ? bits >> 7 : 0u)) << 31;
+        rot_pair<false>(cs[t].x, flip31(cs[t].y, P1), flip31(cs[t].y, P1 ^ px), v[i], v[i | (1 << J)]);
+    }
+}
+
+// Three consecutive runs applied in one LDS pass (ApplyTriple), in order
+// (FWD) or as their inverses in reverse order; pbz: the three runs' entries
+// of the sub-cube's fixed-bit parities.
+template <bool FWD>
+__device__ __forceinline__ void apply_three(double2 *st, const double2 *stab, const ApplyTriple &T,
+                                            const uint32_t *pbz, uint32_t tid)
+{
+    const uint32_t c0 = insert0(insert0(insert0(tid, (T.w0 >> 8) & 31u), (T.w0 >> 16) & 31u), T.w0 >> 24);
+    // (the addresses are formed again for the stores: 8 fewer live registers)
+    auto yi = [&](int i) { return c0 ^ ((i & 1) ? T.x[0] : 0u) ^ ((i & 2) ? T.x[1] : 0u) ^ ((i & 4) ? T.x[2] : 0u); };
+    double2 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        v[i] = st[yi(i)];
+    uint32_t u0[3], p0[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const uint32_t pb = pbz[j];
+        u0[j] = (pb & 63u) ^ par(c0 & T.b[j][0]) ^ (par(c0 & T.b[j][1]) << 1) ^ (par(c0 & T.b[j][2]) << 2);
+        // the inverse negates the angle: one more sign on every pair
+        p0[j] = par(c0 & T.z0[j]) ^ (pb >> 6) ^ (T.bits[j] >> 9) ^ (FWD ? 0u : 1u);
+    }
+    const double2 *tb0 = stab + (T.tabs & 1023u), *tb1 = stab + ((T.tabs >> 10) & 1023u),
+                  *tb2 = stab + (T.tabs >> 20);
+    if (FWD) {
+        triple_run<0>(v, tb0, u0[0], p0[0], T.bits[0]);
+        triple_run<1>(v, tb1, u0[1], p0[1], T.bits[1]);
+        triple_run<2>(v, tb2, u0[2], p0[2], T.bits[2]);
+    } else {
+        triple_run<2>(v, tb2, u0[2], p0[2], T.bits[2]);
+        triple_run<1>(v, tb1, u0[1], p0[1], T.bits[1]);
+        triple_run<0>(v, tb0, u0[0], p0[0], T.bits[0]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++)
+        st[yi(i)] = v[i];
+}
+
+// *p += v for an LDS word that only this lane adds to: the LDS add returns
+// nothing, so the lane does not wait for the old value (the order of the
+// additions is the lane's program order)
+__device__ __forceinline__ void wave_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One flip-run pair of the reverse sweep on registers: q of the pair (a, b)
+// (phi) and (la, lb) (lambda) as in adjoint_pairs, then the pair undone.
+template <bool SW>
+__device__ __forceinline__ double adjoint_one_pair(double2 &a, double2 &b, double2 &la, double2 &lb, double2 cs,
+                                                   uint32_t P1, uint32_t px31, uint32_t dq31)
+{
+    const uint32_t P2 = P1 ^ px31;
+    const double f1 = SW ? lb.x * a.y - lb.y * a.x : lb.x * a.x + lb.y * a.y;
+    const double f2 = SW ? la.x * b.y - la.y * b.x : la.x * b.x + la.y * b.y;
+    const double q = flip31(f1, P1 ^ dq31) + flip31(f2, P2 ^ dq31);
+    const double s1 = flip31(cs.y, P1), s2 = flip31(cs.y, P2);
+    rot_pair<SW>(cs.x, s1, s2, a, b);
+    rot_pair<SW>(cs.x, s1, s2, la, lb);
+    return q;
+}
+
+// Two consecutive runs undone in one LDS pass (an AdjPair).  The sub-cube
+// splits into the 2^(B-2) cosets {c0, c0 ^ xA, c0 ^ xB, c0 ^ xA ^ xB} of
+// span(xA, xB); thread t holds coset t (c0: zeros opened at the pair's two
+// pivot bits) of phi and lambda in registers, so both runs' pairs are its own
+// and no barrier separates them.  Run A's pairs are (c0, c0 ^ xA) and
+// (c2, c2 ^ xA) with c2 = c0 ^ xB, run B's (c0, c2) and (c1, c1 ^ xB) with
+// c1 = c0 ^ xA.  Table index and Z-parity are affine in y, so each second
+// pair differs from the first by the tabulated uniform offsets.  Both runs'
+// Walsh sums of the wave are added to (ADD) or stored in sumA and sumB
+// (their 8 entries).
+template <bool ADD>
+__device__ __forceinline__ void adjoint_two(double2 *sp, double2 *sl, const double2 *stab, const AdjPair &pr,
+                                            uint32_t pbzA, uint32_t pbzB, uint32_t tid, int lane, double *sumA,
+                                            double *sumB)
+{
+    const uint32_t plo = (pr.w0 >> 8) & 31u, phi = (pr.w0 >> 16) & 31u;
+    const uint32_t c0 = insert0(insert0(tid, plo), phi);
+    const uint32_t c1 = c0 ^ pr.xA, c2 = c0 ^ pr.xB, c3 = c2 ^ pr.xA;
+    const uint32_t bA = pr.bits & 0xffu, bB = (pr.bits >> 8) & 0xffu;
+    const double2 *tbA = stab + (pr.tabs & 0xffffu), *tbB = stab + (pr.tabs >> 16);
+    const uint32_t uA0 = (pbzA & 63u) ^ par(c0 & pr.bA[0]) ^ (par(c0 & pr.bA[1]) << 1) ^ (par(c0 & pr.bA[2]) << 2);
+    const uint32_t uB0 = (pbzB & 63u) ^ par(c0 & pr.bB[0]) ^ (par(c0 & pr.bB[1]) << 1) ^ (par(c0 & pr.bB[2]) << 2);
+    const uint32_t uA1 = uA0 ^ (bA & 7u), uB1 = uB0 ^ (bB & 7u);
+    const double2 csA0 = tbA[uA0], csA1 = tbA[uA1], csB0 = tbB[uB0], csB1 = tbB[uB1];
+    double2 a0 = sp[c0], a1 = sp[c1], a2 = sp[c2], a3 = sp[c3];
+    double2 l0 = sl[c0], l1 = sl[c1], l2 = sl[c2], l3 = sl[c3];
+    const uint32_t PA0 = (par(c0 & pr.z0A) ^ (pbzA >> 6) ^ (bA >> 5)) << 31;
+    const uint32_t PA1 = PA0 ^ ((bA >> 3) << 31);
+    const uint32_t PB0 = (par(c0 & pr.z0B) ^ (pbzB >> 6) ^ (bB >> 5)) << 31;
+    const uint32_t PB1 = PB0 ^ ((bB >> 3) << 31);
+    // Run A, then run B one pair at a time, each B pair stored as soon as it
+    // is final; the Walsh sums and wave reductions follow with only the four
+    // q values live.  (Scheduling fences between the steps: interleaved, the
+    // steps hold more than the 128 registers of four waves per SIMD.)
+    double qA[2], qB[2];
+    {
+        const uint32_t px = (bA >> 4) << 31, dq = (bA >> 6) << 31;
+        qA[0] = adjoint_one_pair<false>(a0, a1, l0, l1, csA0, PA0, px, dq);
+        __builtin_amdgcn_sched_barrier(0);
+        qA[1] = adjoint_one_pair<false>(a2, a3, l2, l3, csA1, PA1, px, dq);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        const uint32_t px = (bB >> 4) << 31, dq = (bB >> 6) << 31;
+        qB[0] = adjoint_one_pair<false>(a0, a2, l0, l2, csB0, PB0, px, dq);
+        sp[c0] = a0;
+        sp[c2] = a2;
+        sl[c0] = l0;
+        sl[c2] = l2;
+        __builtin_amdgcn_sched_barrier(0);
+        qB[1] = adjoint_one_pair<false>(a1, a3, l1, l3, csB1, PB1, px, dq);
+        sp[c1] = a1;
+        sp[c3] = a3;
+        sl[c1] = l1;
+        sl[c3] = l3;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // (no branch before both sums: a branch lets the compiler sink run B's
+    // q past it and keep all eight amplitudes live through the first sum)
+    double w[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        double acc[kMaxRun];
+#pragma unroll
+        for (int k = 0; k < kMaxRun; k++)
+            acc[k] = -0.0;
+        const uint32_t du[2] = {0u, h ? uB0 ^ uB1 : uA0 ^ uA1};
+        walsh_add<2>(acc, h ? uB0 : uA0, du, h ? qB : qA);
+        w[h] = wave_sum8(acc, lane);
+    }
+    if (sum8_writer(lane)) {
+        if (ADD) {
+            wave_add(&sumA[sum8_index(lane)], w[0]);
+            wave_add(&sumB[sum8_index(lane)], w[1]);
+        } else {
+            sumA[sum8_index(lane)] = w[0];
+            sumB[sum8_index(lane)] = w[1];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- sigma, streamed
 // lambda = H psi with the signs evaluated at the output index.  For a string
 // of real phase omega(y ^ x) = omega(y), for one of imaginary phase
