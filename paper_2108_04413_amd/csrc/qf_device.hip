@@ -1181,6 +1181,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             sp[l] = phi[y];
             sl[l] = lam[y];
         }
+        if constexpr (!UNDO)
+            __syncthreads();  // the sub-cube is loaded (the undo path waits at every run)
         for (int ri = nr - 1; ri >= 0; ri--) {
             if constexpr (kTwo) {
                 const AdjPair pr = apairs[sg.r0 + ri];
@@ -1219,7 +1221,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                             acc[k] += flip(q[i], (__popc((u0 ^ du[i]) & d.e[k]) ^ (d.s[k] < 0 ? 1u : 0u)) & 1u);
                 }
             };
-            __syncthreads();  // the previous run's updates are visible
+            // the previous run's updates are visible (read-only: nothing changes
+            // between the runs of a sub-cube, and no barrier is needed)
+            if constexpr (UNDO)
+                __syncthreads();
             if (d.x) {
                 const uint32_t m = (d.a0 + 1u) & 3u;
                 const uint32_t yt = insert0(tid, d.hbit);
