@@ -1126,11 +1126,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr int NW = NT / 64;
     __shared__ double2 sp[NB], sl[NB];
     __shared__ uint32_t hoff[64];
-    __shared__ double2 stab[kAdjTab];
+    // runs per segment: the read-only sweep stages no tables, which leaves
+    // room for the sums of more runs
+    constexpr int RMAX = UNDO ? kAdjRuns : kPoolRuns;
+    __shared__ double2 stab[UNDO ? kAdjTab : 1];
     // per wave and run, the run's 8 sums over this workgroup's sub-cubes so
     // far (each wave adds to its own: no barrier, no cross-wave step per run)
-    __shared__ double wred[NW][kAdjRuns][kMaxRun];
-    __shared__ uint32_t spbz[kAdjRuns];
+    __shared__ double wred[NW][RMAX][kMaxRun];
+    __shared__ uint32_t spbz[RMAX];
     static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
     // two runs per pass need a coset of 4 amplitudes per thread (apairs is
     // read only then)
@@ -1149,12 +1152,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if constexpr (UNDO)
         for (int t = (int)tid; t < sg.ntab; t += NT)
             stab[t] = tab[sg.tab0 + t];
-    for (int t = (int)tid; t < NW * kAdjRuns * kMaxRun; t += NT)
+    for (int t = (int)tid; t < NW * RMAX * kMaxRun; t += NT)
         (&wred[0][0][0])[t] = 0.0;
     const uint32_t nsub = 1u << (n - B);
     const int nr = sg.r1 - sg.r0;
     // thread r < nr keeps run r's full-space masks (z0f, bf) in registers for
-    // the per-sub-cube parities (nr <= kAdjRuns < NT)
+    // the per-sub-cube parities (nr <= RMAX < NT)
     uint32_t pm[kMaxRank + 1] = {};
     if (tid < (uint32_t)nr) {
         const LocalRun &d = lruns[sg.r0 + (int)tid];
@@ -2088,7 +2091,9 @@ void set_block_bits(qf_plan &P, int B)
     if (!lr.empty())
         P.upload(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun));
     if (P.adj_bits) {
-        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr, kAdjRuns, kAdjTab);
+        // (a pool plan only runs the read-only sweep: longer segments, no tables)
+        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr, P.is_pool ? kPoolRuns : kAdjRuns,
+                       P.is_pool ? kSegTab : kAdjTab);
         for (const Segment &sg : P.asegs) {
             const int k0 = sg.Q ? lr[(size_t)sg.r0].k0 : 0;
             P.aseg_k0.push_back(k0);
@@ -2449,6 +2454,8 @@ void launch_adjoint_run(qf_plan &P, double2 *phi, double2 *lam, const RunDesc &d
 
 void launch_adjoint(qf_plan &P, double2 *phi, double2 *lam, hipStream_t s)
 {
+    if (P.is_pool)  // its segments exceed the undoing sweep's kAdjRuns
+        raise(QF_E_ARG, "reverse sweep: a pool plan only takes the read-only sweep");
     if (P.adj_bits) {
         for (size_t i = P.asegs.size(); i-- > 0;) {
             const Segment &sg = P.asegs[i];
@@ -2577,8 +2584,8 @@ void pool_init(qf_plan &Q, int n, const qf_term *pool, const int64_t *pool_off, 
     Q.pool_c.resize(sorted.size());
     for (size_t k = 0; k < sorted.size(); k++)
         Q.pool_c[k] = sorted[k].c;
+    Q.is_pool = true;  // before the segments are built (longer read-only segments)
     plan_init(Q, n, sorted.data(), (int64_t)sorted.size(), nullptr, nullptr, 0);
-    Q.is_pool = true;
     std::vector<double> zero(sorted.size(), 0.0);
     upload_theta(Q, zero.data(), nullptr);
     QF_HIP(hipStreamSynchronize(nullptr));

@@ -64,6 +64,7 @@ constexpr int kItemStride = 512;
 constexpr int kSegRuns = kSegStr;  // runs of one segment (each has >= 1 string)
 constexpr int kAdjRuns = 20;       // runs of one blocked reverse-sweep segment (per-wave sums in LDS)
 constexpr int kAdjTab = 256;       // (cos, sin) entries of one blocked reverse-sweep segment
+constexpr int kPoolRuns = 30;      // runs of one read-only (pool) sweep segment: no tables staged
 
 struct LocalRun {
     uint32_t x, hbit, z0, a0;       // local flip mask, its highest bit, local z0, i^a0
