@@ -472,6 +472,65 @@ def test_blocked_adjoint_matches_oracle(qf, B):
     assert np.max(np.abs(g - g_o)) < G_TOL
 
 
+def multi_run_terms(n, seed, runs=120):
+    """Runs that form the multi-run LDS passes (flip runs with an odd number
+    of Y, rank <= 3, masks inside qubits 0..11) interleaved with runs that
+    must take the one-run path: diagonal runs, even-Y runs, runs of rank > 3
+    and runs repeating the previous mask."""
+    rng = np.random.default_rng([seed, 131])
+    xs, zs = [], []
+    prev = 0
+    for r in range(runs):
+        kind = rng.random()
+        if kind < 0.08:
+            x = 0
+        elif kind < 0.12 and prev:
+            x = prev
+        else:
+            bits = rng.choice(12, size=int(rng.integers(2, 5)), replace=False)
+            x = int(sum(1 << int(b) for b in bits))
+        odd = kind >= 0.2 or x == 0
+        wide = 0.16 <= kind < 0.2
+        m = int(rng.integers(6, 9)) if wide else int(rng.integers(1, 5))
+        for _ in range(m):
+            z = int(rng.integers(0, 1 << n))
+            if x and ((bin(x & z).count("1") & 1) != (1 if odd else 0)):
+                z ^= 1 << int(np.flatnonzero([(x >> q) & 1 for q in range(n)])[0])
+            xs.append(x)
+            zs.append(z)
+        prev = x
+    return np.array(xs, dtype=np.uint64), np.array(zs, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_multi_run_passes_match_oracle(qf, seed):
+    """Three-run apply passes (2^12 sub-cubes, forward and inverse) and
+    two-run reverse-sweep passes (2^11 sub-cubes) against the oracle, on runs
+    built to form them, mixed with runs that break them."""
+    n = 14
+    xs, zs = multi_run_terms(n, seed)
+    th = qi.random_angles(len(xs), 140 + seed, 1.0)
+    psi0 = qi.random_state(n, 150 + seed)
+    hx, hz, hc = qi.random_paulis(n, 200, 160 + seed)
+    hx, hz, hc, off = grouped(hx, hz, hc)
+    A = qf.terms_array(xs, zs, np.ones(len(xs)))
+    plan = qf.Plan(n, A, qf.terms_array(hx, hz, hc), off)
+    plan.set_block_bits(12)
+    for inverse in (False, True):
+        psi = dev(psi0)
+        qf.apply_pauli_exp(psi, n, A, th, inverse=inverse)
+        want = sv.apply_product(psi0, n, xs, zs, th, inverse=inverse)
+        assert np.max(np.abs(host(psi) - want)) < A_TOL
+    occ = (1 << 7) - 1
+    ws = torch.empty(2 << n, dtype=torch.complex128, device="cuda")
+    e_o, g_o = core.energy_grad(n, occ, xs, zs, th, hx, hz, hc)
+    for B in (12, 11):
+        plan.set_block_bits(B)
+        e, g = plan.energy_grad(occ, th, ws)
+        assert e == pytest.approx(e_o, abs=E_TOL)
+        assert np.max(np.abs(g - g_o)) < G_TOL
+
+
 @pytest.mark.parametrize("B", [10, 11])
 def test_blocked_adjoint_20q_matches_golden(qf, B):
     """20 qubits: more sub-cubes than resident workgroups at B = 10, so
