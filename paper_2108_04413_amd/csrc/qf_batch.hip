@@ -173,9 +173,10 @@ static_assert(kBT == 512 && kSub >= (1 << kSsL) + kBT + kBT / 4,
               "the sigma tile and its lo-term and group windows fit the sub-cube image");
 // pairs per thread in the common sub-cubes (2^12 forward, 2^11 reverse), which get unrolled variants
 constexpr int kApplyPairs = kSub / 2 / kBT, kAdjPairs = kSub / 4 / kBT;
-// runs of one segment (their fixed-bit parities in LDS; with the two-run
-// reduction array this keeps the LDS image within two workgroups per CU)
-constexpr int kBatchSegRuns = 256;
+// runs of one forward segment (their fixed-bit parities in LDS; with the
+// per-wave reverse-sweep sums this keeps the LDS image within two workgroups
+// per CU); reverse segments hold at most kAdjRuns
+constexpr int kBatchSegRuns = 128;
 
 // member's slice [b, e) of `units`, in whole tiles of kBT * kItems
 __device__ __forceinline__ void member_slice(uint64_t units, int W, int rank, uint64_t &b, uint64_t &e)
@@ -418,14 +419,16 @@ __device__ __forceinline__ void sub_adjoint_pairs(double2 *sp, double2 *sl, cons
 }
 
 // Undo a segment's runs (last first) on one 2^B sub-cube of phi (sp) and
-// lambda (sl), adding each run's 2 Im <lambda|P_k|phi> / 2 per string to
-// lacc[k - sk0] before the run is undone.
+// lambda (sl); before a run is undone each wave adds the run's 8 sums of
+// 2 Im <lambda|P_k|phi> / 2 over the sub-cube (Walsh sums, or per string for
+// rank > 3) to its own slots wred[wave][run] (no barrier, no cross-wave step
+// per run; the member sums the waves once per segment).
 // FIXNB: the sub-cube size when it is the common 2^11, 0 for 2^B
 template <uint32_t FIXNB>
 __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam, int B, uint32_t base,
                             const Segment &sg, const LocalRun *__restrict__ lr, const AdjPair *__restrict__ apairs,
-                            const double2 *tab, const uint32_t *hoff, double2 *sp, double2 *sl, double *lacc,
-                            double (*red)[2 * kMaxRun], int sk0, uint32_t *pbzs)
+                            const double2 *tab, const uint32_t *hoff, double2 *sp, double2 *sl,
+                            double (*wred)[kAdjRuns][kMaxRun], uint32_t *pbzs)
 {
     const uint32_t NB = FIXNB ? FIXNB : 1u << B, lomask = (1u << sg.q0) - 1u;
     const int lane = (int)(threadIdx.x & 63u), wave = (int)(threadIdx.x >> 6);
@@ -438,31 +441,13 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
     }
     for (int ri = sg.r1 - 1; ri >= sg.r0; ri--) {
         if constexpr (FIXNB == 4u * kBT) {
-            // two runs per pass (AdjPair), the sums reduced per pass as below
+            // two runs per pass (AdjPair)
             const AdjPair pr = apairs[ri];
             if (pr.w0 & 1u) {
                 const uint32_t pbzA = pbzs[ri - sg.r0], pbzB = pbzs[ri - 1 - sg.r0];
                 __syncthreads();  // the previous run's updates are visible
-                adjoint_two<false>(sp, sl, tab, pr, pbzA, pbzB, threadIdx.x, lane, red[wave], red[wave] + kMaxRun);
-                __syncthreads();
-                if (threadIdx.x < 2u * kMaxRun) {
-                    // lanes 0..7: run A's strings, 8..15: run B's
-                    const LocalRun &dA = lr[ri], &dB = lr[ri - 1];
-                    const bool hiB = threadIdx.x >= (uint32_t)kMaxRun;
-                    const int k = (int)(threadIdx.x & (kMaxRun - 1));
-                    const LocalRun &d = hiB ? dB : dA;
-                    if (k < d.m) {
-                        const bool walsh = d.r <= 3;
-                        const int col = (hiB ? kMaxRun : 0) + (walsh ? (int)d.e[k] : k);
-                        double v = 0.0;
-#pragma unroll
-                        for (int w = 0; w < kBW; w++)
-                            v += red[w][col];
-                        if (walsh && d.s[k] < 0)
-                            v = -v;
-                        lacc[d.k0 - sk0 + k] += v;
-                    }
-                }
+                adjoint_two<true>(sp, sl, tab, pr, pbzA, pbzB, threadIdx.x, lane, wred[wave][ri - sg.r0],
+                                  wred[wave][ri - 1 - sg.r0]);
                 ri--;
                 continue;
             }
@@ -530,23 +515,7 @@ __device__ void sub_adjoint(double2 *__restrict__ phi, double2 *__restrict__ lam
         {
             const double h = wave_sum8(acc, lane);
             if (sum8_writer(lane))
-                red[wave][sum8_index(lane)] = h;
-        }
-        __syncthreads();
-        if (threadIdx.x < (uint32_t)d.m) {
-            // (byte k of e and s is string k's; the sign bit of s_k moves to bit 0)
-            uint64_t epk, spk;
-            __builtin_memcpy(&epk, d.e, sizeof epk);
-            __builtin_memcpy(&spk, d.s, sizeof spk);
-            spk = (spk >> 7) & 0x0101010101010101ull;
-            const int col = walsh ? (int)((epk >> (8 * threadIdx.x)) & 0xffu) : (int)threadIdx.x;
-            double v = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBW; w++)
-                v += red[w][col];
-            if (walsh && ((spk >> (8 * threadIdx.x)) & 1u))
-                v = -v;
-            lacc[d.k0 - sk0 + (int)threadIdx.x] += v;
+                wave_add(&wred[wave][ri - sg.r0][sum8_index(lane)], h);
         }
     }
     __syncthreads();
@@ -735,6 +704,7 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                const Segment *__restrict__ segs, const LocalRun *__restrict__ lruns,
                                                const ApplyTriple *__restrict__ atrip,
                                                const AdjPair *__restrict__ apairs,
+                                               const uint32_t *__restrict__ smap,
                                                const GroupDesc *__restrict__ groups,
                                                const SsCls *__restrict__ sscls, const uint32_t *__restrict__ sswords,
                                                const SsLo *__restrict__ sslos, double2 *__restrict__ tabs,
@@ -746,10 +716,9 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
 {
     __shared__ int s_entry, s_rank;
     __shared__ double2 s_sub[kSub];
-    __shared__ double2 s_tab[kSegTab];
+    __shared__ double2 s_tab[kAdjTab];
     __shared__ uint32_t s_hoff[64];
-    __shared__ double s_lacc[kSegStr];
-    __shared__ double s_red[kBW][2 * kMaxRun];
+    __shared__ double s_wred[kBW][kAdjRuns][kMaxRun];  // per-wave run sums of a reverse segment
     __shared__ double s_part[kMaxRun];
     __shared__ uint32_t s_pbz[kBatchSegRuns];
     for (;;) {
@@ -875,22 +844,29 @@ __global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4))) void k
                 for (int t = (int)threadIdx.x; t < sg.ntab; t += kBT)
                     s_tab[t] = tabs[en.tabs0 + sg.tab0 + t];
                 seg_hoff(sg, s_hoff);
-                for (int t = (int)threadIdx.x; t < nstr; t += kBT)
-                    s_lacc[t] = 0.0;
+                for (int t = (int)threadIdx.x; t < kBW * kAdjRuns * kMaxRun; t += kBT)
+                    (&s_wred[0][0][0])[t] = 0.0;
                 const uint32_t nsub = 1u << (n - en.Badj);
                 for (uint32_t sc = (uint32_t)rank; sc < nsub; sc += (uint32_t)W) {
                     const uint32_t base = subcube_base(sc, sg);
                     if (en.Badj == 11)
                         sub_adjoint<(uint32_t)kSub / 2>(phi, lam, en.Badj, base, sg, lr, apairs + en.dlr0, s_tab,
-                                                        s_hoff, s_sub, s_sub + (kSub / 2), s_lacc, s_red, sk0,
-                                                        s_pbz);
+                                                        s_hoff, s_sub, s_sub + (kSub / 2), s_wred, s_pbz);
                     else
                         sub_adjoint<0>(phi, lam, en.Badj, base, sg, lr, apairs + en.dlr0, s_tab, s_hoff, s_sub,
-                                       s_sub + (kSub / 2), s_lacc, s_red, sk0, s_pbz);
+                                       s_sub + (kSub / 2), s_wred, s_pbz);
                 }
+                // the waves' sums in wave order; smap: each string's run,
+                // Walsh column (or string index) and sign
                 __syncthreads();
-                for (int t = (int)threadIdx.x; t < nstr; t += kBT)
-                    gpart[(size_t)rank * en.K + sk0 + t] = s_lacc[t];
+                for (int t = (int)threadIdx.x; t < nstr; t += kBT) {
+                    const uint32_t m = smap[en.theta0 + sk0 + t];
+                    double v = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kBW; w++)
+                        v += s_wred[w][m >> 4][m & 7u];
+                    gpart[(size_t)rank * en.K + sk0 + t] = (m & 8u) ? -v : v;
+                }
             }
             team_sync(W, ts, ++epoch, spin_limit, ierr);
         }
@@ -956,6 +932,7 @@ struct qf_batch {
     qf::SsLo *d_sslos = nullptr;
     qf::ApplyTriple *d_atrip = nullptr;
     qf::AdjPair *d_apairs = nullptr;
+    uint32_t *d_smap = nullptr;
     double2 *d_tabs = nullptr;  // (cos, sin) tables of every instance's runs, filled in the launch
     uint32_t *d_z = nullptr;
     double *d_c = nullptr;
@@ -1032,6 +1009,7 @@ struct BatchHost {
     std::vector<LocalRun> lruns;
     std::vector<ApplyTriple> atrip;  // parallel to lruns: forward three-run passes
     std::vector<AdjPair> apairs;     // parallel to lruns: reverse two-run passes
+    std::vector<uint32_t> smap;      // per ansatz string (caller offsets): run, column, sign
     std::vector<GroupDesc> groups;
     std::vector<SsCls> sscls;
     std::vector<uint32_t> sswords;
@@ -1110,6 +1088,7 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
     std::vector<int> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.nq[a] > B.nq[b]; });
+    T.smap.assign((size_t)std::max<int64_t>(B.K_total, 1), 0u);
     for (int i : order) {
         const int n = n_qubits[i];
         int tab = 0;
@@ -1133,8 +1112,8 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::vector<Segment> sa, sd;
         std::vector<LocalRun> la, ld;
         if (!r.empty()) {
-            build_segments(r, n, Bapp, std::min(6, Bapp), sa, la, kBatchSegRuns);
-            build_segments(r, n, Badj, std::min(6, Badj), sd, ld, kBatchSegRuns);
+            build_segments(r, n, Bapp, std::min(6, Bapp), sa, la, kBatchSegRuns, kAdjTab);
+            build_segments(r, n, Badj, std::min(6, Badj), sd, ld, kAdjRuns, kAdjTab);
         }
         // multi-run passes on the full-size sub-cubes: three runs forward
         // (flags in the flip runs' itm[1]), two runs in the reverse sweep
@@ -1150,6 +1129,19 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
         std::memset(ap.data(), 0, ap.size() * sizeof(AdjPair));
         if (Badj == 11 && !ld.empty())
             ap = adjoint_pairs(sd, ld);
+        // string k of reverse-segment run r: Walsh column e_k (rank <= 3) or
+        // k, the sign of s_k, r within its segment (at the caller's offset)
+        for (const Segment &sg : sd) {
+            if (!sg.Q)
+                continue;
+            for (int rr = sg.r0; rr < sg.r1; rr++) {
+                const LocalRun &L = ld[(size_t)rr];
+                const bool walsh = L.r <= 3;
+                for (int k = 0; k < L.m; k++)
+                    T.smap[(size_t)(B.koff[(size_t)i] + L.k0 + k)] =
+                        (uint32_t)(walsh ? L.e[k] : k) | (walsh && L.s[k] < 0 ? 8u : 0u) | (uint32_t)(rr - sg.r0) << 4;
+            }
+        }
         BatchEntry e;
         std::memset(&e, 0, sizeof e);
         e.n = n;
@@ -1219,13 +1211,13 @@ void batch_assemble(qf_batch &B, BatchHost &T, int count, const int *n_qubits, c
 
 // Device layout: one contiguous region, every array 256-byte aligned.
 struct Layout {
-    size_t off[21];
+    size_t off[22];
     size_t total;
 };
 
 Layout batch_layout(const qf_batch &B, const BatchHost &T)
 {
-    const size_t sizes[21] = {
+    const size_t sizes[22] = {
         T.ent.size() * sizeof(BatchEntry), std::max<size_t>(T.runs.size(), 1) * sizeof(RunDesc),
         T.groups.size() * sizeof(GroupDesc), T.zs.size() * sizeof(uint32_t), T.cs.size() * sizeof(double),
         (size_t)std::max<int64_t>(B.K_total, 1) * sizeof(double), B.state_bytes,
@@ -1235,10 +1227,11 @@ Layout batch_layout(const qf_batch &B, const BatchHost &T)
         std::max<size_t>(T.segs.size(), 1) * sizeof(Segment), std::max<size_t>(T.lruns.size(), 1) * sizeof(LocalRun),
         std::max<size_t>(T.sscls.size(), 1) * sizeof(SsCls), (size_t)std::max<int64_t>(T.tabs, 1) * sizeof(double2),
         std::max<size_t>(T.sswords.size(), 1) * sizeof(uint32_t), std::max<size_t>(T.sslos.size(), 1) * sizeof(SsLo),
-        std::max<size_t>(T.lruns.size(), 1) * sizeof(ApplyTriple), std::max<size_t>(T.lruns.size(), 1) * sizeof(AdjPair)};
+        std::max<size_t>(T.lruns.size(), 1) * sizeof(ApplyTriple), std::max<size_t>(T.lruns.size(), 1) * sizeof(AdjPair),
+        T.smap.size() * sizeof(uint32_t)};
     Layout L;
     size_t at = 0;
-    for (int i = 0; i < 21; i++) {
+    for (int i = 0; i < 22; i++) {
         L.off[i] = at;
         at += (sizes[i] + 255) & ~(size_t)255;
     }
@@ -1269,6 +1262,7 @@ void batch_bind(qf_batch &B, char *base, const Layout &L)
     B.d_sslos = (SsLo *)(base + L.off[18]);
     B.d_atrip = (ApplyTriple *)(base + L.off[19]);
     B.d_apairs = (AdjPair *)(base + L.off[20]);
+    B.d_smap = (uint32_t *)(base + L.off[21]);
 }
 
 __global__ void k_fill_zero(double *p, int64_t n)
@@ -1292,6 +1286,7 @@ void batch_upload(qf_batch &B, const BatchHost &T, hipStream_t s)
         QF_HIP(hipMemcpyAsync(B.d_apairs, T.apairs.data(), T.apairs.size() * sizeof(AdjPair), hipMemcpyHostToDevice,
                               s));
     }
+    QF_HIP(hipMemcpyAsync(B.d_smap, T.smap.data(), T.smap.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     QF_HIP(hipMemcpyAsync(B.d_groups, T.groups.data(), T.groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice,
                           s));
     if (!T.sscls.empty()) {
@@ -1314,7 +1309,7 @@ void batch_kernels(qf_batch &B, hipStream_t s)
     hipLaunchKernelGGL(k_batch_reset, dim3(std::max(1, std::min(64, (B.nentries * kSyncWords + 255) / 256))), dim3(256), 0, s,
                        B.d_sync, B.nentries, B.d_ticket, B.d_err);
     hipLaunchKernelGGL(k_batch, dim3(B.grid), dim3(kBT), 0, s, B.d_entries, B.nentries, B.total_tickets,
-                       B.d_runs, B.d_segs, B.d_lruns, B.d_atrip, B.d_apairs, B.d_groups, B.d_sscls, B.d_sswords, B.d_sslos, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
+                       B.d_runs, B.d_segs, B.d_lruns, B.d_atrip, B.d_apairs, B.d_smap, B.d_groups, B.d_sscls, B.d_sswords, B.d_sslos, B.d_tabs, B.d_z, B.d_c, B.d_theta, B.d_states, B.d_partials, B.d_sync,
                        B.d_ticket, B.d_err, B.d_E, B.d_grad, B.spin_limit, B.mb_E, B.mb_grad, B.mb_flag);
     QF_HIP(hipGetLastError());
 }
