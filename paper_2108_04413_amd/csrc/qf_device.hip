@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr int PER = (int)(NB / NT);
     static_assert(PER == 1 || NT == kItemStride, "a thread's items are kItemStride apart");
     __shared__ double2 st[NB];
-    __shared__ uint32_t hoff[64];
+    __shared__ uint32_t hoff[kMaxHoff];
     __shared__ double2 stab[kSegTab];
     __shared__ uint32_t spbz[kSegRuns];
     // base: the block index scattered into the qubits outside Q
@@ -1125,7 +1125,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr int PER = (int)(NB / NT);
     constexpr int NW = NT / 64;
     __shared__ double2 sp[NB], sl[NB];
-    __shared__ uint32_t hoff[64];
+    __shared__ uint32_t hoff[kMaxHoff];
     // runs per segment: the read-only sweep stages no tables, which leaves
     // room for the sums of more runs
     constexpr int RMAX = UNDO ? kAdjRuns : kPoolRuns;
@@ -1598,6 +1598,8 @@ void build_segments(const std::vector<RunDesc> &runs, int n, int B, int q0, std:
         int qlow = 0;
         while (qlow < 32 && ((Q >> qlow) & 1u))
             qlow++;
+        if (B - qlow > 8)
+            raise(QF_E_ARG, "segment: more than 8 sub-cube qubits above the contiguous rows");
         sg.Q = Q;
         sg.q0 = qlow;
         sg.nhi = 0;
@@ -2075,7 +2077,7 @@ void set_block_bits(qf_plan &P, int B)
     if (!B || P.runs.empty())
         return;
     std::vector<LocalRun> lr;
-    build_segments(P.runs, P.n, B, std::min(6, B), P.segs, lr);
+    build_segments(P.runs, P.n, B, std::min(kApplyQ0, B), P.segs, lr);
     if (B == 12) {
         // triple flags in the flip runs' free itm[1] (the kernel tests them on
         // the descriptor it loads anyway)
@@ -2092,7 +2094,7 @@ void set_block_bits(qf_plan &P, int B)
         P.upload(P.d_lruns, lr.data(), lr.size() * sizeof(LocalRun));
     if (P.adj_bits) {
         // (a pool plan only runs the read-only sweep: longer segments, no tables)
-        build_segments(P.runs, P.n, P.adj_bits, 6, P.asegs, lr, P.is_pool ? kPoolRuns : kAdjRuns,
+        build_segments(P.runs, P.n, P.adj_bits, kAdjQ0, P.asegs, lr, P.is_pool ? kPoolRuns : kAdjRuns,
                        P.is_pool ? kSegTab : kAdjTab);
         for (const Segment &sg : P.asegs) {
             const int k0 = sg.Q ? lr[(size_t)sg.r0].k0 : 0;

@@ -64,7 +64,17 @@ constexpr int kItemStride = 512;
 constexpr int kSegRuns = kSegStr;  // runs of one segment (each has >= 1 string)
 constexpr int kAdjRuns = 20;       // runs of one blocked reverse-sweep segment (per-wave sums in LDS)
 constexpr int kAdjTab = 256;       // (cos, sin) entries of one blocked reverse-sweep segment
-constexpr int kPoolRuns = 30;      // runs of one read-only (pool) sweep segment: no tables staged
+constexpr int kPoolRuns = 28;      // runs of one read-only (pool) sweep segment: no tables staged
+// Qubits 0 .. q0-1 are in every plan segment's set Q: rows of 2^q0
+// amplitudes are contiguous in HBM.  Fewer fixed qubits leave more of Q for
+// the runs' flip masks, so a segment holds more runs and the state makes
+// fewer passes (24q UCCSD sweep, 2^11 sub-cubes: 217 segments at q0 = 6, 166
+// at 3; 28q apply, 2^12: 122 at 6, 96 at 4); a row stays one or more whole
+// 128-byte cache lines.  At most 8 qubits of Q lie above q0, so the row
+// offsets of a sub-cube take 2^8 entries.
+constexpr int kApplyQ0 = 4;
+constexpr int kAdjQ0 = 3;
+constexpr int kMaxHoff = 256;
 
 struct LocalRun {
     uint32_t x, hbit, z0, a0;       // local flip mask, its highest bit, local z0, i^a0
