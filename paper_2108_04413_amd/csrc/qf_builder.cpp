@@ -509,4 +509,4 @@ extern "C" int qf_grad_t(const qf_term *A, const int64_t *exc_off, int64_t n_par
 
 extern "C" const char *qf_last_error(void) { return qf::last_error().c_str(); }
 
-extern "C" const char *qf_version(void) { return "qforte-mi355x 0.9 (gfx950)"; }
+extern "C" const char *qf_version(void) { return "qforte-mi355x 0.10 (gfx950)"; }

@@ -836,6 +836,15 @@ __device__ __forceinline__ double sigma_stream(const double2 *__restrict__ psi, 
                 // entries that are not used)
                 lch = wlo[min(jw + lane, NT - 1)];
                 jw += nlo;
+                // a group whose lo-terms all cancel on this tile adds nothing
+                // (number-conserving Hamiltonians: ~20 % of group-tile pairs)
+                {
+                    const double Cl = __hiloint2double((int)lch.w, (int)lch.z);
+                    const uint64_t nz = __builtin_amdgcn_ballot_w64(Cl != 0.0);
+                    const uint64_t lm = nlo >= 64 ? ~0ull : ((1ull << nlo) - 1ull);
+                    if (!(nz & lm))
+                        continue;
+                }
                 const uint32_t base = tid16 ^ ((gw & (T - 1u)) << 4);
                 auto row = [&](int i) __attribute__((always_inline)) {
                     return *reinterpret_cast<const double2 *>(reinterpret_cast<const char *>(tile) +
