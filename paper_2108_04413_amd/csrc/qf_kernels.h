@@ -43,7 +43,7 @@ constexpr int kSegStr = 512;  // strings of one segment (blocked adjoint accumul
 
 struct Segment {
     uint32_t Q;      // qubits of the sub-cube
-    int32_t q0;      // Q contains qubits 0 .. q0-1 (q0 >= min(6, B))
+    int32_t q0;      // Q contains qubits 0 .. q0-1 (plans: kApplyQ0 / kAdjQ0; batched: 6; at most B)
     int32_t r0, r1;  // runs [r0, r1) of the segment (LocalRun array)
     uint32_t hi[8];  // positions of Q's qubits above q0, ascending
     int32_t nhi;
@@ -68,7 +68,7 @@ constexpr int kPoolRuns = 28;      // runs of one read-only (pool) sweep segment
 // Qubits 0 .. q0-1 are in every plan segment's set Q: rows of 2^q0
 // amplitudes are contiguous in HBM.  Fewer fixed qubits leave more of Q for
 // the runs' flip masks, so a segment holds more runs and the state makes
-// fewer passes (24q UCCSD sweep, 2^11 sub-cubes: 217 segments at q0 = 6, 166
+// fewer passes (24q UCCSD sweep, 2^11 sub-cubes: 217 segments at q0 = 6, 171
 // at 3; 28q apply, 2^12: 122 at 6, 96 at 4); a row stays one or more whole
 // 128-byte cache lines.  At most 8 qubits of Q lie above q0, so the row
 // offsets of a sub-cube take 2^8 entries.
