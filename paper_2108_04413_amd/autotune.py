@@ -19,7 +19,15 @@ clamps to) and keeps the fastest.  The table is written as JSON
 {"arch": ..., "team": {n: W}, "ms": {n: {W: ms}}} and picked up by
 api.Batch when it matches the running device.
 
+The per-size search sees one size at a time, while a mixed batch shares the
+grid between sizes: a team that is fastest for 43 instances of one size can
+slow the mixed launch.  `--what mixed` therefore refines the table on the
+mixed batched configuration (`qf_inputs.batched_instances`): for each size
+in turn it tries half and twice the team and keeps a change only when the
+whole launch gets faster (coordinate descent from the per-size table).
+
     python -m paper_2108_04413_amd.autotune --out tuned_gfx950.json
+    python -m paper_2108_04413_amd.autotune --what mixed --merge
 """
 from __future__ import annotations
 
@@ -102,6 +110,58 @@ def tune(ns=(12, 14, 16, 18, 20, 22, 24), count: int = 43, reps: int = 2, max_te
     return result
 
 
+def tune_mixed(team: dict, count: int = 256, reps: int = 2, max_team: int = 256, log=print) -> dict:
+    """Refine per-size teams on the mixed batch: for each size, try W / 2
+    and 2 W and keep a change that makes the whole launch faster."""
+    import paper_2108_04413_amd as qf
+    sys.path.insert(0, os.path.dirname(HERE))
+    import qf_inputs as qi
+
+    insts = []
+    for r in qi.batched_instances(count):
+        h, g = qi.integrals(r["n_orb"], r["n_elec"], r["seed"])
+        H, off, _ = qf.build_paulis("hamiltonian", r["n_orb"], r["n_elec"], h, g)
+        A, aoff, _ = qf.build_paulis("uccsd", r["n_orb"], r["n_elec"])
+        t = qi.amplitudes(len(aoff) - 1, r["seed"], r["t_scale"])
+        insts.append(dict(n=2 * r["n_orb"], occ=(1 << r["n_elec"]) - 1, H=H, off=off, A=A,
+                          theta=qf.ansatz_angles(A, aoff, t)))
+    thetas = [d["theta"] for d in insts]
+    sizes = sorted({d["n"] for d in insts})
+
+    def launch_ms(tab):
+        B = qf.Batch(insts, team=[tab.get(d["n"], 0) for d in insts])
+        B.run(thetas, use_graph=True)  # capture + warm
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            B.run(thetas, use_graph=True)
+            best = min(best, time.perf_counter() - t0)
+        B.close()
+        return best * 1e3
+
+    cur = {n: int(team.get(n, 0)) for n in sizes}
+    t_cur = launch_ms(cur)
+    log(f"autotune mixed: start {cur}: {t_cur:.1f} ms for {count} instances")
+    trials = {}
+    for n in sorted(sizes, reverse=True):
+        if cur[n] <= 0:
+            continue
+        for w in (cur[n] // 2, cur[n] * 2):
+            # the library's clamp: one 2^11 sub-cube per member
+            if w < 1 or w > max_team or w > max(1, (1 << (n - 1)) // 1024):
+                continue
+            tab = dict(cur)
+            tab[n] = w
+            t = launch_ms(tab)
+            trials[f"{n}:{w}"] = t
+            log(f"autotune mixed: n={n} W={w}: {t:.1f} ms")
+            # keep a change only if it clears the launch-to-launch spread
+            if t < 0.98 * t_cur:
+                cur, t_cur = tab, t
+                log(f"autotune mixed: keep n={n} W={w}")
+    return {"team": {str(n): w for n, w in cur.items()}, "mixed_ms": {"final": t_cur, "trials": trials}}
+
+
 def load_plan_table(arch: str | None = None) -> dict:
     """Tuned plan tiles {n: {"block_bits": B, "energy_tile": L}} for this
     architecture ({} if none)."""
@@ -176,7 +236,7 @@ def main():
     ap.add_argument("--count", type=int, default=43)
     ap.add_argument("--ns", default="12,14,16,18,20,22,24")
     ap.add_argument("--merge", action="store_true", help="update the existing table instead of replacing it")
-    ap.add_argument("--what", default="all", choices=["all", "team", "plan"])
+    ap.add_argument("--what", default="all", choices=["all", "team", "plan", "mixed"])
     args = ap.parse_args()
     ns = tuple(int(v) for v in args.ns.split(","))
     say = lambda m: print(m, flush=True)  # noqa: E731
@@ -185,10 +245,16 @@ def main():
         res.update(tune(ns, count=args.count, log=say))
     if args.what in ("all", "plan"):
         res.update(tune_plan(ns, log=say))
+    if args.what in ("all", "mixed"):
+        start = res["team"] if res["team"] else {}
+        if not start and os.path.exists(args.out):
+            with open(args.out) as f:
+                start = json.load(f).get("team", {})
+        res.update(tune_mixed({int(k): int(v) for k, v in start.items()}, log=say))
     if args.merge and os.path.exists(args.out):
         with open(args.out) as f:
             old = json.load(f)
-        for key in ("team", "ms", "plan", "plan_ms"):
+        for key in ("team", "ms", "plan", "plan_ms", "mixed_ms"):
             if key in res:
                 old.setdefault(key, {}).update(res[key])
         res = old
